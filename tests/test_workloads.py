@@ -1,0 +1,53 @@
+"""Host-side checks of the seeded workload generators (no GPU)."""
+import numpy as np
+
+from oracle import decomposition as dec
+from paper_1912_03243_amd import workloads as W
+
+
+def test_brick_gate_counts():
+    for n, layers, total in [(30, 20, 890), (34, 16, 808), (36, 16, 856), (28, 16, 664)]:
+        g = W.layered_brick(n, layers, seed=3)
+        assert len(g) == total
+        assert np.sum(g["op"] == W.OP_CZ) == total - n * layers
+
+
+def test_generators_are_deterministic():
+    a = W.layered_brick(12, 4, seed=2)
+    b = W.layered_brick(12, 4, seed=2)
+    assert a.tobytes() == b.tobytes()
+    assert W.bitstrings(30, 16, 1002).tolist() == W.bitstrings(30, 16, 1002).tolist()
+
+
+def test_haar_matrices_are_unitary():
+    g = W.layered_brick(8, 2, seed=9)
+    for rec in g[g["op"] == W.OP_U]:
+        m = rec["u"].reshape(2, 2, 2)
+        m = m[..., 0] + 1j * m[..., 1]
+        assert np.allclose(m.conj().T @ m, np.eye(2), atol=1e-14)
+
+
+def test_grid_cut_has_ten_crossing_czs():
+    g, side = W.grid_circuit()
+    assert len(dec.crossing_czs(g, side)) == 10
+    assert side.tolist() == [0] * 24 + [1] * 24
+    full, _ = W.grid_circuit(max_cross=None)
+    assert len(dec.crossing_czs(full, side)) == 12
+    assert len(full) - len(g) == 2
+
+
+def test_batch_instance_ranges():
+    inst = W.batch_instances(64)
+    ns = [n for n, _ in inst]
+    assert min(ns) >= 12 and max(ns) <= 24
+    for n, g in inst:
+        assert np.all(g["q0"] < n) and np.all(g["q1"] < n)
+        depth = np.sum(g["op"] == W.OP_U) // n
+        assert 10 <= depth <= 40
+
+
+def test_mixed_circuit_pairs_are_distinct():
+    g = W.random_mixed(20, 200, seed=1)
+    two = g[g["op"] >= W.OP_CNOT]
+    assert np.all(two["q0"] != two["q1"])
+    assert 0.25 < len(two) / len(g) < 0.55
