@@ -1,0 +1,315 @@
+/*
+ * juqcs_gpu -- state-vector gate engine for one AMD MI355X (gfx950).
+ *
+ * The hot path of a universal quantum computer simulator in the sense of
+ * Willsch et al., "Benchmarking Supercomputers with the Juelich Universal
+ * Quantum Computer Simulator" (arXiv:1912.03243):  sparse 1- and 2-qubit
+ * gates applied to the full vector of 2^n complex amplitudes, each gate one
+ * memory-bound pass (Section 2, Eq. (1)); a two-byte amplitude coding
+ * (Section 1); and the entangling-gate decomposition into a sum over
+ * branches (Section 4, Eqs. (2) and (3)).
+ *
+ * Conventions used by every call
+ *   - qubit q is bit q of the amplitude index (little endian); qubit
+ *     arguments are logical qubits, 0 <= q < n;
+ *   - complex numbers are (re, im) pairs of doubles on the host side;
+ *   - a 2x2 matrix u[8] is row-major: u = {U00re,U00im, U01re,U01im,
+ *     U10re,U10im, U11re,U11im}; it acts as in Eq. (1): for every index i
+ *     with bit t clear and j = i + 2^t, (psi_i, psi_j) <- U (psi_i, psi_j);
+ *   - a 2^k x 2^k matrix m has row/column index r = sum_j b_{targets[j]} 2^j,
+ *     row-major, (re, im) pairs: m[2*(row*2^k + col) + {0,1}];
+ *   - device buffers are borrowed, never freed by the library; the caller
+ *     keeps them alive until juqcs_state_destroy returns;
+ *   - host arrays passed in are copied before the call returns;
+ *   - every apply call is asynchronous on the handle's HIP stream; calls that
+ *     return host data (amplitudes, norm, expectations) synchronise it;
+ *   - every function returns a juqcs_status; arguments are validated on the
+ *     host before anything is launched, and the library never aborts.
+ *     Asynchronous device errors surface at the next synchronising call as
+ *     JUQCS_ERR_HIP.  juqcs_last_error() returns a message for the last
+ *     non-OK status of the calling thread;
+ *   - a handle is not thread-safe; separate handles are independent.
+ */
+#ifndef JUQCS_GPU_H
+#define JUQCS_GPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JUQCS_OK = 0,
+  JUQCS_ERR_ARG = -1,         /* null pointer, bad count, bad option        */
+  JUQCS_ERR_QUBIT = -2,       /* qubit out of range or repeated             */
+  JUQCS_ERR_DTYPE = -3,       /* operation not defined for this amplitude type */
+  JUQCS_ERR_SIZE = -4,        /* buffer smaller than juqcs_state_bytes says */
+  JUQCS_ERR_HIP = -5,         /* HIP runtime error (message has the text)   */
+  JUQCS_ERR_UNSUPPORTED = -6, /* valid request this build does not support  */
+  JUQCS_ERR_NUMERIC = -7      /* non-finite matrix entry or non-finite norm */
+} juqcs_status;
+
+/* Amplitude storage.  C128: FP64 complex, 16 B/amp (the paper's numerically
+ * exact form, Section 1).  C64: FP32 complex, 8 B/amp.  ENC2: the two-byte
+ * form (Section 1 says only "adaptive coding", two bytes per amplitude; this
+ * library defines it): blocks of 2^B consecutive amplitudes share one FP32
+ * scale s = max |component|; each component is int8 q = rint(x * fl(127/s)),
+ * decoded as q * fl(s/127).  Gate arithmetic on ENC2 states is FP32. */
+typedef enum { JUQCS_C128 = 0, JUQCS_C64 = 1, JUQCS_ENC2 = 2 } juqcs_dtype;
+
+/* Arithmetic of a fused dense block (juqcs_apply_fused_k). */
+typedef enum {
+  JUQCS_MMA_FP64 = 0,   /* FP64 matrix cores (C128 states)                 */
+  JUQCS_MMA_FP32 = 1,   /* FP32 matrix cores (C64 states)                  */
+  JUQCS_MMA_BF16 = 2,   /* BF16 inputs, FP32 accumulation (C64 states)     */
+  JUQCS_MMA_BF16X3 = 3, /* hi/lo BF16 split, three products, FP32 accum.   */
+  JUQCS_MMA_AUTO = 4    /* FP64 for C128, FP32 for C64                     */
+} juqcs_mma;
+
+/* Gate record: the unit of a circuit handed to juqcs_run_circuit and the
+ * batch / branch calls.  88 bytes, naturally aligned. */
+typedef enum {
+  JUQCS_OP_H = 0, JUQCS_OP_X = 1, JUQCS_OP_Y = 2, JUQCS_OP_Z = 3,
+  JUQCS_OP_S = 4, JUQCS_OP_T = 5,
+  JUQCS_OP_U = 6,    /* arbitrary 2x2 in u[8] on q0                            */
+  JUQCS_OP_CNOT = 7, /* control q0, target q1 (Section 3: "(CNOT i i+1)")      */
+  JUQCS_OP_CZ = 8,   /* sign flip where q0 and q1 are both 1 (Section 4)       */
+  JUQCS_OP_CP = 9    /* phase e^{i theta} where q0 and q1 are both 1           */
+} juqcs_op;
+
+typedef struct {
+  int32_t op;     /* juqcs_op                                   */
+  int32_t q0;     /* target (1q), control (CNOT), first qubit   */
+  int32_t q1;     /* target (CNOT), second qubit (CZ, CP); -1 for 1q */
+  int32_t pad;
+  double theta;   /* CP angle                                   */
+  double u[8];    /* JUQCS_OP_U matrix                          */
+} juqcs_gate;
+
+typedef struct juqcs_state juqcs_state; /* opaque host-side handle */
+
+/* ------------------------------------------------------------------------
+ * Sizing and lifetime
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device memory a state needs.  amp_bytes: 2^n amplitudes
+ * (16, 8 or 2 bytes each).  scale_bytes: ENC2 scales, 4 * ceil(2^n / 2^B)
+ * (0 for C128/C64).  work_bytes: library workspace (gate programs, partial
+ * sums, index lists).  block_bits B is used for ENC2 only (0 = default 8,
+ * else 4..12).  1 <= n <= 40.  Errors: JUQCS_ERR_ARG. */
+juqcs_status juqcs_state_bytes(int n, juqcs_dtype dtype, int block_bits,
+                               size_t* amp_bytes, size_t* scale_bytes,
+                               size_t* work_bytes);
+
+/* Wrap caller-owned device buffers (sizes at least those of
+ * juqcs_state_bytes; d_scales may be NULL unless ENC2; d_work may be NULL,
+ * then the library allocates its own workspace and frees it on destroy).
+ * hip_stream is a hipStream_t (NULL = default stream).  The amplitudes are
+ * not initialised: call juqcs_state_init.  Errors: ARG, SIZE, DTYPE, HIP. */
+juqcs_status juqcs_state_create(juqcs_state** out, int n, juqcs_dtype dtype,
+                                int block_bits, void* d_amps, size_t amp_bytes,
+                                void* d_scales, size_t scale_bytes,
+                                void* d_work, size_t work_bytes,
+                                void* hip_stream);
+
+/* Releases the handle (not the caller's buffers). NULL is accepted. */
+juqcs_status juqcs_state_destroy(juqcs_state* st);
+
+/* psi = |basis_index> (the computer starts in |0...0>, Section 4 before
+ * Eq. (3)); resets the qubit permutation to identity.  Errors: ARG. */
+juqcs_status juqcs_state_init(juqcs_state* st, uint64_t basis_index);
+
+/* Switch the handle's stream. */
+juqcs_status juqcs_state_set_stream(juqcs_state* st, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Single gates (Section 2, Eq. (1)); one pass over the touched amplitudes
+ * ---------------------------------------------------------------------- */
+
+/* Eq. (1) on target t.  Diagonal matrices only touch the amplitudes whose
+ * factor differs from 1.  Errors: QUBIT, ARG (null u), NUMERIC. */
+juqcs_status juqcs_apply_1q(juqcs_state* st, int t, const double u[8]);
+
+/* Controlled-U: Eq. (1) on target t for the indices whose bit c is 1
+ * (CNOT = controlled-X, CZ = controlled-Z; Sections 3 and 4).
+ * Errors: QUBIT (c == t or out of range), ARG, NUMERIC. */
+juqcs_status juqcs_apply_controlled(juqcs_state* st, int c, int t, const double u[8]);
+
+/* General two-qubit gate, 4x4 matrix with row/col index b_q0 + 2 b_q1.
+ * Errors: QUBIT, ARG, NUMERIC. */
+juqcs_status juqcs_apply_2q(juqcs_state* st, int q0, int q1, const double m[32]);
+
+/* Dense 2^k x 2^k block on k distinct targets (1 <= k <= 6), applied as a
+ * dense contraction [2^k x 2^k] x [2^k x 2^(n-k)] on the matrix cores.
+ * mode: FP64 for C128; FP32, BF16 or BF16X3 (FP32 accumulation) for C64;
+ * AUTO picks FP64 / FP32.  ENC2: JUQCS_ERR_DTYPE.  Errors: QUBIT, ARG,
+ * DTYPE, NUMERIC. */
+juqcs_status juqcs_apply_fused_k(juqcs_state* st, int k, const int* targets,
+                                 const double* m, juqcs_mma mode);
+
+/* ------------------------------------------------------------------------
+ * Whole circuits through the planner
+ * ---------------------------------------------------------------------- */
+typedef enum {
+  JUQCS_PLAN_PLAIN = 0, /* one kernel pass per gate (the paper's scheme)   */
+  JUQCS_PLAN_TILE = 1,  /* on-chip tile passes: every gate whose qubits lie
+                           in the chosen tile bits is applied in LDS, one
+                           HBM read+write per pass                        */
+  JUQCS_PLAN_FUSED = 2, /* greedy fusion into dense k-qubit blocks applied
+                           with juqcs_apply_fused_k's kernels             */
+  JUQCS_PLAN_AUTO = 3   /* TILE (the fastest on this hardware)             */
+} juqcs_plan_mode;
+
+typedef struct {
+  int32_t mode;        /* juqcs_plan_mode                                */
+  int32_t fuse_k;      /* FUSED: block width 2..6 (0 = 5)                 */
+  int32_t mma;         /* FUSED: juqcs_mma                                */
+  int32_t tile_bits;   /* TILE: total tile bits (0 = default for dtype)   */
+  int32_t low_bits;    /* TILE: contiguous low bits per chunk (0 = default) */
+  int32_t reserved[3];
+  /* outputs */
+  int64_t passes;      /* kernel passes over the state that were launched */
+  int64_t gates;       /* gate records consumed                           */
+} juqcs_plan_opts;
+
+/* Applies count gate records in order (gates commuting on disjoint qubits
+ * may be regrouped; the result equals the sequential product).  opts may be
+ * NULL (AUTO).  Errors: ARG, QUBIT, NUMERIC, UNSUPPORTED. */
+juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates,
+                               size_t count, juqcs_plan_opts* opts);
+
+/* ------------------------------------------------------------------------
+ * Read-out
+ * ---------------------------------------------------------------------- */
+
+/* out[2k], out[2k+1] = re, im of <idx[k]|psi> (logical basis index; ENC2
+ * amplitudes are decoded).  Host arrays; synchronises the stream.
+ * (Section 4: the M requested coefficients.)  Errors: ARG, HIP. */
+juqcs_status juqcs_amplitudes(juqcs_state* st, const uint64_t* idx,
+                              size_t count, double* out);
+
+/* Same on device arrays, asynchronous (idx: count uint64, out: 2*count
+ * doubles). */
+juqcs_status juqcs_amplitudes_device(juqcs_state* st, const uint64_t* d_idx,
+                                     size_t count, double* d_out);
+
+/* out = sum_i |psi_i|^2, FP64 accumulation in a fixed order (deterministic).
+ * Synchronises.  Errors: HIP, NUMERIC (result not finite). */
+juqcs_status juqcs_norm(juqcs_state* st, double* out);
+
+/* Multiplies every amplitude by the real factor (FP64 for C128, FP32 for
+ * C64; ENC2 scales are multiplied).  Used to renormalise by 1/sqrt(norm). */
+juqcs_status juqcs_scale(juqcs_state* st, double factor);
+
+/* Single-qubit expectation values <Q_alpha(i)> = (1 - <sigma^alpha_i>)/2
+ * for every qubit (Section 3), alpha = x, y, z: out[3*i + a], FP64, one
+ * read pass.  Synchronises.  Errors: ARG, HIP. */
+juqcs_status juqcs_expectations(juqcs_state* st, double* out);
+
+/* ------------------------------------------------------------------------
+ * Qubit layout
+ * ---------------------------------------------------------------------- */
+
+/* Moves logical qubit q to physical bit new_phys[q] (a permutation of
+ * 0..n-1): one read+write pass.  Logical results are unchanged.
+ * Errors: ARG, QUBIT. */
+juqcs_status juqcs_permute(juqcs_state* st, const int* new_phys);
+
+/* Restores identity order (physical bit q = logical qubit q), so the raw
+ * buffer can be read directly. */
+juqcs_status juqcs_state_canonicalize(juqcs_state* st);
+
+/* Current logical->physical map (n ints). */
+juqcs_status juqcs_get_layout(const juqcs_state* st, int* phys);
+
+/* ------------------------------------------------------------------------
+ * Two-byte codec (Section 1, adaptive two-byte amplitudes)
+ * ---------------------------------------------------------------------- */
+
+/* Encodes count amplitudes (C128 or C64 source, device) into d_codes
+ * (2*count int8) and d_scales (ceil(count / 2^B) floats).  Bit-exact with the
+ * format described at juqcs_dtype.  Asynchronous on hip_stream.
+ * Errors: ARG, DTYPE. */
+juqcs_status juqcs_encode2(const void* d_src, juqcs_dtype src, uint64_t count,
+                           int block_bits, void* d_codes, void* d_scales,
+                           void* hip_stream);
+
+/* Decodes into C128 or C64 amplitudes (device).  Errors: ARG, DTYPE. */
+juqcs_status juqcs_decode2(const void* d_codes, const void* d_scales,
+                           uint64_t count, int block_bits, void* d_dst,
+                           juqcs_dtype dst, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent circuits (many small states, one persistent launch)
+ * ---------------------------------------------------------------------- */
+
+typedef struct juqcs_batch juqcs_batch; /* opaque */
+
+/* Builds a batch of count circuits: circuit i has n[i] qubits (1..30) and
+ * gate records gates[offsets[i] .. offsets[i+1]).  States are C64 in
+ * d_states at byte offsets state_offset[i] (each 8 * 2^n[i] bytes, caller
+ * allocated, disjoint); every circuit starts from |0...0>.  The planner
+ * builds a device work list once (uploaded into library-owned device
+ * memory); juqcs_batch_run then executes everything in one persistent
+ * kernel launch.  Errors: ARG, QUBIT, NUMERIC, HIP. */
+juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
+                                const juqcs_gate* gates, const int64_t* offsets,
+                                void* d_states, const uint64_t* state_offset,
+                                const juqcs_plan_opts* opts);
+
+/* Runs the whole batch on hip_stream (asynchronous; may be captured in a
+ * HIP graph). */
+juqcs_status juqcs_batch_run(juqcs_batch* b, void* hip_stream);
+
+/* Work-list statistics: passes (tile tasks) and total gate applications. */
+juqcs_status juqcs_batch_stats(const juqcs_batch* b, int64_t* tasks,
+                               int64_t* gate_apps, int64_t* passes);
+
+juqcs_status juqcs_batch_destroy(juqcs_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Entangling-gate decomposition (Section 4, Eqs. (2) and (3))
+ * ---------------------------------------------------------------------- */
+
+/* <z|C|0> for count bitstrings z of an n-qubit circuit (n <= 62) whose
+ * qubits are split in two parts by side[q] in {0,1} (each part at most 30
+ * qubits).  Every CZ whose qubits lie in different parts is decomposed with
+ * Eq. (2) (x = pi/4 - (i/2) asinh 1); branch b in [0, 2^m) uses s_k = +1 if
+ * bit k of b is 0, else -1, for the k-th crossing CZ in circuit order, and
+ * applies diag(e^{i(x s_k - pi/4)}, e^{-i(x s_k - pi/4)}) to both of its
+ * qubits at that position.  Every branch's two half-states are simulated in
+ * C64 with batched persistent launches (group_size half-states resident at
+ * a time, 0 = automatic), and the result
+ * 2^-m sum_b A_b(z_A) B_b(z_B) is summed in FP64 on the device (Eq. (3)).
+ * Only CZ may cross the cut (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.
+ * out: 2*count doubles (host).  Synchronises hip_stream.  The library
+ * allocates the device memory this needs and frees it before returning. */
+juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates,
+                                     size_t gate_count, const uint8_t* side,
+                                     const uint64_t* z, size_t count,
+                                     int group_size, double* out,
+                                     void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Utilities
+ * ---------------------------------------------------------------------- */
+
+/* Device-to-device streaming copy of bytes (multiple of 16, 16-byte aligned
+ * pointers) with the library's own copy kernel: the practical HBM ceiling
+ * that gate passes are compared with.  Asynchronous. */
+juqcs_status juqcs_copy(void* d_dst, const void* d_src, size_t bytes,
+                        void* hip_stream);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* juqcs_last_error(void);
+
+/* Library version string. */
+const char* juqcs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JUQCS_GPU_H */

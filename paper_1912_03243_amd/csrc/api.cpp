@@ -1,0 +1,660 @@
+// C-ABI entry points of libjuqcs_gpu (declared in include/juqcs_gpu.h).
+// Host-side validation, the logical->physical qubit map, workspace handling,
+// and dispatch to the kernels and the planner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "juqcs_internal.hpp"
+
+namespace juqcs {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace juqcs
+
+using namespace juqcs;
+
+namespace {
+
+constexpr size_t kWorkBytes = size_t(32) << 20;  // 32 MiB library workspace
+constexpr size_t kPartialOff = 0;                // 16 KiB of FP64 partials
+constexpr size_t kResultOff = 64 << 10;          // small results (norm, Pauli sums)
+constexpr size_t kRingOff = 128 << 10;           // programs, matrices, indices
+constexpr int kDefaultBlockBits = 8;
+
+using C = cplx<double>;
+
+juqcs_status fail(juqcs_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+juqcs_status hip_fail(hipError_t e, const char* where) {
+  set_error(std::string(where) + ": " + hipGetErrorString(e));
+  return JUQCS_ERR_HIP;
+}
+
+size_t amp_size(juqcs_dtype dt) { return dt == JUQCS_C128 ? 16 : dt == JUQCS_C64 ? 8 : 2; }
+
+bool finite8(const double* u, int count) {
+  for (int i = 0; i < count; ++i)
+    if (!std::isfinite(u[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct juqcs_state {
+  int n;
+  juqcs_dtype dt;
+  int B;
+  void* amps;
+  void* scales;
+  char* work;
+  size_t work_bytes;
+  bool own_work;
+  hipStream_t stream;
+  int phys[64];  // logical qubit -> physical bit
+  size_t ring;   // next free offset inside the ring
+};
+
+namespace {
+
+// Stream-ordered ring allocation inside the workspace: later kernels on the
+// same stream only start after earlier ones finish, so reusing ring space is
+// safe for work issued on the handle's stream.
+char* ring_alloc(juqcs_state* st, size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (kRingOff + bytes > st->work_bytes) return nullptr;
+  if (st->ring + bytes > st->work_bytes) st->ring = kRingOff;
+  char* p = st->work + st->ring;
+  st->ring += bytes;
+  return p;
+}
+
+juqcs_status upload(juqcs_state* st, const void* host, size_t bytes, char** dev) {
+  *dev = ring_alloc(st, bytes);
+  if (!*dev) return fail(JUQCS_ERR_SIZE, "workspace too small for upload");
+  hipError_t e = hipMemcpyAsync(*dev, host, bytes, hipMemcpyHostToDevice, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  return JUQCS_OK;
+}
+
+juqcs_status check_state(const juqcs_state* st) {
+  if (!st) return fail(JUQCS_ERR_ARG, "null state handle");
+  return JUQCS_OK;
+}
+
+juqcs_status check_qubit(const juqcs_state* st, int q) {
+  if (q < 0 || q >= st->n) return fail(JUQCS_ERR_QUBIT, "qubit out of range");
+  return JUQCS_OK;
+}
+
+bool is_diag2(const C u[4]) {
+  return u[1].re == 0.0 && u[1].im == 0.0 && u[2].re == 0.0 && u[2].im == 0.0;
+}
+bool is_one(C z) { return z.re == 1.0 && z.im == 0.0; }
+
+template <typename T>
+void convert(const std::vector<C>& in, std::vector<cplx<T>>* out) {
+  out->resize(in.size());
+  for (size_t i = 0; i < in.size(); ++i) (*out)[i] = {(T)in[i].re, (T)in[i].im};
+}
+
+// Runs a tile plan: upload ops + matrices once, then launch every pass.
+juqcs_status run_tile_plan(juqcs_state* st, const TilePlan& plan) {
+  if (plan.passes.empty()) return JUQCS_OK;
+  const size_t ops_bytes = plan.ops.size() * sizeof(TileOp);
+  std::vector<char> buf;
+  size_t mats_off = (ops_bytes + 255) & ~size_t(255);
+  if (st->dt == JUQCS_C128) {
+    buf.resize(mats_off + plan.mats.size() * sizeof(C));
+    std::memcpy(buf.data() + mats_off, plan.mats.data(), plan.mats.size() * sizeof(C));
+  } else {
+    std::vector<cplx<float>> m;
+    convert(plan.mats, &m);
+    buf.resize(mats_off + m.size() * sizeof(cplx<float>));
+    std::memcpy(buf.data() + mats_off, m.data(), m.size() * sizeof(cplx<float>));
+  }
+  std::memcpy(buf.data(), plan.ops.data(), ops_bytes);
+  char* dev = nullptr;
+  juqcs_status rc = upload(st, buf.data(), buf.size(), &dev);
+  if (rc != JUQCS_OK) return rc;
+  const TileOp* d_ops = (const TileOp*)dev;
+  const void* d_mats = dev + mats_off;
+  for (const TilePass& p : plan.passes) {
+    hipError_t e = launch_tile(st->dt, st->amps, st->scales, p.g, d_ops + p.op_begin,
+                               p.op_count, d_mats, st->stream);
+    if (e != hipSuccess) return hip_fail(e, "tile pass launch");
+  }
+  return JUQCS_OK;
+}
+
+void default_tile_bits(juqcs_dtype dt, int B, int* L, int* b) {
+  if (dt == JUQCS_C128) {
+    *b = 12;
+    *L = 6;
+  } else if (dt == JUQCS_C64) {
+    *b = 13;
+    *L = 7;
+  } else {
+    *b = 13;
+    *L = std::max(B, 7);
+  }
+}
+
+juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, int b,
+                        int64_t* passes) {
+  const int maxb = tile_max_bits(st->dt);
+  if (b <= 0 || L <= 0) default_tile_bits(st->dt, st->B, &L, &b);
+  if (b > maxb) return fail(JUQCS_ERR_ARG, "tile_bits above the LDS limit");
+  if (L > b) return fail(JUQCS_ERR_ARG, "low_bits > tile_bits");
+  if (b - L > kMaxGather) return fail(JUQCS_ERR_ARG, "too many gathered tile bits");
+  if (st->dt == JUQCS_ENC2 && L < st->B) L = st->B;
+  if (st->dt == JUQCS_ENC2 && b < L) b = L;
+  TilePlan plan;
+  plan_tiles(st->n, std::min(L, st->n), b, st->B, gates, &plan);
+  if (passes) *passes = (int64_t)plan.passes.size();
+  return run_tile_plan(st, plan);
+}
+
+// Gate on physical qubits.
+Gate make_gate1(int t, const C u[4]) {
+  Gate g{};
+  g.nq = 1;
+  g.q[0] = t;
+  g.q[1] = -1;
+  for (int i = 0; i < 4; ++i) g.m[i] = u[i];
+  g.diag = is_diag2(u);
+  return g;
+}
+
+juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g) {
+  hipError_t e = hipSuccess;
+  if (st->dt == JUQCS_ENC2) {
+    std::vector<Gate> one{g};
+    return tile_gates(st, one, 0, 0, nullptr);
+  }
+  if (g.nq == 1) {
+    const C* u = g.m;
+    if (g.diag && is_one(u[0])) {
+      if (is_one(u[3])) return JUQCS_OK;  // identity
+      e = launch_diag(st->dt, st->amps, st->n, uint64_t(1) << g.q[0], u[3], st->stream);
+    } else {
+      e = launch_1q(st->dt, st->amps, st->n, g.q[0], -1, u, st->stream);
+    }
+  } else {
+    // controlled-U form: identity where bit q0 is clear?
+    const C* m = g.m;
+    bool ctrl = true;  // rows/cols with b_q0 = 0 are identity (index r = b_q0 + 2 b_q1)
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        const bool r0 = (r & 1) == 0, c0 = (c & 1) == 0;
+        if (r0 || c0) {
+          const C want = (r == c) ? C{1, 0} : C{0, 0};
+          if (m[r * 4 + c].re != want.re || m[r * 4 + c].im != want.im) ctrl = false;
+        }
+      }
+    if (ctrl) {
+      const C u[4] = {m[1 * 4 + 1], m[1 * 4 + 3], m[3 * 4 + 1], m[3 * 4 + 3]};
+      if (is_diag2(u) && is_one(u[0])) {
+        if (is_one(u[3])) return JUQCS_OK;
+        e = launch_diag(st->dt, st->amps, st->n, (uint64_t(1) << g.q[0]) | (uint64_t(1) << g.q[1]),
+                        u[3], st->stream);
+      } else {
+        e = launch_1q(st->dt, st->amps, st->n, g.q[1], g.q[0], u, st->stream);
+      }
+    } else {
+      e = launch_2q(st->dt, st->amps, st->n, g.q[0], g.q[1], m, st->stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "gate launch");
+  return JUQCS_OK;
+}
+
+// Real embedding of a complex K x K matrix, padded to R = max(16, 2K), stored
+// transposed (At[col * R + row]), interleaved rows (row 2r+p = part p of r).
+template <typename T>
+std::vector<T> embed_real(const C* m, int K) {
+  const int R = std::max(16, 2 * K);
+  std::vector<T> at((size_t)R * R, T(0));
+  for (int r = 0; r < K; ++r)
+    for (int c = 0; c < K; ++c) {
+      const C z = m[r * K + c];
+      // rows (2r, 2r+1), cols (2c, 2c+1): [[re, -im], [im, re]]
+      at[(size_t)(2 * c) * R + 2 * r] = (T)z.re;
+      at[(size_t)(2 * c + 1) * R + 2 * r] = (T)(-z.im);
+      at[(size_t)(2 * c) * R + 2 * r + 1] = (T)z.im;
+      at[(size_t)(2 * c + 1) * R + 2 * r + 1] = (T)z.re;
+    }
+  return at;
+}
+
+juqcs_status apply_fused_phys(juqcs_state* st, int k, const int* targets, const C* m,
+                              juqcs_mma mode) {
+  if (mode == JUQCS_MMA_AUTO) mode = st->dt == JUQCS_C128 ? JUQCS_MMA_FP64 : JUQCS_MMA_FP32;
+  if (st->dt == JUQCS_C128 && mode != JUQCS_MMA_FP64)
+    return fail(JUQCS_ERR_DTYPE, "C128 states use FP64 matrix cores");
+  if (st->dt == JUQCS_C64 && mode == JUQCS_MMA_FP64)
+    return fail(JUQCS_ERR_DTYPE, "C64 states use FP32/BF16 matrix cores");
+  const int K = 1 << k;
+  char* dev = nullptr;
+  juqcs_status rc;
+  if (mode == JUQCS_MMA_FP64) {
+    std::vector<double> at = embed_real<double>(m, K);
+    rc = upload(st, at.data(), at.size() * sizeof(double), &dev);
+  } else {
+    std::vector<float> at = embed_real<float>(m, K);
+    rc = upload(st, at.data(), at.size() * sizeof(float), &dev);
+  }
+  if (rc != JUQCS_OK) return rc;
+  hipError_t e = launch_fused(st->dt, st->amps, st->n, k, targets, dev, mode, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "fused launch");
+  return JUQCS_OK;
+}
+
+juqcs_status decode_all(juqcs_state* st, const juqcs_gate* gates, size_t count,
+                        std::vector<Gate>* out) {
+  out->resize(count);
+  std::string err;
+  for (size_t i = 0; i < count; ++i) {
+    if (!decode_gate(gates[i], st->n, &(*out)[i], &err)) {
+      const bool numeric = err.find("non-finite") != std::string::npos;
+      const bool qubit = err.find("qubit") != std::string::npos;
+      return fail(numeric ? JUQCS_ERR_NUMERIC : qubit ? JUQCS_ERR_QUBIT : JUQCS_ERR_ARG,
+                  "gate " + std::to_string(i) + ": " + err);
+    }
+    Gate& g = (*out)[i];
+    for (int j = 0; j < g.nq; ++j) g.q[j] = st->phys[g.q[j]];
+  }
+  return JUQCS_OK;
+}
+
+juqcs_status sync(juqcs_state* st) {
+  hipError_t e = hipStreamSynchronize(st->stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "device");
+  return JUQCS_OK;
+}
+
+// Physical data move: SWAP gates on physical bit pairs, run as tile passes.
+juqcs_status move_layout(juqcs_state* st, const int* target) {
+  std::vector<int> cur(st->phys, st->phys + st->n);
+  std::vector<Gate> swaps;
+  // where[p] = logical qubit currently at physical bit p
+  std::vector<int> where(st->n);
+  for (int q = 0; q < st->n; ++q) where[cur[q]] = q;
+  for (int q = 0; q < st->n; ++q) {
+    const int from = cur[q], to = target[q];
+    if (from == to) continue;
+    Gate g{};
+    g.nq = 2;
+    g.q[0] = from;
+    g.q[1] = to;
+    for (int i = 0; i < 16; ++i) g.m[i] = C{0, 0};
+    g.m[0] = g.m[1 * 4 + 2] = g.m[2 * 4 + 1] = g.m[15] = C{1, 0};  // SWAP
+    g.diag = false;
+    swaps.push_back(g);
+    const int other = where[to];
+    cur[other] = from;
+    where[from] = other;
+    cur[q] = to;
+    where[to] = q;
+  }
+  if (!swaps.empty()) {
+    juqcs_status rc = tile_gates(st, swaps, 0, 0, nullptr);
+    if (rc != JUQCS_OK) return rc;
+  }
+  for (int q = 0; q < st->n; ++q) st->phys[q] = target[q];
+  return JUQCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* juqcs_last_error(void) { return juqcs::g_last_error.c_str(); }
+
+const char* juqcs_version(void) { return "juqcs_gpu 0.1 (gfx950)"; }
+
+juqcs_status juqcs_state_bytes(int n, juqcs_dtype dt, int block_bits, size_t* amp_bytes,
+                               size_t* scale_bytes, size_t* work_bytes) {
+  if (n < 1 || n > 40) return fail(JUQCS_ERR_ARG, "n must be in [1, 40]");
+  if (dt != JUQCS_C128 && dt != JUQCS_C64 && dt != JUQCS_ENC2)
+    return fail(JUQCS_ERR_DTYPE, "unknown dtype");
+  int B = block_bits == 0 ? kDefaultBlockBits : block_bits;
+  if (dt == JUQCS_ENC2) {
+    if (B < 3 || B > 12) return fail(JUQCS_ERR_ARG, "block_bits must be in [3, 12]");
+    if (n < B) return fail(JUQCS_ERR_ARG, "ENC2 needs n >= block_bits");
+  }
+  const uint64_t count = uint64_t(1) << n;
+  if (amp_bytes) *amp_bytes = (size_t)(count * amp_size(dt));
+  if (scale_bytes) *scale_bytes = dt == JUQCS_ENC2 ? (size_t)(4 * (count >> B)) : 0;
+  if (work_bytes) *work_bytes = kWorkBytes;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_state_create(juqcs_state** out, int n, juqcs_dtype dt, int block_bits,
+                                void* d_amps, size_t amp_bytes, void* d_scales,
+                                size_t scale_bytes, void* d_work, size_t work_bytes,
+                                void* hip_stream) {
+  if (!out) return fail(JUQCS_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  size_t need_a = 0, need_s = 0, need_w = 0;
+  juqcs_status rc = juqcs_state_bytes(n, dt, block_bits, &need_a, &need_s, &need_w);
+  if (rc != JUQCS_OK) return rc;
+  if (!d_amps) return fail(JUQCS_ERR_ARG, "null amplitude buffer");
+  if (((uintptr_t)d_amps & 15) != 0) return fail(JUQCS_ERR_ARG, "amplitudes not 16-byte aligned");
+  if (amp_bytes < need_a) return fail(JUQCS_ERR_SIZE, "amplitude buffer too small");
+  if (dt == JUQCS_ENC2) {
+    if (!d_scales) return fail(JUQCS_ERR_ARG, "null scale buffer");
+    if (scale_bytes < need_s) return fail(JUQCS_ERR_SIZE, "scale buffer too small");
+  }
+  if (d_work && work_bytes < need_w) return fail(JUQCS_ERR_SIZE, "workspace too small");
+  juqcs_state* st = new juqcs_state();
+  st->n = n;
+  st->dt = dt;
+  st->B = dt == JUQCS_ENC2 ? (block_bits == 0 ? kDefaultBlockBits : block_bits) : 0;
+  st->amps = d_amps;
+  st->scales = d_scales;
+  st->stream = (hipStream_t)hip_stream;
+  st->own_work = false;
+  if (d_work) {
+    st->work = (char*)d_work;
+    st->work_bytes = work_bytes;
+  } else {
+    hipError_t e = hipMalloc((void**)&st->work, need_w);
+    if (e != hipSuccess) {
+      delete st;
+      return hip_fail(e, "workspace hipMalloc");
+    }
+    st->work_bytes = need_w;
+    st->own_work = true;
+  }
+  st->ring = kRingOff;
+  for (int q = 0; q < 64; ++q) st->phys[q] = q;
+  *out = st;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_state_destroy(juqcs_state* st) {
+  if (!st) return JUQCS_OK;
+  if (st->own_work) {
+    (void)hipStreamSynchronize(st->stream);
+    (void)hipFree(st->work);
+  }
+  delete st;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_state_set_stream(juqcs_state* st, void* hip_stream) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  st->stream = (hipStream_t)hip_stream;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_state_init(juqcs_state* st, uint64_t basis_index) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (st->n < 64 && (basis_index >> st->n) != 0) return fail(JUQCS_ERR_ARG, "basis index >= 2^n");
+  for (int q = 0; q < 64; ++q) st->phys[q] = q;
+  hipError_t e = launch_init(st->dt, st->amps, st->scales, st->n, st->B, basis_index, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "init launch");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_apply_1q(juqcs_state* st, int t, const double u[8]) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!u) return fail(JUQCS_ERR_ARG, "null matrix");
+  if (juqcs_status rc = check_qubit(st, t)) return rc;
+  if (!finite8(u, 8)) return fail(JUQCS_ERR_NUMERIC, "non-finite matrix entry");
+  const C m[4] = {{u[0], u[1]}, {u[2], u[3]}, {u[4], u[5]}, {u[6], u[7]}};
+  return apply_gate_plain(st, make_gate1(st->phys[t], m));
+}
+
+juqcs_status juqcs_apply_controlled(juqcs_state* st, int c, int t, const double u[8]) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!u) return fail(JUQCS_ERR_ARG, "null matrix");
+  if (juqcs_status rc = check_qubit(st, c)) return rc;
+  if (juqcs_status rc = check_qubit(st, t)) return rc;
+  if (c == t) return fail(JUQCS_ERR_QUBIT, "control equals target");
+  if (!finite8(u, 8)) return fail(JUQCS_ERR_NUMERIC, "non-finite matrix entry");
+  Gate g{};
+  g.nq = 2;
+  g.q[0] = st->phys[c];
+  g.q[1] = st->phys[t];
+  for (int i = 0; i < 16; ++i) g.m[i] = C{0, 0};
+  g.m[0] = g.m[2 * 4 + 2] = C{1, 0};  // index b_c + 2 b_t: control clear -> identity
+  g.m[1 * 4 + 1] = C{u[0], u[1]};
+  g.m[1 * 4 + 3] = C{u[2], u[3]};
+  g.m[3 * 4 + 1] = C{u[4], u[5]};
+  g.m[3 * 4 + 3] = C{u[6], u[7]};
+  g.diag = false;
+  return apply_gate_plain(st, g);
+}
+
+juqcs_status juqcs_apply_2q(juqcs_state* st, int q0, int q1, const double m[32]) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!m) return fail(JUQCS_ERR_ARG, "null matrix");
+  if (juqcs_status rc = check_qubit(st, q0)) return rc;
+  if (juqcs_status rc = check_qubit(st, q1)) return rc;
+  if (q0 == q1) return fail(JUQCS_ERR_QUBIT, "repeated qubit");
+  if (!finite8(m, 32)) return fail(JUQCS_ERR_NUMERIC, "non-finite matrix entry");
+  Gate g{};
+  g.nq = 2;
+  g.q[0] = st->phys[q0];
+  g.q[1] = st->phys[q1];
+  for (int i = 0; i < 16; ++i) g.m[i] = C{m[2 * i], m[2 * i + 1]};
+  g.diag = false;
+  return apply_gate_plain(st, g);
+}
+
+juqcs_status juqcs_apply_fused_k(juqcs_state* st, int k, const int* targets, const double* m,
+                                 juqcs_mma mode) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!targets || !m) return fail(JUQCS_ERR_ARG, "null targets or matrix");
+  if (k < 1 || k > 6 || k > st->n) return fail(JUQCS_ERR_ARG, "k must be in [1, min(6, n)]");
+  if (st->dt == JUQCS_ENC2) return fail(JUQCS_ERR_DTYPE, "fused blocks need C128 or C64");
+  if (mode < JUQCS_MMA_FP64 || mode > JUQCS_MMA_AUTO) return fail(JUQCS_ERR_ARG, "bad mma mode");
+  int phys[6];
+  for (int j = 0; j < k; ++j) {
+    if (juqcs_status rc = check_qubit(st, targets[j])) return rc;
+    for (int i = 0; i < j; ++i)
+      if (targets[i] == targets[j]) return fail(JUQCS_ERR_QUBIT, "repeated target");
+    phys[j] = st->phys[targets[j]];
+  }
+  const int K = 1 << k;
+  if (!finite8(m, 2 * K * K)) return fail(JUQCS_ERR_NUMERIC, "non-finite matrix entry");
+  std::vector<C> mm(K * K);
+  for (int i = 0; i < K * K; ++i) mm[i] = C{m[2 * i], m[2 * i + 1]};
+  return apply_fused_phys(st, k, phys, mm.data(), mode);
+}
+
+juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates, size_t count,
+                               juqcs_plan_opts* opts) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (count > 0 && !gates) return fail(JUQCS_ERR_ARG, "null gate array");
+  juqcs_plan_opts dflt{};
+  dflt.mode = JUQCS_PLAN_AUTO;
+  juqcs_plan_opts* o = opts ? opts : &dflt;
+  if (o->mode < JUQCS_PLAN_PLAIN || o->mode > JUQCS_PLAN_AUTO)
+    return fail(JUQCS_ERR_ARG, "bad plan mode");
+  std::vector<Gate> g;
+  if (juqcs_status rc = decode_all(st, gates, count, &g)) return rc;
+  int mode = o->mode == JUQCS_PLAN_AUTO ? JUQCS_PLAN_TILE : o->mode;
+  if (st->dt == JUQCS_ENC2) mode = JUQCS_PLAN_TILE;
+  o->gates = (int64_t)count;
+  o->passes = 0;
+  if (mode == JUQCS_PLAN_PLAIN) {
+    for (const Gate& x : g) {
+      if (juqcs_status rc = apply_gate_plain(st, x)) return rc;
+      ++o->passes;
+    }
+    return JUQCS_OK;
+  }
+  if (mode == JUQCS_PLAN_TILE) {
+    int64_t passes = 0;
+    juqcs_status rc = tile_gates(st, g, o->low_bits, o->tile_bits, &passes);
+    o->passes = passes;
+    return rc;
+  }
+  // FUSED
+  int k = o->fuse_k == 0 ? 5 : o->fuse_k;
+  if (k < 1 || k > 6) return fail(JUQCS_ERR_ARG, "fuse_k must be in [1, 6]");
+  k = std::min(k, st->n);
+  juqcs_mma mode_mma = (juqcs_mma)o->mma;
+  if (mode_mma == JUQCS_MMA_FP64 && st->dt == JUQCS_C64) mode_mma = JUQCS_MMA_FP32;
+  std::vector<FusedBlock> blocks;
+  plan_fused(st->n, k, g, &blocks);
+  for (const FusedBlock& b : blocks) {
+    if (juqcs_status rc = apply_fused_phys(st, (int)b.targets.size(), b.targets.data(),
+                                           b.m.data(), mode_mma))
+      return rc;
+    ++o->passes;
+  }
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_amplitudes_device(juqcs_state* st, const uint64_t* d_idx, size_t count,
+                                     double* d_out) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (count > 0 && (!d_idx || !d_out)) return fail(JUQCS_ERR_ARG, "null index or output");
+  int8_t phys[64];
+  for (int q = 0; q < 64; ++q) phys[q] = (int8_t)st->phys[q];
+  hipError_t e = launch_gather(st->dt, st->amps, st->scales, st->n, st->B, d_idx, count, phys,
+                               d_out, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "gather launch");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_amplitudes(juqcs_state* st, const uint64_t* idx, size_t count, double* out) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (count > 0 && (!idx || !out)) return fail(JUQCS_ERR_ARG, "null index or output");
+  for (size_t i = 0; i < count; ++i)
+    if (st->n < 64 && (idx[i] >> st->n) != 0) return fail(JUQCS_ERR_ARG, "index >= 2^n");
+  const size_t chunk = 1 << 18;
+  for (size_t off = 0; off < count; off += chunk) {
+    const size_t m = std::min(chunk, count - off);
+    char* d_idx = nullptr;
+    if (juqcs_status rc = upload(st, idx + off, m * sizeof(uint64_t), &d_idx)) return rc;
+    double* d_out = (double*)ring_alloc(st, m * 2 * sizeof(double));
+    if (!d_out) return fail(JUQCS_ERR_SIZE, "workspace too small");
+    if (juqcs_status rc = juqcs_amplitudes_device(st, (const uint64_t*)d_idx, m, d_out)) return rc;
+    hipError_t e = hipMemcpyAsync(out + 2 * off, d_out, m * 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, st->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
+    if (juqcs_status rc = sync(st)) return rc;
+  }
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_norm(juqcs_state* st, double* out) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!out) return fail(JUQCS_ERR_ARG, "null output");
+  double* partials = (double*)(st->work + kPartialOff);
+  double* res = (double*)(st->work + kResultOff);
+  hipError_t e = launch_norm(st->dt, st->amps, st->scales, st->n, st->B, partials, res, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "norm launch");
+  e = hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
+  if (juqcs_status rc = sync(st)) return rc;
+  if (!std::isfinite(*out)) return fail(JUQCS_ERR_NUMERIC, "norm is not finite");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_scale(juqcs_state* st, double factor) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!std::isfinite(factor)) return fail(JUQCS_ERR_NUMERIC, "non-finite factor");
+  if (st->dt == JUQCS_ENC2 && !(factor > 0)) return fail(JUQCS_ERR_ARG, "ENC2 scale factor must be > 0");
+  hipError_t e = launch_scale(st->dt, st->amps, st->scales, st->n, st->B, factor, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "scale launch");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_expectations(juqcs_state* st, double* out) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!out) return fail(JUQCS_ERR_ARG, "null output");
+  double* partials = (double*)(st->work + kPartialOff);
+  double* res = (double*)(st->work + kResultOff);
+  std::vector<double> sums(3 * st->n);
+  for (int q = 0; q < st->n; ++q) {
+    hipError_t e = launch_pauli(st->dt, st->amps, st->scales, st->n, st->B, st->phys[q], partials,
+                                res + 3 * q, st->stream);
+    if (e != hipSuccess) return hip_fail(e, "Pauli launch");
+  }
+  hipError_t e = hipMemcpyAsync(sums.data(), res, 3 * st->n * sizeof(double),
+                                hipMemcpyDeviceToHost, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
+  if (juqcs_status rc = sync(st)) return rc;
+  for (int i = 0; i < 3 * st->n; ++i) out[i] = 0.5 * (1.0 - sums[i]);
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_permute(juqcs_state* st, const int* new_phys) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!new_phys) return fail(JUQCS_ERR_ARG, "null permutation");
+  std::vector<char> seen(st->n, 0);
+  for (int q = 0; q < st->n; ++q) {
+    if (new_phys[q] < 0 || new_phys[q] >= st->n) return fail(JUQCS_ERR_QUBIT, "position out of range");
+    if (seen[new_phys[q]]) return fail(JUQCS_ERR_QUBIT, "not a permutation");
+    seen[new_phys[q]] = 1;
+  }
+  return move_layout(st, new_phys);
+}
+
+juqcs_status juqcs_state_canonicalize(juqcs_state* st) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  std::vector<int> id(st->n);
+  for (int q = 0; q < st->n; ++q) id[q] = q;
+  return move_layout(st, id.data());
+}
+
+juqcs_status juqcs_get_layout(const juqcs_state* st, int* phys) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!phys) return fail(JUQCS_ERR_ARG, "null output");
+  for (int q = 0; q < st->n; ++q) phys[q] = st->phys[q];
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_encode2(const void* d_src, juqcs_dtype src, uint64_t count, int block_bits,
+                           void* d_codes, void* d_scales, void* hip_stream) {
+  if (src != JUQCS_C128 && src != JUQCS_C64) return fail(JUQCS_ERR_DTYPE, "source must be C128 or C64");
+  if (block_bits < 3 || block_bits > 12) return fail(JUQCS_ERR_ARG, "block_bits must be in [3, 12]");
+  if (count > 0 && (!d_src || !d_codes || !d_scales)) return fail(JUQCS_ERR_ARG, "null buffer");
+  hipError_t e = launch_encode2(d_src, src, count, block_bits, d_codes, d_scales,
+                                (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "encode2 launch");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_decode2(const void* d_codes, const void* d_scales, uint64_t count,
+                           int block_bits, void* d_dst, juqcs_dtype dst, void* hip_stream) {
+  if (dst != JUQCS_C128 && dst != JUQCS_C64) return fail(JUQCS_ERR_DTYPE, "target must be C128 or C64");
+  if (block_bits < 3 || block_bits > 12) return fail(JUQCS_ERR_ARG, "block_bits must be in [3, 12]");
+  if (count > 0 && (!d_codes || !d_scales || !d_dst)) return fail(JUQCS_ERR_ARG, "null buffer");
+  hipError_t e = launch_decode2(d_codes, d_scales, count, block_bits, d_dst, dst,
+                                (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "decode2 launch");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_copy(void* d_dst, const void* d_src, size_t bytes, void* hip_stream) {
+  if (bytes == 0) return JUQCS_OK;
+  if (!d_dst || !d_src) return fail(JUQCS_ERR_ARG, "null buffer");
+  if ((bytes & 15) || ((uintptr_t)d_dst & 15) || ((uintptr_t)d_src & 15))
+    return fail(JUQCS_ERR_ARG, "copy needs 16-byte multiples and alignment");
+  hipError_t e = launch_copy(d_dst, d_src, bytes, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "copy launch");
+  return JUQCS_OK;
+}
+
+}  // extern "C"

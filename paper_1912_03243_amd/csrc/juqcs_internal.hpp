@@ -1,0 +1,167 @@
+// Internal declarations shared by the kernel translation units and the
+// host-side engine of libjuqcs_gpu.  Not installed; the public interface is
+// include/juqcs_gpu.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "juqcs_gpu.h"
+
+namespace juqcs {
+
+// ---------------------------------------------------------------------------
+// Complex arithmetic on interleaved (re, im) storage.  The alignment makes a
+// C128 amplitude one 16-byte load and a C64 amplitude one 8-byte load.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a*b
+template <typename T>
+__host__ __device__ inline cplx<T> cmad(cplx<T> a, cplx<T> b, cplx<T> acc) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+  return acc;
+}
+
+template <typename T>
+struct Mat2 {
+  cplx<T> m[4];  // row-major
+};
+template <typename T>
+struct Mat4 {
+  cplx<T> m[16];  // row-major, index b_q0 + 2 b_q1
+};
+
+// Insert a zero bit at position pos of x (bits >= pos move up by one).
+__host__ __device__ inline uint64_t insert_zero(uint64_t x, int pos) {
+  const uint64_t low = x & ((uint64_t(1) << pos) - 1);
+  return ((x >> pos) << (pos + 1)) | low;
+}
+
+// ---------------------------------------------------------------------------
+// Tile passes: 2^b amplitudes per workgroup, made of 2^H chunks of 2^L
+// contiguous amplitudes; local index bit j < L is physical bit j, local bit
+// L + i is physical bit hbits[i].  Ops act on local bits.
+// ---------------------------------------------------------------------------
+constexpr int kMaxGather = 10;  // gathered chunk bits of a tile pass
+constexpr int kHbitsCap = 12;   // fused blocks reuse the struct: 2k <= 12
+
+struct TileGeom {
+  int32_t n, L, H, b;
+  int32_t hbits[kHbitsCap];      // ascending physical positions (>= L)
+  int32_t block_bits;            // ENC2 only
+  int32_t pad;
+};
+
+enum TileOpKind : int32_t {
+  TOP_DENSE1 = 0,  // 2x2 on local bit a
+  TOP_DENSE2 = 1,  // 4x4 on local bits (a, b), index b_a + 2 b_b
+  TOP_DIAG2 = 2,   // phases d[b_a + 2 b_b] (b may equal -1: d[b_a])
+  TOP_PERM = 3,    // (reserved) local bit permutation
+  TOP_DENSEK = 4,  // 2^k x 2^k on k local bits (k <= 4), bits in bits[]
+};
+
+struct TileOp {
+  int32_t kind;
+  int32_t a, b;
+  int32_t k;
+  int32_t bits[4];
+  int64_t moff;  // offset of the matrix in the complex coefficient array
+};
+
+// A tile pass: geometry plus a range of ops.
+struct TilePass {
+  TileGeom g;
+  int32_t op_begin, op_count;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All asynchronous on stream.
+// Return hipSuccess or the launch error.
+// ---------------------------------------------------------------------------
+hipError_t launch_init(juqcs_dtype dt, void* amps, void* scales, int n,
+                       int block_bits, uint64_t idx, hipStream_t s);
+hipError_t launch_1q(juqcs_dtype dt, void* amps, int n, int t, int c,
+                     const cplx<double> u[4], hipStream_t s);
+hipError_t launch_diag(juqcs_dtype dt, void* amps, int n, uint64_t mask,
+                       cplx<double> phase, hipStream_t s);
+hipError_t launch_2q(juqcs_dtype dt, void* amps, int n, int q0, int q1,
+                     const cplx<double> m[16], hipStream_t s);
+hipError_t launch_norm(juqcs_dtype dt, const void* amps, const void* scales,
+                       int n, int block_bits, double* partials, double* out,
+                       hipStream_t s);
+hipError_t launch_gather(juqcs_dtype dt, const void* amps, const void* scales,
+                         int n, int block_bits, const uint64_t* idx,
+                         uint64_t count, const int8_t* phys, double* out,
+                         hipStream_t s);
+hipError_t launch_scale(juqcs_dtype dt, void* amps, void* scales, int n,
+                        int block_bits, double f, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales,
+                       const TileGeom& g, const TileOp* d_ops, int nops,
+                       const void* d_mats, hipStream_t s);
+int tile_max_bits(juqcs_dtype dt);
+
+hipError_t launch_fused(juqcs_dtype dt, void* amps, int n, int k,
+                        const int* targets, const void* d_mat, juqcs_mma mode,
+                        hipStream_t s);
+
+hipError_t launch_encode2(const void* src, juqcs_dtype sdt, uint64_t count,
+                          int block_bits, void* codes, void* scales,
+                          hipStream_t s);
+hipError_t launch_decode2(const void* codes, const void* scales,
+                          uint64_t count, int block_bits, void* dst,
+                          juqcs_dtype ddt, hipStream_t s);
+// Sums over the pairs of target bit t: (2 Re conj(a0) a1, 2 Im conj(a0) a1,
+// |a0|^2 - |a1|^2) = (<sigma^x_t>, <sigma^y_t>, <sigma^z_t>), FP64, fixed order.
+hipError_t launch_pauli(juqcs_dtype dt, const void* amps, const void* scales, int n,
+                        int block_bits, int t, double* partials, double* out3,
+                        hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Host-side planning (planner.cpp)
+// ---------------------------------------------------------------------------
+struct Gate {  // decoded gate: matrix on 1 or 2 qubits (physical positions)
+  int nq;
+  int q[2];
+  cplx<double> m[16];  // 2x2 (first 4) or 4x4, index b_q0 + 2 b_q1
+  bool diag;
+};
+
+bool decode_gate(const juqcs_gate& g, int n, Gate* out, std::string* err);
+
+struct TilePlan {
+  std::vector<TilePass> passes;
+  std::vector<TileOp> ops;
+  std::vector<cplx<double>> mats;
+  int64_t gates = 0;
+};
+
+// Plans tile passes for gates (physical qubits).  L, b: low contiguous bits
+// and total tile bits.  fixed_low: the low L bits are always tile bits.
+void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
+                TilePlan* plan);
+
+struct FusedBlock {
+  std::vector<int> targets;           // physical
+  std::vector<cplx<double>> m;        // 2^k x 2^k
+};
+void plan_fused(int n, int kmax, const std::vector<Gate>& gates,
+                std::vector<FusedBlock>* blocks);
+
+void set_error(const std::string& msg);
+
+}  // namespace juqcs

@@ -1,0 +1,310 @@
+// On-chip tile passes.  A workgroup gathers 2^b amplitudes -- 2^H chunks of
+// 2^L contiguous amplitudes, the chunk bits being chosen physical qubits --
+// into LDS, applies a program of gate ops whose qubits all lie in those b
+// bits, and writes the tile back: one HBM read + write per pass however many
+// gates the pass holds.  This is the single-GPU counterpart of the paper's
+// "minimise the data that must move" for gates on qubits that are not local
+// (Section 2), with LDS playing the role of node memory.
+//
+// Storage forms: C128 and C64 amplitudes, and the two-byte form (ENC2),
+// which is decoded into FP32 on load and re-encoded with fresh per-block
+// scales on store (Section 1, adaptive two-byte coding).
+#include "juqcs_internal.hpp"
+
+namespace juqcs {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+struct TileCfg;
+template <>
+struct TileCfg<double> {
+  static constexpr int kMaxBits = 13;  // 128 KiB of C128 amplitudes
+};
+template <>
+struct TileCfg<float> {
+  static constexpr int kMaxBits = 14;  // 128 KiB of C64 amplitudes
+};
+
+__device__ inline uint64_t tile_base(uint64_t tau, const TileGeom& g) {
+  uint64_t base = tau << g.L;
+  for (int j = 0; j < g.H; ++j) base = insert_zero(base, g.hbits[j]);
+  return base;
+}
+
+// ---------------------------------------------------------------- ops ----
+template <typename T>
+__device__ inline void op_dense1(cplx<T>* sh, int b, int a, const cplx<T>* __restrict__ m) {
+  const cplx<T> u0 = m[0], u1 = m[1], u2 = m[2], u3 = m[3];
+  const int npairs = 1 << (b - 1);
+  const int abit = 1 << a;
+  for (int p = threadIdx.x; p < npairs; p += kThreads) {
+    const int i0 = (int)insert_zero((uint64_t)p, a);
+    const cplx<T> x = sh[i0], y = sh[i0 | abit];
+    sh[i0] = cmad(u1, y, cmul(u0, x));
+    sh[i0 | abit] = cmad(u3, y, cmul(u2, x));
+  }
+}
+
+template <typename T>
+__device__ inline void op_dense2(cplx<T>* sh, int b, int a, int c, const cplx<T>* __restrict__ m) {
+  cplx<T> u[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) u[i] = m[i];
+  const int lo = a < c ? a : c, hi = a < c ? c : a;
+  const int ba = 1 << a, bc = 1 << c;
+  const int nq = 1 << (b - 2);
+  for (int p = threadIdx.x; p < nq; p += kThreads) {
+    const int i = (int)insert_zero(insert_zero((uint64_t)p, lo), hi);
+    const int idx[4] = {i, i | ba, i | bc, i | ba | bc};
+    cplx<T> v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = sh[idx[r]];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      cplx<T> acc = cmul(u[4 * r], v[0]);
+#pragma unroll
+      for (int s = 1; s < 4; ++s) acc = cmad(u[4 * r + s], v[s], acc);
+      sh[idx[r]] = acc;
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void op_diag2(cplx<T>* sh, int b, int a, int c, const cplx<T>* __restrict__ m) {
+  const cplx<T> d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
+  const int n = 1 << b;
+  for (int e = threadIdx.x; e < n; e += kThreads) {
+    const int r = ((e >> a) & 1) | (c >= 0 ? (((e >> c) & 1) << 1) : 0);
+    const cplx<T> d = r == 0 ? d0 : r == 1 ? d1 : r == 2 ? d2 : d3;
+    sh[e] = cmul(d, sh[e]);
+  }
+}
+
+// Dense 2^k x 2^k on k local bits (k <= 4).  bits[] in matrix order (bit j of
+// the row index <-> local bit bits[j]); zeros are inserted in ascending order.
+template <typename T, int K>
+__device__ inline void op_densek(cplx<T>* sh, int b, const int32_t* bits,
+                                 const cplx<T>* __restrict__ m) {
+  constexpr int D = 1 << K;
+  int sorted[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) sorted[j] = bits[j];
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = 0; j + 1 < K - i; ++j)
+      if (sorted[j] > sorted[j + 1]) {
+        const int t = sorted[j];
+        sorted[j] = sorted[j + 1];
+        sorted[j + 1] = t;
+      }
+  int off[D];
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    int o = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) o |= ((r >> j) & 1) << bits[j];
+    off[r] = o;
+  }
+  const int ng = 1 << (b - K);
+  for (int p = threadIdx.x; p < ng; p += kThreads) {
+    uint64_t i = (uint64_t)p;
+#pragma unroll
+    for (int j = 0; j < K; ++j) i = insert_zero(i, sorted[j]);
+    cplx<T> v[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) v[r] = sh[(int)i | off[r]];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      cplx<T> acc = cmul(m[r * D], v[0]);
+#pragma unroll
+      for (int s = 1; s < D; ++s) acc = cmad(m[r * D + s], v[s], acc);
+      sh[(int)i | off[r]] = acc;
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void run_ops(cplx<T>* sh, int b, const TileOp* __restrict__ ops, int nops,
+                               const cplx<T>* __restrict__ mats) {
+  for (int o = 0; o < nops; ++o) {
+    const TileOp op = ops[o];
+    const cplx<T>* m = mats + op.moff;
+    switch (op.kind) {
+      case TOP_DENSE1: op_dense1<T>(sh, b, op.a, m); break;
+      case TOP_DENSE2: op_dense2<T>(sh, b, op.a, op.b, m); break;
+      case TOP_DIAG2: op_diag2<T>(sh, b, op.a, op.b, m); break;
+      case TOP_DENSEK:
+        if (op.k == 3) op_densek<T, 3>(sh, b, op.bits, m);
+        else op_densek<T, 4>(sh, b, op.bits, m);
+        break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------- C128 / C64 -------
+template <typename T, int MAXB>
+__global__ __launch_bounds__(kThreads) void k_tile(cplx<T>* __restrict__ psi, TileGeom g,
+                                                   const TileOp* __restrict__ ops, int nops,
+                                                   const cplx<T>* __restrict__ mats) {
+  __shared__ cplx<T> sh[1 << MAXB];
+  __shared__ uint64_t choff[1 << kMaxGather];
+  const int b = g.b;
+  const int tile_amps = 1 << b;
+  const int nch = 1 << g.H;
+  for (int c = threadIdx.x; c < nch; c += kThreads) {
+    uint64_t o = 0;
+    for (int j = 0; j < g.H; ++j) o |= (uint64_t)((c >> j) & 1) << g.hbits[j];
+    choff[c] = o;
+  }
+  __syncthreads();
+  const uint64_t ntiles = uint64_t(1) << (g.n - b);
+  const int lmask = (1 << g.L) - 1;
+  for (uint64_t tau = blockIdx.x; tau < ntiles; tau += gridDim.x) {
+    const uint64_t base = tile_base(tau, g);
+    // load: 8 independent loads in flight per thread per round
+    for (int e0 = 0; e0 < tile_amps; e0 += kThreads * 8) {
+      cplx<T> v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + k * kThreads + threadIdx.x;
+        if (e < tile_amps) v[k] = psi[base + choff[e >> g.L] + (e & lmask)];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + k * kThreads + threadIdx.x;
+        if (e < tile_amps) sh[e] = v[k];
+      }
+    }
+    __syncthreads();
+    run_ops<T>(sh, b, ops, nops, mats);
+    for (int e = threadIdx.x; e < tile_amps; e += kThreads)
+      psi[base + choff[e >> g.L] + (e & lmask)] = sh[e];
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------- ENC2 -----
+// Codes are int8 (re, im) pairs; a thread moves 8 amplitudes (16 bytes of
+// codes) at a time, which always lie in one scale block (block_bits >= 3).
+constexpr float kTiny = 7.888609052210118e-31f;  // 2^-100
+
+__global__ __launch_bounds__(kThreads) void k_tile_enc2(int8_t* __restrict__ codes,
+                                                        float* __restrict__ scales, TileGeom g,
+                                                        const TileOp* __restrict__ ops, int nops,
+                                                        const cplx<float>* __restrict__ mats) {
+  constexpr int MAXB = TileCfg<float>::kMaxBits;
+  __shared__ cplx<float> sh[1 << MAXB];
+  __shared__ uint64_t choff[1 << kMaxGather];
+  __shared__ uint32_t bmax[1 << (MAXB - 3)];
+  const int b = g.b;
+  const int B = g.block_bits;
+  const int tile_amps = 1 << b;
+  const int ngroups = tile_amps >> 3;
+  const int nblk = tile_amps >> B;
+  const int nch = 1 << g.H;
+  for (int c = threadIdx.x; c < nch; c += kThreads) {
+    uint64_t o = 0;
+    for (int j = 0; j < g.H; ++j) o |= (uint64_t)((c >> j) & 1) << g.hbits[j];
+    choff[c] = o;
+  }
+  __syncthreads();
+  const uint64_t ntiles = uint64_t(1) << (g.n - b);
+  const int lmask = (1 << g.L) - 1;
+  for (uint64_t tau = blockIdx.x; tau < ntiles; tau += gridDim.x) {
+    const uint64_t base = tile_base(tau, g);
+    for (int q = threadIdx.x; q < nblk; q += kThreads) bmax[q] = 0u;
+    // load + decode
+    for (int gq = threadIdx.x; gq < ngroups; gq += kThreads) {
+      const int e = gq << 3;
+      const uint64_t gi = base + choff[e >> g.L] + (e & lmask);
+      const int4 raw = *reinterpret_cast<const int4*>(codes + 2 * gi);
+      const float d = scales[gi >> B] / 127.0f;
+      const int w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int8_t c0 = (int8_t)(w[j] & 0xff), c1 = (int8_t)((w[j] >> 8) & 0xff);
+        const int8_t c2 = (int8_t)((w[j] >> 16) & 0xff), c3 = (int8_t)((w[j] >> 24) & 0xff);
+        sh[e + 2 * j] = {(float)c0 * d, (float)c1 * d};
+        sh[e + 2 * j + 1] = {(float)c2 * d, (float)c3 * d};
+      }
+    }
+    __syncthreads();
+    run_ops<float>(sh, b, ops, nops, mats);
+    // per-block max of |component| (non-negative floats order like their bits)
+    for (int gq = threadIdx.x; gq < ngroups; gq += kThreads) {
+      const int e = gq << 3;
+      float mx = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const cplx<float> v = sh[e + j];
+        mx = fmaxf(mx, fmaxf(fabsf(v.re), fabsf(v.im)));
+      }
+      atomicMax(&bmax[e >> B], __float_as_uint(mx));
+    }
+    __syncthreads();
+    // encode + store
+    for (int gq = threadIdx.x; gq < ngroups; gq += kThreads) {
+      const int e = gq << 3;
+      const uint64_t gi = base + choff[e >> g.L] + (e & lmask);
+      const float s = __uint_as_float(bmax[e >> B]);
+      int w[4] = {0, 0, 0, 0};
+      if (s >= kTiny) {
+        const float r = 127.0f / s;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const cplx<float> v = sh[e + j];
+          const float qr = fminf(fmaxf(rintf(v.re * r), -127.0f), 127.0f);
+          const float qi = fminf(fmaxf(rintf(v.im * r), -127.0f), 127.0f);
+          const int pr = ((int)qr) & 0xff, pi = ((int)qi) & 0xff;
+          w[j >> 1] |= (pr | (pi << 8)) << (16 * (j & 1));
+        }
+      }
+      *reinterpret_cast<int4*>(codes + 2 * gi) = make_int4(w[0], w[1], w[2], w[3]);
+      if (((e & ((1 << B) - 1)) == 0)) scales[gi >> B] = (s >= kTiny) ? s : 0.0f;
+    }
+    __syncthreads();
+  }
+}
+
+inline unsigned tile_grid(uint64_t ntiles) {
+  return (unsigned)(ntiles < (1u << 20) ? ntiles : (1u << 20));
+}
+
+}  // namespace
+
+int tile_max_bits(juqcs_dtype dt) {
+  return dt == JUQCS_C128 ? TileCfg<double>::kMaxBits : TileCfg<float>::kMaxBits;
+}
+
+hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom& g,
+                       const TileOp* d_ops, int nops, const void* d_mats, hipStream_t s) {
+  const uint64_t ntiles = uint64_t(1) << (g.n - g.b);
+  const dim3 grid(tile_grid(ntiles)), block(kThreads);
+  if (dt == JUQCS_C128) {
+    if (g.b <= 12)
+      hipLaunchKernelGGL((k_tile<double, 12>), grid, block, 0, s, (cplx<double>*)amps, g, d_ops,
+                         nops, (const cplx<double>*)d_mats);
+    else
+      hipLaunchKernelGGL((k_tile<double, 13>), grid, block, 0, s, (cplx<double>*)amps, g, d_ops,
+                         nops, (const cplx<double>*)d_mats);
+  } else if (dt == JUQCS_C64) {
+    if (g.b <= 13)
+      hipLaunchKernelGGL((k_tile<float, 13>), grid, block, 0, s, (cplx<float>*)amps, g, d_ops,
+                         nops, (const cplx<float>*)d_mats);
+    else
+      hipLaunchKernelGGL((k_tile<float, 14>), grid, block, 0, s, (cplx<float>*)amps, g, d_ops,
+                         nops, (const cplx<float>*)d_mats);
+  } else {
+    hipLaunchKernelGGL(k_tile_enc2, grid, block, 0, s, (int8_t*)amps, (float*)scales, g, d_ops,
+                       nops, (const cplx<float>*)d_mats);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace juqcs

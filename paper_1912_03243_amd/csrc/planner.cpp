@@ -1,0 +1,379 @@
+// Host-side planning: gate decoding, tile-pass selection with on-chip fusion,
+// and dense k-qubit block fusion.  Pure C++ (no device code).
+//
+// Reordering rule used everywhere: a gate may move earlier past any gate that
+// acts on none of its qubits (gates on disjoint qubits commute), so every
+// plan computes the same product as the circuit order, up to rounding.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "juqcs_internal.hpp"
+
+namespace juqcs {
+
+namespace {
+
+using C = cplx<double>;
+
+inline C cx(double re, double im) { return C{re, im}; }
+inline C cadd(C a, C b) { return C{a.re + b.re, a.im + b.im}; }
+
+bool finite(C z) { return std::isfinite(z.re) && std::isfinite(z.im); }
+
+// Dense square matrix product out = a * b (dim x dim), row-major.
+void matmul(const C* a, const C* b, C* out, int dim) {
+  for (int i = 0; i < dim; ++i)
+    for (int j = 0; j < dim; ++j) {
+      C acc = cx(0, 0);
+      for (int k = 0; k < dim; ++k) acc = cmad(a[i * dim + k], b[k * dim + j], acc);
+      out[i * dim + j] = acc;
+    }
+}
+
+// Expand a gate given on qubits gq (size gk, matrix index sum_j b_{gq[j]} 2^j)
+// into the space of the qubit list space (size k): M[r][r'] =
+// G[sub(r)][sub(r')] if r and r' agree outside the gate's qubits.
+void expand(const C* g, const int* gq, int gk, const int* space, int k, C* out) {
+  int pos[6];
+  for (int j = 0; j < gk; ++j) {
+    pos[j] = -1;
+    for (int i = 0; i < k; ++i)
+      if (space[i] == gq[j]) pos[j] = i;
+  }
+  int gmask = 0;
+  for (int j = 0; j < gk; ++j) gmask |= 1 << pos[j];
+  const int dim = 1 << k, gd = 1 << gk;
+  for (int r = 0; r < dim; ++r)
+    for (int c = 0; c < dim; ++c) {
+      if ((r & ~gmask) != (c & ~gmask)) {
+        out[r * dim + c] = cx(0, 0);
+        continue;
+      }
+      int sr = 0, sc = 0;
+      for (int j = 0; j < gk; ++j) {
+        sr |= ((r >> pos[j]) & 1) << j;
+        sc |= ((c >> pos[j]) & 1) << j;
+      }
+      out[r * dim + c] = g[sr * gd + sc];
+    }
+}
+
+bool is_diag(const C* m, int dim) {
+  for (int r = 0; r < dim; ++r)
+    for (int c = 0; c < dim; ++c)
+      if (r != c && (m[r * dim + c].re != 0.0 || m[r * dim + c].im != 0.0)) return false;
+  return true;
+}
+
+// A fused cluster: qubit list + dense matrix over it (index sum_j b_{q[j]} 2^j).
+struct Cluster {
+  std::vector<int> q;
+  std::vector<C> m;
+};
+
+bool touches(const Cluster& c, const Gate& g) {
+  for (int x : c.q)
+    for (int j = 0; j < g.nq; ++j)
+      if (x == g.q[j]) return true;
+  return false;
+}
+
+// Union qubit list of a cluster and a gate, preserving the cluster's order.
+std::vector<int> union_q(const Cluster& c, const Gate& g) {
+  std::vector<int> u = c.q;
+  for (int j = 0; j < g.nq; ++j)
+    if (std::find(u.begin(), u.end(), g.q[j]) == u.end()) u.push_back(g.q[j]);
+  return u;
+}
+
+// Fold gate g into cluster c (g applied after c), re-expressed on the union.
+void merge_into(Cluster& c, const Gate& g) {
+  std::vector<int> u = union_q(c, g);
+  const int k = (int)u.size(), dim = 1 << k;
+  std::vector<C> old(dim * dim), gg(dim * dim), out(dim * dim);
+  if (c.q.empty()) {
+    for (int r = 0; r < dim; ++r)
+      for (int s = 0; s < dim; ++s) old[r * dim + s] = cx(r == s ? 1 : 0, 0);
+  } else {
+    expand(c.m.data(), c.q.data(), (int)c.q.size(), u.data(), k, old.data());
+  }
+  expand(g.m, g.q, g.nq, u.data(), k, gg.data());
+  matmul(gg.data(), old.data(), out.data(), dim);
+  c.q = u;
+  c.m = out;
+}
+
+// Greedy fusion: each gate joins the most recent cluster it may legally join
+// (no later cluster touches its qubits) whose union with the gate has at most
+// kmax qubits, preferring one that already shares a qubit; otherwise it opens
+// a new cluster.  The backward scan is bounded to keep planning linear.
+void fuse(const std::vector<Gate>& gates, const std::vector<int>& order, int kmax,
+          std::vector<Cluster>* out) {
+  constexpr int kScan = 64;
+  std::vector<Cluster>& cl = *out;
+  cl.clear();
+  for (int gi : order) {
+    const Gate& g = gates[gi];
+    int chosen = -1, fallback = -1;
+    for (int i = (int)cl.size() - 1; i >= 0 && (int)cl.size() - 1 - i < kScan; --i) {
+      const bool t = touches(cl[i], g);
+      const bool fits = (int)union_q(cl[i], g).size() <= kmax;
+      if (t) {
+        if (fits) chosen = i;
+        break;
+      }
+      if (fits && fallback < 0) fallback = i;
+    }
+    if (chosen < 0) chosen = fallback;
+    if (chosen < 0) {
+      cl.push_back(Cluster{});
+      chosen = (int)cl.size() - 1;
+    }
+    merge_into(cl[chosen], g);
+  }
+}
+
+}  // namespace
+
+bool decode_gate(const juqcs_gate& g, int n, Gate* out, std::string* err) {
+  Gate r{};
+  const double s2 = 1.0 / std::sqrt(2.0);
+  auto set2 = [&](C a, C b, C c, C d) {
+    r.nq = 1;
+    r.m[0] = a;
+    r.m[1] = b;
+    r.m[2] = c;
+    r.m[3] = d;
+  };
+  auto check_q = [&](int q) { return q >= 0 && q < n; };
+  r.q[0] = g.q0;
+  r.q[1] = g.q1;
+  switch (g.op) {
+    case JUQCS_OP_H: set2(cx(s2, 0), cx(s2, 0), cx(s2, 0), cx(-s2, 0)); break;
+    case JUQCS_OP_X: set2(cx(0, 0), cx(1, 0), cx(1, 0), cx(0, 0)); break;
+    case JUQCS_OP_Y: set2(cx(0, 0), cx(0, -1), cx(0, 1), cx(0, 0)); break;
+    case JUQCS_OP_Z: set2(cx(1, 0), cx(0, 0), cx(0, 0), cx(-1, 0)); break;
+    case JUQCS_OP_S: set2(cx(1, 0), cx(0, 0), cx(0, 0), cx(0, 1)); break;
+    case JUQCS_OP_T:
+      set2(cx(1, 0), cx(0, 0), cx(0, 0), cx(std::cos(M_PI / 4), std::sin(M_PI / 4)));
+      break;
+    case JUQCS_OP_U:
+      set2(cx(g.u[0], g.u[1]), cx(g.u[2], g.u[3]), cx(g.u[4], g.u[5]), cx(g.u[6], g.u[7]));
+      break;
+    case JUQCS_OP_CNOT:
+    case JUQCS_OP_CZ:
+    case JUQCS_OP_CP: {
+      r.nq = 2;
+      for (int i = 0; i < 16; ++i) r.m[i] = cx(0, 0);
+      if (g.op == JUQCS_OP_CNOT) {  // index b_control + 2 b_target
+        r.m[0 * 4 + 0] = cx(1, 0);
+        r.m[2 * 4 + 2] = cx(1, 0);
+        r.m[1 * 4 + 3] = cx(1, 0);
+        r.m[3 * 4 + 1] = cx(1, 0);
+      } else {
+        r.m[0] = r.m[5] = r.m[10] = cx(1, 0);
+        r.m[15] = g.op == JUQCS_OP_CZ ? cx(-1, 0) : cx(std::cos(g.theta), std::sin(g.theta));
+      }
+      break;
+    }
+    default:
+      *err = "unknown gate op " + std::to_string(g.op);
+      return false;
+  }
+  if (!check_q(r.q[0]) || (r.nq == 2 && !check_q(r.q[1]))) {
+    *err = "gate qubit out of range";
+    return false;
+  }
+  if (r.nq == 2 && r.q[0] == r.q[1]) {
+    *err = "two-qubit gate with equal qubits";
+    return false;
+  }
+  if (r.nq == 1) r.q[1] = -1;
+  const int dim = 1 << r.nq;
+  for (int i = 0; i < dim * dim; ++i)
+    if (!finite(r.m[i])) {
+      *err = "non-finite matrix entry";
+      return false;
+    }
+  r.diag = is_diag(r.m, dim);
+  *out = r;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Tile planning
+// ---------------------------------------------------------------------------
+namespace {
+
+// Number of gates at the front of `rem` absorbable by the tile set.
+int absorb_count(const std::vector<Gate>& gates, const std::vector<int>& rem,
+                 const std::vector<char>& in_tile, int ntile) {
+  std::vector<char> blocked(in_tile.size(), 0);
+  int nblocked = 0, cnt = 0;
+  for (int gi : rem) {
+    const Gate& g = gates[gi];
+    bool ok = true;
+    for (int j = 0; j < g.nq; ++j)
+      if (!in_tile[g.q[j]] || blocked[g.q[j]]) ok = false;
+    if (ok) {
+      ++cnt;
+    } else {
+      for (int j = 0; j < g.nq; ++j)
+        if (!blocked[g.q[j]]) {
+          blocked[g.q[j]] = 1;
+          if (in_tile[g.q[j]]) ++nblocked;
+        }
+      if (nblocked >= ntile) break;
+    }
+  }
+  return cnt;
+}
+
+void emit_ops(const std::vector<Cluster>& cl, const TileGeom& geom, TilePlan* plan) {
+  auto local = [&](int p) {
+    if (p < geom.L) return p;
+    for (int j = 0; j < geom.H; ++j)
+      if (geom.hbits[j] == p) return geom.L + j;
+    return -1;
+  };
+  for (const Cluster& c : cl) {
+    TileOp op{};
+    const int k = (int)c.q.size();
+    const int dim = 1 << k;
+    op.k = k;
+    op.moff = (int64_t)plan->mats.size();
+    if (is_diag(c.m.data(), dim) && k <= 2) {
+      op.kind = TOP_DIAG2;
+      op.a = local(c.q[0]);
+      op.b = k == 2 ? local(c.q[1]) : -1;
+      for (int r = 0; r < 4; ++r) plan->mats.push_back(c.m[(r % dim) * dim + (r % dim)]);
+    } else if (k == 1) {
+      op.kind = TOP_DENSE1;
+      op.a = local(c.q[0]);
+      op.b = -1;
+      for (int i = 0; i < 4; ++i) plan->mats.push_back(c.m[i]);
+    } else if (k == 2) {
+      op.kind = TOP_DENSE2;
+      op.a = local(c.q[0]);
+      op.b = local(c.q[1]);
+      for (int i = 0; i < 16; ++i) plan->mats.push_back(c.m[i]);
+    } else {
+      op.kind = TOP_DENSEK;
+      for (int j = 0; j < k; ++j) op.bits[j] = local(c.q[j]);
+      for (int i = 0; i < dim * dim; ++i) plan->mats.push_back(c.m[i]);
+    }
+    plan->ops.push_back(op);
+  }
+}
+
+}  // namespace
+
+void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
+                TilePlan* plan) {
+  (void)block_bits;
+  plan->passes.clear();
+  plan->ops.clear();
+  plan->mats.clear();
+  plan->gates = (int64_t)gates.size();
+  if (n <= b) {
+    L = n;
+    b = n;
+  }
+  const int H = b - L;
+  std::vector<int> rem(gates.size());
+  for (size_t i = 0; i < gates.size(); ++i) rem[i] = (int)i;
+  constexpr int kCandidates = 24;
+  const int kin = 2;  // on-chip fusion width
+  while (!rem.empty()) {
+    std::vector<char> in_tile(n, 0);
+    for (int q = 0; q < L; ++q) in_tile[q] = 1;
+    std::vector<int> chosen;
+    if (H > 0) {
+      std::vector<int> cand;
+      std::vector<char> seen(n, 0);
+      for (int gi : rem) {
+        const Gate& g = gates[gi];
+        for (int j = 0; j < g.nq; ++j) {
+          const int q = g.q[j];
+          if (q >= L && !seen[q]) {
+            seen[q] = 1;
+            cand.push_back(q);
+          }
+        }
+        if ((int)cand.size() >= kCandidates) break;
+      }
+      // greedy: add the candidate that lets the most gates through
+      for (int step = 0; step < H; ++step) {
+        int best = -1, bc = -1;
+        for (int c : cand) {
+          if (in_tile[c]) continue;
+          in_tile[c] = 1;
+          const int v = absorb_count(gates, rem, in_tile, L + (int)chosen.size() + 1);
+          in_tile[c] = 0;
+          if (v > bc) {
+            bc = v;
+            best = c;
+          }
+        }
+        if (best < 0) {
+          // fewer candidates than slots: fill with unused high bits
+          for (int q = n - 1; q >= L; --q)
+            if (!in_tile[q]) {
+              best = q;
+              break;
+            }
+        }
+        in_tile[best] = 1;
+        chosen.push_back(best);
+      }
+    }
+    std::sort(chosen.begin(), chosen.end());
+    // absorb
+    std::vector<int> taken, keep;
+    std::vector<char> blocked(n, 0);
+    for (int gi : rem) {
+      const Gate& g = gates[gi];
+      bool ok = true;
+      for (int j = 0; j < g.nq; ++j)
+        if (!in_tile[g.q[j]] || blocked[g.q[j]]) ok = false;
+      if (ok) {
+        taken.push_back(gi);
+      } else {
+        keep.push_back(gi);
+        for (int j = 0; j < g.nq; ++j) blocked[g.q[j]] = 1;
+      }
+    }
+    TilePass pass{};
+    pass.g.n = n;
+    pass.g.L = L;
+    pass.g.H = H;
+    pass.g.b = b;
+    pass.g.block_bits = block_bits;
+    for (int j = 0; j < H; ++j) pass.g.hbits[j] = chosen[j];
+    std::vector<Cluster> cl;
+    fuse(gates, taken, kin, &cl);
+    pass.op_begin = (int32_t)plan->ops.size();
+    emit_ops(cl, pass.g, plan);
+    pass.op_count = (int32_t)plan->ops.size() - pass.op_begin;
+    plan->passes.push_back(pass);
+    rem.swap(keep);
+  }
+}
+
+void plan_fused(int n, int kmax, const std::vector<Gate>& gates, std::vector<FusedBlock>* blocks) {
+  (void)n;
+  std::vector<int> order(gates.size());
+  for (size_t i = 0; i < gates.size(); ++i) order[i] = (int)i;
+  std::vector<Cluster> cl;
+  fuse(gates, order, kmax, &cl);
+  blocks->clear();
+  for (Cluster& c : cl) {
+    FusedBlock fb;
+    fb.targets = c.q;
+    fb.m = c.m;
+    blocks->push_back(std::move(fb));
+  }
+}
+
+}  // namespace juqcs

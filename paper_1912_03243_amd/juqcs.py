@@ -1,0 +1,368 @@
+"""ctypes binding of libjuqcs_gpu (C-ABI declared in include/juqcs_gpu.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  PyTorch provides device memory and the HIP stream.
+The module-level functions carry the C names; ``State`` and ``Batch`` wrap a
+handle plus the torch buffers it borrows.
+
+Importing this module loads the library and raises ImportError if it has
+not been built (``python -m paper_1912_03243_amd.build``): there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+from .workloads import GATE_DTYPE
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjuqcs_gpu.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with: python -m paper_1912_03243_amd.build")
+_lib = ct.CDLL(LIB_PATH)
+
+# ---- enums (include/juqcs_gpu.h) -------------------------------------------
+OK, ERR_ARG, ERR_QUBIT, ERR_DTYPE, ERR_SIZE, ERR_HIP, ERR_UNSUPPORTED, ERR_NUMERIC = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+C128, C64, ENC2 = 0, 1, 2
+DTYPES = {"c128": C128, "c64": C64, "enc2": ENC2}
+MMA_FP64, MMA_FP32, MMA_BF16, MMA_BF16X3, MMA_AUTO = 0, 1, 2, 3, 4
+MMAS = {"fp64": MMA_FP64, "fp32": MMA_FP32, "bf16": MMA_BF16, "bf16x3": MMA_BF16X3,
+        "auto": MMA_AUTO}
+PLAN_PLAIN, PLAN_TILE, PLAN_FUSED, PLAN_AUTO = 0, 1, 2, 3
+PLANS = {"plain": PLAN_PLAIN, "tile": PLAN_TILE, "fused": PLAN_FUSED, "auto": PLAN_AUTO}
+
+
+class PlanOpts(ct.Structure):
+    _fields_ = [("mode", ct.c_int32), ("fuse_k", ct.c_int32), ("mma", ct.c_int32),
+                ("tile_bits", ct.c_int32), ("low_bits", ct.c_int32),
+                ("reserved", ct.c_int32 * 3), ("passes", ct.c_int64), ("gates", ct.c_int64)]
+
+
+class JuqcsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.juqcs_last_error().decode()
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+_P = ct.c_void_p
+_I = ct.c_int
+_S = ct.c_size_t
+_U64 = ct.c_uint64
+_DP = ct.POINTER(ct.c_double)
+
+_SIGS = {
+    "juqcs_state_bytes": [_I, _I, _I, ct.POINTER(_S), ct.POINTER(_S), ct.POINTER(_S)],
+    "juqcs_state_create": [ct.POINTER(_P), _I, _I, _I, _P, _S, _P, _S, _P, _S, _P],
+    "juqcs_state_destroy": [_P],
+    "juqcs_state_init": [_P, _U64],
+    "juqcs_state_set_stream": [_P, _P],
+    "juqcs_apply_1q": [_P, _I, _DP],
+    "juqcs_apply_controlled": [_P, _I, _I, _DP],
+    "juqcs_apply_2q": [_P, _I, _I, _DP],
+    "juqcs_apply_fused_k": [_P, _I, ct.POINTER(_I), _DP, _I],
+    "juqcs_run_circuit": [_P, _P, _S, ct.POINTER(PlanOpts)],
+    "juqcs_amplitudes": [_P, ct.POINTER(_U64), _S, _DP],
+    "juqcs_amplitudes_device": [_P, _P, _S, _P],
+    "juqcs_norm": [_P, _DP],
+    "juqcs_scale": [_P, ct.c_double],
+    "juqcs_expectations": [_P, _DP],
+    "juqcs_permute": [_P, ct.POINTER(_I)],
+    "juqcs_state_canonicalize": [_P],
+    "juqcs_get_layout": [_P, ct.POINTER(_I)],
+    "juqcs_encode2": [_P, _I, _U64, _I, _P, _P, _P],
+    "juqcs_decode2": [_P, _P, _U64, _I, _P, _I, _P],
+    "juqcs_batch_create": [ct.POINTER(_P), _I, ct.POINTER(_I), _P, ct.POINTER(ct.c_int64), _P,
+                           ct.POINTER(_U64), ct.POINTER(PlanOpts)],
+    "juqcs_batch_run": [_P, _P],
+    "juqcs_batch_stats": [_P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
+                          ct.POINTER(ct.c_int64)],
+    "juqcs_batch_destroy": [_P],
+    "juqcs_branch_amplitudes": [_I, _P, _S, ct.POINTER(ct.c_uint8), ct.POINTER(_U64), _S, _I,
+                                _DP, _P],
+    "juqcs_copy": [_P, _P, _S, _P],
+}
+EXPORTED = sorted(list(_SIGS) + ["juqcs_last_error", "juqcs_version"])
+
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ct.c_int
+_lib.juqcs_last_error.restype = ct.c_char_p
+_lib.juqcs_last_error.argtypes = []
+_lib.juqcs_version.restype = ct.c_char_p
+_lib.juqcs_version.argtypes = []
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise JuqcsError(rc, where)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def _cplx_to_f64(m) -> np.ndarray:
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    return np.ascontiguousarray(np.stack([m.real, m.imag], axis=-1).reshape(-1))
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _gates(gates) -> np.ndarray:
+    g = np.ascontiguousarray(gates)
+    if g.dtype != GATE_DTYPE:
+        raise TypeError("gate records must use workloads.GATE_DTYPE")
+    return g
+
+
+# ---- thin wrappers with the C names ------------------------------------------
+def juqcs_version() -> str:
+    return _lib.juqcs_version().decode()
+
+
+def juqcs_last_error() -> str:
+    return _lib.juqcs_last_error().decode()
+
+
+def juqcs_state_bytes(n: int, dtype: int, block_bits: int = 0):
+    a, s, w = _S(), _S(), _S()
+    _check(_lib.juqcs_state_bytes(n, dtype, block_bits, ct.byref(a), ct.byref(s), ct.byref(w)),
+           "juqcs_state_bytes")
+    return a.value, s.value, w.value
+
+
+def juqcs_encode2(src, src_dtype: int, count: int, block_bits: int, codes, scales, stream=None):
+    _check(_lib.juqcs_encode2(src.data_ptr(), src_dtype, count, block_bits, codes.data_ptr(),
+                              scales.data_ptr(), _stream_handle(stream)), "juqcs_encode2")
+
+
+def juqcs_decode2(codes, scales, count: int, block_bits: int, dst, dst_dtype: int, stream=None):
+    _check(_lib.juqcs_decode2(codes.data_ptr(), scales.data_ptr(), count, block_bits,
+                              dst.data_ptr(), dst_dtype, _stream_handle(stream)), "juqcs_decode2")
+
+
+def juqcs_copy(dst, src, nbytes: int, stream=None):
+    _check(_lib.juqcs_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream_handle(stream)),
+           "juqcs_copy")
+
+
+def juqcs_branch_amplitudes(n: int, gates, side, z, group_size: int = 0, stream=None) -> np.ndarray:
+    g = _gates(gates)
+    side = np.ascontiguousarray(side, dtype=np.uint8)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    out = np.empty(2 * z.size, dtype=np.float64)
+    _check(_lib.juqcs_branch_amplitudes(n, g.ctypes.data, g.size,
+                                        side.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                                        z.ctypes.data_as(ct.POINTER(_U64)), z.size, group_size,
+                                        _dptr(out), _stream_handle(stream)),
+           "juqcs_branch_amplitudes")
+    return out[0::2] + 1j * out[1::2]
+
+
+# ---- State --------------------------------------------------------------------
+class State:
+    """A state vector in torch-owned device memory plus its library handle."""
+
+    def __init__(self, n: int, dtype: str = "c128", block_bits: int = 0, device="cuda",
+                 stream=None, amps=None):
+        import torch
+        self.n = n
+        self.dtype_name = dtype
+        self.dtype = DTYPES[dtype]
+        self.block_bits = (block_bits or 8) if self.dtype == ENC2 else 0
+        ab, sb, wb = juqcs_state_bytes(n, self.dtype, block_bits)
+        self.amps = amps if amps is not None else torch.empty(ab, dtype=torch.uint8, device=device)
+        self.scales = torch.empty(max(sb, 16), dtype=torch.uint8, device=device) if sb else None
+        self.work = torch.empty(wb, dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = _P()
+        _check(_lib.juqcs_state_create(
+            ct.byref(h), n, self.dtype, block_bits, self.amps.data_ptr(),
+            self.amps.numel() * self.amps.element_size(),
+            self.scales.data_ptr() if self.scales is not None else None, sb,
+            self.work.data_ptr(), wb, _stream_handle(stream)), "juqcs_state_create")
+        self.h = h
+
+    # lifetime
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.juqcs_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # gates
+    def init(self, basis_index: int = 0):
+        _check(_lib.juqcs_state_init(self.h, basis_index), "juqcs_state_init")
+        return self
+
+    def apply_1q(self, t: int, u):
+        _check(_lib.juqcs_apply_1q(self.h, t, _dptr(_cplx_to_f64(u))), "juqcs_apply_1q")
+
+    def apply_controlled(self, c: int, t: int, u):
+        _check(_lib.juqcs_apply_controlled(self.h, c, t, _dptr(_cplx_to_f64(u))),
+               "juqcs_apply_controlled")
+
+    def apply_2q(self, q0: int, q1: int, m):
+        _check(_lib.juqcs_apply_2q(self.h, q0, q1, _dptr(_cplx_to_f64(m))), "juqcs_apply_2q")
+
+    def apply_fused(self, targets, m, mode: str = "auto"):
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        arr = (ct.c_int * t.size)(*t.tolist())
+        _check(_lib.juqcs_apply_fused_k(self.h, t.size, arr, _dptr(_cplx_to_f64(m)), MMAS[mode]),
+               "juqcs_apply_fused_k")
+
+    def run(self, gates, mode: str = "auto", fuse_k: int = 0, mma: str = "auto",
+            tile_bits: int = 0, low_bits: int = 0) -> PlanOpts:
+        g = _gates(gates)
+        o = PlanOpts(mode=PLANS[mode], fuse_k=fuse_k, mma=MMAS[mma], tile_bits=tile_bits,
+                     low_bits=low_bits)
+        _check(_lib.juqcs_run_circuit(self.h, g.ctypes.data, g.size, ct.byref(o)),
+               "juqcs_run_circuit")
+        return o
+
+    # read-out
+    def amplitudes(self, idx) -> np.ndarray:
+        z = np.ascontiguousarray(idx, dtype=np.uint64)
+        out = np.empty(2 * z.size, dtype=np.float64)
+        _check(_lib.juqcs_amplitudes(self.h, z.ctypes.data_as(ct.POINTER(_U64)), z.size,
+                                     _dptr(out)), "juqcs_amplitudes")
+        return out[0::2] + 1j * out[1::2]
+
+    def amplitudes_device(self, d_idx, d_out):
+        _check(_lib.juqcs_amplitudes_device(self.h, d_idx.data_ptr(), d_idx.numel(),
+                                            d_out.data_ptr()), "juqcs_amplitudes_device")
+
+    def norm(self) -> float:
+        out = np.zeros(1)
+        _check(_lib.juqcs_norm(self.h, _dptr(out)), "juqcs_norm")
+        return float(out[0])
+
+    def scale(self, f: float):
+        _check(_lib.juqcs_scale(self.h, f), "juqcs_scale")
+
+    def expectations(self) -> np.ndarray:
+        out = np.zeros(3 * self.n)
+        _check(_lib.juqcs_expectations(self.h, _dptr(out)), "juqcs_expectations")
+        return out.reshape(self.n, 3)
+
+    def permute(self, new_phys):
+        p = (ct.c_int * self.n)(*[int(x) for x in new_phys])
+        _check(_lib.juqcs_permute(self.h, p), "juqcs_permute")
+
+    def canonicalize(self):
+        _check(_lib.juqcs_state_canonicalize(self.h), "juqcs_state_canonicalize")
+
+    def layout(self):
+        p = (ct.c_int * self.n)()
+        _check(_lib.juqcs_get_layout(self.h, p), "juqcs_get_layout")
+        return list(p)
+
+    def state_vector(self) -> np.ndarray:
+        """Whole state in logical order as complex128 (host copy)."""
+        import torch
+        self.canonicalize()
+        if self.dtype == C128:
+            t = self.amps[: (1 << self.n) * 16].view(torch.float64)
+        elif self.dtype == C64:
+            t = self.amps[: (1 << self.n) * 8].view(torch.float32)
+        else:
+            t = torch.empty(2 << self.n, dtype=torch.float32, device=self.amps.device)
+            juqcs_decode2(self.amps, self.scales, 1 << self.n, self.block_bits, t, C64,
+                          self.stream)
+        torch.cuda.synchronize()
+        a = t.cpu().numpy().astype(np.float64)
+        return a[0::2] + 1j * a[1::2]
+
+    def raw_codes(self):
+        """(codes int8 (2^n, 2), scales float32) of an ENC2 state (host copies)."""
+        import torch
+        torch.cuda.synchronize()
+        codes = self.amps[: 2 << self.n].cpu().numpy().view(np.int8).reshape(-1, 2)
+        nb = (1 << self.n) >> self.block_bits
+        scales = self.scales[: 4 * nb].cpu().numpy().view(np.float32)
+        return codes, scales
+
+
+# ---- Batch --------------------------------------------------------------------
+class Batch:
+    """Many independent C64 circuits executed by one persistent launch."""
+
+    def __init__(self, circuits, device="cuda", states=None, tile_bits: int = 0,
+                 low_bits: int = 0):
+        import torch
+        ns = np.array([n for n, _ in circuits], dtype=np.int32)
+        offs = np.zeros(len(circuits) + 1, dtype=np.int64)
+        for i, (_, g) in enumerate(circuits):
+            offs[i + 1] = offs[i] + len(g)
+        allg = np.ascontiguousarray(np.concatenate([g for _, g in circuits])) if len(circuits) \
+            else np.zeros(0, dtype=GATE_DTYPE)
+        sizes = (8 << ns.astype(np.int64))
+        soff = np.zeros(len(circuits), dtype=np.uint64)
+        run = 0
+        for i, s in enumerate(sizes):
+            soff[i] = run
+            run += int((s + 255) // 256 * 256)
+        self.n = ns
+        self.state_offset = soff
+        self.states = states if states is not None else torch.empty(max(run, 256), dtype=torch.uint8,
+                                                                     device=device)
+        o = PlanOpts(mode=PLAN_TILE, tile_bits=tile_bits, low_bits=low_bits)
+        h = _P()
+        _check(_lib.juqcs_batch_create(ct.byref(h), len(circuits),
+                                       ns.ctypes.data_as(ct.POINTER(_I)), allg.ctypes.data,
+                                       offs.ctypes.data_as(ct.POINTER(ct.c_int64)),
+                                       self.states.data_ptr(),
+                                       soff.ctypes.data_as(ct.POINTER(_U64)), ct.byref(o)),
+               "juqcs_batch_create")
+        self.h = h
+
+    def run(self, stream=None):
+        _check(_lib.juqcs_batch_run(self.h, _stream_handle(stream)), "juqcs_batch_run")
+
+    def stats(self):
+        a, b, c = ct.c_int64(), ct.c_int64(), ct.c_int64()
+        _check(_lib.juqcs_batch_stats(self.h, ct.byref(a), ct.byref(b), ct.byref(c)),
+               "juqcs_batch_stats")
+        return {"tasks": a.value, "gate_apps": b.value, "passes": c.value}
+
+    def state_vector(self, i: int) -> np.ndarray:
+        import torch
+        torch.cuda.synchronize()
+        n = int(self.n[i])
+        off = int(self.state_offset[i])
+        a = self.states[off: off + (8 << n)].view(torch.float32).cpu().numpy().astype(np.float64)
+        return a[0::2] + 1j * a[1::2]
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.juqcs_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
