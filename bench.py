@@ -1,0 +1,249 @@
+"""Benchmark: one step = the whole hot path on the 30-qubit layered circuit.
+
+Workload (the metric's configuration): n = 30 qubits, complex128 state
+(16 GiB), 20 layers of Haar-random U(2) on every qubit followed by CZ on
+alternating nearest-neighbour bricks (890 gates, seed 2), then the
+amplitudes of 4096 seeded bitstrings (seed 1002) and the FP64 norm.
+
+A step = init |0...0> + every gate (planner mode, default "tile": on-chip
+tile passes) + amplitude read-out + norm, inputs resident in HBM.  The value
+is gate-updates/s = 890 / step time (a gate-update is one logical gate
+applied to all 2^30 amplitudes).  The roofline figure is for the dominant
+kernel (the tile pass): algorithmic bytes per pass (read + write of the whole
+state, 32 GiB) divided by its device duration from HIP events recorded on the
+state's stream around every pass of the timed steps.
+
+usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--mode tile]
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gate-updates/s and achieved HBM GB/s per gate pass (fraction of peak), 1 GPU"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n, gates, budget_s):
+    """Times the FP64 CPU oracle on the same circuit at full size: the first
+    gates of the circuit on the 2^30-amplitude state, until the budget is
+    spent.  numpy's element-wise kernels run on one thread."""
+    import numpy as np
+    from oracle import statevector as sv
+    t0 = time.perf_counter()
+    psi = sv.init_state(n)
+    t_init = time.perf_counter() - t0
+    done = 0
+    t1 = time.perf_counter()
+    for rec in gates:
+        sv.apply_record(psi, n, rec)
+        done += 1
+        if time.perf_counter() - t1 > budget_s:
+            break
+    el = time.perf_counter() - t1
+    del psi
+    return {"value": done / el, "unit": "gate-updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {done} of {len(gates)} gates of the same n={n} circuit on the "
+                       f"full FP64 state (numpy, one thread), {el:.1f} s; init {t_init:.1f} s; "
+                       f"host: {cpu_model()}, {os.cpu_count()} logical CPUs")}
+
+
+def traffic_for(kernel_src):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/), used
+    only while the kernel source is unchanged since the measurement."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_1912_03243_amd", "csrc", kernel_src), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+        if rec.get("source_sha256") == h:
+            return rec.get("traffic_bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="tile", choices=["tile", "plain", "fused"])
+    ap.add_argument("--compare", type=int, default=1,
+                    help="also time one step of the other planner modes")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run only the reference copy kernel (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1912_03243_amd import juqcs
+    from paper_1912_03243_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    if args.copy_calib:
+        nbytes = 8 << 30
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            juqcs.juqcs_copy(dst, src, nbytes, stream)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 launches of {nbytes} bytes")
+        return
+
+    n, gates, z = W.workload_brick30()
+    zd = torch.from_numpy(z.astype(np.int64)).to(dev)
+    outd = torch.empty(2 * z.size, dtype=torch.float64, device=dev)
+    log(f"workload: n={n}, {len(gates)} gates, {z.size} bitstrings, mode={args.mode}")
+
+    st = juqcs.State(n, "c128", device=dev, stream=stream)
+
+    def step(mode, profile):
+        st.init(0)
+        o = st.run(gates, mode=mode, profile=profile, fuse_k=5)
+        st.amplitudes_device(zd, outd)
+        nrm = st.norm()
+        return o, nrm
+
+    for i in range(args.warmup):
+        step(args.mode, True)
+        log(f"warmup step {i} done")
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kernel_ms = 0.0
+    kbytes = 0.0
+    passes = 0
+    torch.cuda.synchronize()
+    start.record(stream)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        o, nrm = step(args.mode, True)
+        kernel_ms += o.kernel_ms
+        kbytes += o.bytes
+        passes += o.passes
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop) / args.steps
+    log(f"timed {args.steps} steps: {ms:.2f} ms/step (host wall {1e3 * wall / args.steps:.2f})")
+
+    amps = outd.cpu().numpy()
+    amps = amps[0::2] + 1j * amps[1::2]
+    check = {"norm_minus_1": nrm - 1.0}
+    try:
+        # stored FP64 amplitudes of this circuit (written by tests/golden/make_golden.py)
+        rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "brick30_amplitudes.txt"),
+                          dtype=np.float64, comments="#", ndmin=2)
+        gz = rows[:, 0].astype(np.uint64)
+        ga = rows[:, 1] + 1j * rows[:, 2]
+        assert np.array_equal(gz, z[: gz.size])
+        check["oracle_max_abs_err"] = float(np.max(np.abs(amps[: gz.size] - ga)))
+        check["oracle_points"] = int(gz.size)
+    except OSError as e:
+        log(f"no stored oracle amplitudes: {e}")
+
+    ngates = len(gates)
+    value = ngates / (ms / 1e3)
+    pass_ms = kernel_ms / max(passes, 1)
+    achieved = (kbytes / max(passes, 1)) / (pass_ms / 1e3) / 1e9
+    per_launch = kbytes / max(passes, 1)
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "gate-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "brick30: n=30 complex128 state (16 GiB), 20 layers of Haar U(2) "
+                               "on every qubit + brick CZ (890 gates, seed 2); init, all gates, "
+                               "4096 amplitudes (seed 1002) and the norm per step",
+                   "n": n, "gates": ngates, "bitstrings": int(z.size), "mode": args.mode,
+                   "passes_per_step": passes // args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic_for("k_tile.hip") if args.mode == "tile" else None,
+                     "kernel": "k_tile<double,12>" if args.mode == "tile" else args.mode,
+                     "bytes_per_launch": per_launch, "avg_launch_ms": pass_ms},
+        "amp_updates_per_s": value * float(1 << n),
+        "check": check,
+    }
+
+    # reference copy kernel: the practical streaming ceiling on this GPU
+    nb = 8 << 30
+    buf = torch.empty(nb, dtype=torch.uint8, device=dev)
+    juqcs.juqcs_copy(buf, st.amps, nb, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        juqcs.juqcs_copy(buf, st.amps, nb, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 3 * 2 * nb / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del buf
+    result["copy_kernel_GBps"] = copy_gbps
+    result["roofline"]["frac_of_copy"] = achieved / copy_gbps
+
+    if args.compare:
+        for mode in ("plain", "fused"):
+            if mode == args.mode:
+                continue
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            o, _ = step(mode, True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            result[f"{mode}_step"] = {
+                "ms_per_step": el * 1e3, "gate_updates_per_s": ngates / el, "passes": o.passes,
+                "avg_pass_ms": o.kernel_ms / max(o.passes, 1),
+                "achieved_GBps": o.bytes / (o.kernel_ms / 1e3) / 1e9,
+                "mma": "fp64" if mode == "fused" else None, "fuse_k": 5 if mode == "fused" else None}
+            log(f"{mode}: {el * 1e3:.1f} ms for one step, {o.passes} passes")
+
+    st.close()
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

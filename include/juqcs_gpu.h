@@ -64,7 +64,8 @@ typedef enum {
   JUQCS_MMA_FP64 = 0,   /* FP64 matrix cores (C128 states)                 */
   JUQCS_MMA_FP32 = 1,   /* FP32 matrix cores (C64 states)                  */
   JUQCS_MMA_BF16 = 2,   /* BF16 inputs, FP32 accumulation (C64 states)     */
-  JUQCS_MMA_BF16X3 = 3, /* hi/lo BF16 split, three products, FP32 accum.   */
+  JUQCS_MMA_BF16X3 = 3, /* hi/lo BF16 split, three products, FP32 accum.,
+                           about 17 significant bits per pass        */
   JUQCS_MMA_AUTO = 4    /* FP64 for C128, FP32 for C64                     */
 } juqcs_mma;
 
@@ -168,10 +169,16 @@ typedef struct {
   int32_t mma;         /* FUSED: juqcs_mma                                */
   int32_t tile_bits;   /* TILE: total tile bits (0 = default for dtype)   */
   int32_t low_bits;    /* TILE: contiguous low bits per chunk (0 = default) */
-  int32_t reserved[3];
+  int32_t profile;     /* 1: time every pass with HIP events on the state's
+                          stream (the call then synchronises the stream)   */
+  int32_t reserved[2];
   /* outputs */
   int64_t passes;      /* kernel passes over the state that were launched */
   int64_t gates;       /* gate records consumed                           */
+  double kernel_ms;    /* profile: summed device durations of the passes  */
+  double bytes;        /* algorithmic HBM bytes of the passes: read + write
+                          of every amplitude (and ENC2 scale) a pass must
+                          touch                                            */
 } juqcs_plan_opts;
 
 /* Applies count gate records in order (gates commuting on disjoint qubits

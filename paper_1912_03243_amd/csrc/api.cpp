@@ -65,9 +65,43 @@ struct juqcs_state {
   hipStream_t stream;
   int phys[64];  // logical qubit -> physical bit
   size_t ring;   // next free offset inside the ring
+  // per-pass timing of juqcs_run_circuit when profiling (else empty)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  double bytes = 0.0;  // algorithmic bytes of the passes launched by the call
 };
 
 namespace {
+
+// Pass timing: an event pair around every pass launch on the state's stream.
+void prof_begin(juqcs_state* st) {
+  if (!st->profiling) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) == hipSuccess) {
+    (void)hipEventRecord(e, st->stream);
+    st->ev.push_back(e);
+  }
+}
+void prof_end(juqcs_state* st) { prof_begin(st); }
+
+double prof_collect(juqcs_state* st) {
+  double total = 0.0;
+  if (!st->ev.empty()) (void)hipEventSynchronize(st->ev.back());
+  for (size_t i = 0; i + 1 < st->ev.size(); i += 2) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, st->ev[i], st->ev[i + 1]) == hipSuccess) total += ms;
+  }
+  for (hipEvent_t e : st->ev) (void)hipEventDestroy(e);
+  st->ev.clear();
+  return total;
+}
+
+double full_pass_bytes(const juqcs_state* st) {
+  const double count = std::ldexp(1.0, st->n);
+  double b = 2.0 * count * (double)(st->dt == JUQCS_C128 ? 16 : st->dt == JUQCS_C64 ? 8 : 2);
+  if (st->dt == JUQCS_ENC2) b += 2.0 * 4.0 * std::ldexp(1.0, st->n - st->B);
+  return b;
+}
 
 // Stream-ordered ring allocation inside the workspace: later kernels on the
 // same stream only start after earlier ones finish, so reusing ring space is
@@ -132,9 +166,12 @@ juqcs_status run_tile_plan(juqcs_state* st, const TilePlan& plan) {
   const TileOp* d_ops = (const TileOp*)dev;
   const void* d_mats = dev + mats_off;
   for (const TilePass& p : plan.passes) {
+    prof_begin(st);
     hipError_t e = launch_tile(st->dt, st->amps, st->scales, p.g, d_ops + p.op_begin,
                                p.op_count, d_mats, st->stream);
+    prof_end(st);
     if (e != hipSuccess) return hip_fail(e, "tile pass launch");
+    st->bytes += full_pass_bytes(st);
   }
   return JUQCS_OK;
 }
@@ -184,13 +221,20 @@ juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g) {
     std::vector<Gate> one{g};
     return tile_gates(st, one, 0, 0, nullptr);
   }
+  const double full = full_pass_bytes(st);
+  prof_begin(st);
   if (g.nq == 1) {
     const C* u = g.m;
     if (g.diag && is_one(u[0])) {
-      if (is_one(u[3])) return JUQCS_OK;  // identity
+      if (is_one(u[3])) {
+        prof_end(st);
+        return JUQCS_OK;  // identity
+      }
       e = launch_diag(st->dt, st->amps, st->n, uint64_t(1) << g.q[0], u[3], st->stream);
+      st->bytes += 0.5 * full;
     } else {
       e = launch_1q(st->dt, st->amps, st->n, g.q[0], -1, u, st->stream);
+      st->bytes += full;
     }
   } else {
     // controlled-U form: identity where bit q0 is clear?
@@ -207,16 +251,23 @@ juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g) {
     if (ctrl) {
       const C u[4] = {m[1 * 4 + 1], m[1 * 4 + 3], m[3 * 4 + 1], m[3 * 4 + 3]};
       if (is_diag2(u) && is_one(u[0])) {
-        if (is_one(u[3])) return JUQCS_OK;
+        if (is_one(u[3])) {
+          prof_end(st);
+          return JUQCS_OK;
+        }
         e = launch_diag(st->dt, st->amps, st->n, (uint64_t(1) << g.q[0]) | (uint64_t(1) << g.q[1]),
                         u[3], st->stream);
+        st->bytes += 0.25 * full;
       } else {
         e = launch_1q(st->dt, st->amps, st->n, g.q[1], g.q[0], u, st->stream);
+        st->bytes += 0.5 * full;
       }
     } else {
       e = launch_2q(st->dt, st->amps, st->n, g.q[0], g.q[1], m, st->stream);
+      st->bytes += full;
     }
   }
+  prof_end(st);
   if (e != hipSuccess) return hip_fail(e, "gate launch");
   return JUQCS_OK;
 }
@@ -257,8 +308,11 @@ juqcs_status apply_fused_phys(juqcs_state* st, int k, const int* targets, const 
     rc = upload(st, at.data(), at.size() * sizeof(float), &dev);
   }
   if (rc != JUQCS_OK) return rc;
+  prof_begin(st);
   hipError_t e = launch_fused(st->dt, st->amps, st->n, k, targets, dev, mode, st->stream);
+  prof_end(st);
   if (e != hipSuccess) return hip_fail(e, "fused launch");
+  st->bytes += full_pass_bytes(st);
   return JUQCS_OK;
 }
 
@@ -318,6 +372,9 @@ juqcs_status move_layout(juqcs_state* st, const int* target) {
   for (int q = 0; q < st->n; ++q) st->phys[q] = target[q];
   return JUQCS_OK;
 }
+
+juqcs_status run_planned(juqcs_state* st, const std::vector<Gate>& g, int mode,
+                         juqcs_plan_opts* o);
 
 }  // namespace
 
@@ -494,6 +551,22 @@ juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates, size_t 
   if (st->dt == JUQCS_ENC2) mode = JUQCS_PLAN_TILE;
   o->gates = (int64_t)count;
   o->passes = 0;
+  o->kernel_ms = 0.0;
+  st->bytes = 0.0;
+  st->profiling = o->profile != 0;
+  juqcs_status rc = run_planned(st, g, mode, o);
+  if (st->profiling) o->kernel_ms = prof_collect(st);
+  st->profiling = false;
+  o->bytes = st->bytes;
+  return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+juqcs_status run_planned(juqcs_state* st, const std::vector<Gate>& g, int mode,
+                         juqcs_plan_opts* o) {
   if (mode == JUQCS_PLAN_PLAIN) {
     for (const Gate& x : g) {
       if (juqcs_status rc = apply_gate_plain(st, x)) return rc;
@@ -523,6 +596,10 @@ juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates, size_t 
   }
   return JUQCS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 juqcs_status juqcs_amplitudes_device(juqcs_state* st, const uint64_t* d_idx, size_t count,
                                      double* d_out) {

@@ -69,8 +69,6 @@ enum TileOpKind : int32_t {
   TOP_DENSE1 = 0,  // 2x2 on local bit a
   TOP_DENSE2 = 1,  // 4x4 on local bits (a, b), index b_a + 2 b_b
   TOP_DIAG2 = 2,   // phases d[b_a + 2 b_b] (b may equal -1: d[b_a])
-  TOP_PERM = 3,    // (reserved) local bit permutation
-  TOP_DENSEK = 4,  // 2^k x 2^k on k local bits (k <= 4), bits in bits[]
 };
 
 struct TileOp {

@@ -9,7 +9,8 @@
 //   FP64   v_mfma_f64_16x16x4f64        (C128 states)
 //   FP32   v_mfma_f32_16x16x4f32        (C64 states)
 //   BF16   v_mfma_f32_16x16x16bf16_1k   (C64 states, FP32 accumulation)
-//   BF16X3 three BF16 products hi*hi + hi*lo + lo*hi (about FP32 accuracy)
+//   BF16X3 three BF16 products hi*hi + hi*lo + lo*hi (operands carried to
+//          about 17 significant bits; lo*lo is dropped)
 //
 // A workgroup (4 waves) owns 64 consecutive columns: it stages the 2K x 64
 // panel in LDS with coalesced loads, each wave multiplies its 16 columns, the

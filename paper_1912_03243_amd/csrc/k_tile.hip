@@ -9,6 +9,9 @@
 // Storage forms: C128 and C64 amplitudes, and the two-byte form (ENC2),
 // which is decoded into FP32 on load and re-encoded with fresh per-block
 // scales on store (Section 1, adaptive two-byte coding).
+#include <mutex>
+#include <unordered_map>
+
 #include "juqcs_internal.hpp"
 
 namespace juqcs {
@@ -35,6 +38,23 @@ __device__ inline uint64_t tile_base(uint64_t tau, const TileGeom& g) {
 }
 
 // ---------------------------------------------------------------- ops ----
+// d[b_a + 2 b_c] with selects only (a table lookup would go through scratch).
+template <typename T>
+__device__ inline cplx<T> diag_pick(int e, int a, int c, cplx<T> d0, cplx<T> d1, cplx<T> d2,
+                                    cplx<T> d3) {
+  const bool x = (e >> a) & 1;
+  const bool y = c >= 0 && ((e >> c) & 1);
+  cplx<T> lo, hi;
+  lo.re = x ? d1.re : d0.re;
+  lo.im = x ? d1.im : d0.im;
+  hi.re = x ? d3.re : d2.re;
+  hi.im = x ? d3.im : d2.im;
+  cplx<T> r;
+  r.re = y ? hi.re : lo.re;
+  r.im = y ? hi.im : lo.im;
+  return r;
+}
+
 template <typename T>
 __device__ inline void op_dense1(cplx<T>* sh, int b, int a, const cplx<T>* __restrict__ m) {
   const cplx<T> u0 = m[0], u1 = m[1], u2 = m[2], u3 = m[3];
@@ -77,53 +97,7 @@ __device__ inline void op_diag2(cplx<T>* sh, int b, int a, int c, const cplx<T>*
   const cplx<T> d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
   const int n = 1 << b;
   for (int e = threadIdx.x; e < n; e += kThreads) {
-    const int r = ((e >> a) & 1) | (c >= 0 ? (((e >> c) & 1) << 1) : 0);
-    const cplx<T> d = r == 0 ? d0 : r == 1 ? d1 : r == 2 ? d2 : d3;
-    sh[e] = cmul(d, sh[e]);
-  }
-}
-
-// Dense 2^k x 2^k on k local bits (k <= 4).  bits[] in matrix order (bit j of
-// the row index <-> local bit bits[j]); zeros are inserted in ascending order.
-template <typename T, int K>
-__device__ inline void op_densek(cplx<T>* sh, int b, const int32_t* bits,
-                                 const cplx<T>* __restrict__ m) {
-  constexpr int D = 1 << K;
-  int sorted[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) sorted[j] = bits[j];
-#pragma unroll
-  for (int i = 0; i < K; ++i)
-#pragma unroll
-    for (int j = 0; j + 1 < K - i; ++j)
-      if (sorted[j] > sorted[j + 1]) {
-        const int t = sorted[j];
-        sorted[j] = sorted[j + 1];
-        sorted[j + 1] = t;
-      }
-  int off[D];
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    int o = 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j) o |= ((r >> j) & 1) << bits[j];
-    off[r] = o;
-  }
-  const int ng = 1 << (b - K);
-  for (int p = threadIdx.x; p < ng; p += kThreads) {
-    uint64_t i = (uint64_t)p;
-#pragma unroll
-    for (int j = 0; j < K; ++j) i = insert_zero(i, sorted[j]);
-    cplx<T> v[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r) v[r] = sh[(int)i | off[r]];
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-      cplx<T> acc = cmul(m[r * D], v[0]);
-#pragma unroll
-      for (int s = 1; s < D; ++s) acc = cmad(m[r * D + s], v[s], acc);
-      sh[(int)i | off[r]] = acc;
-    }
+    sh[e] = cmul(diag_pick(e, a, c, d0, d1, d2, d3), sh[e]);
   }
 }
 
@@ -137,10 +111,6 @@ __device__ inline void run_ops(cplx<T>* sh, int b, const TileOp* __restrict__ op
       case TOP_DENSE1: op_dense1<T>(sh, b, op.a, m); break;
       case TOP_DENSE2: op_dense2<T>(sh, b, op.a, op.b, m); break;
       case TOP_DIAG2: op_diag2<T>(sh, b, op.a, op.b, m); break;
-      case TOP_DENSEK:
-        if (op.k == 3) op_densek<T, 3>(sh, b, op.bits, m);
-        else op_densek<T, 4>(sh, b, op.bits, m);
-        break;
       default: break;
     }
     __syncthreads();
@@ -167,24 +137,175 @@ __global__ __launch_bounds__(kThreads) void k_tile(cplx<T>* __restrict__ psi, Ti
   const int lmask = (1 << g.L) - 1;
   for (uint64_t tau = blockIdx.x; tau < ntiles; tau += gridDim.x) {
     const uint64_t base = tile_base(tau, g);
-    // load: 8 independent loads in flight per thread per round
+    // load: 8 independent loads in flight per thread per round (a native
+    // 2-vector buffer stays in registers)
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2* gp = reinterpret_cast<const v2*>(psi);
+    v2* sp = reinterpret_cast<v2*>(sh);
     for (int e0 = 0; e0 < tile_amps; e0 += kThreads * 8) {
-      cplx<T> v[8];
+      v2 v[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int e = e0 + k * kThreads + threadIdx.x;
-        if (e < tile_amps) v[k] = psi[base + choff[e >> g.L] + (e & lmask)];
+        const int ec = e < tile_amps ? e : 0;
+        v[k] = gp[base + choff[ec >> g.L] + (ec & lmask)];
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int e = e0 + k * kThreads + threadIdx.x;
-        if (e < tile_amps) sh[e] = v[k];
+        if (e < tile_amps) sp[e] = v[k];
       }
     }
     __syncthreads();
     run_ops<T>(sh, b, ops, nops, mats);
     for (int e = threadIdx.x; e < tile_amps; e += kThreads)
       psi[base + choff[e >> g.L] + (e & lmask)] = sh[e];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------- pipelined fixed-size tiles ---
+// Tile size fixed at compile time (TB bits) and 512 threads per workgroup:
+// every loop below has a constant trip count and is unrolled, each op reads
+// all of its LDS operands before it writes, and a persistent grid prefetches
+// the next tile into registers while the current one is processed on chip,
+// so HBM traffic overlaps the ops.
+constexpr int kFixedThreads = 512;
+
+template <typename T, int TB>
+__device__ inline void fop_dense1(cplx<T>* sh, int a, const cplx<T>* __restrict__ m) {
+  constexpr int NP = (1 << (TB - 1)) / kFixedThreads;
+  const cplx<T> u0 = m[0], u1 = m[1], u2 = m[2], u3 = m[3];
+  const int abit = 1 << a;
+  cplx<T> x[NP], y[NP];
+  int i0[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    i0[k] = (int)insert_zero((uint64_t)(k * kFixedThreads + threadIdx.x), a);
+    x[k] = sh[i0[k]];
+    y[k] = sh[i0[k] | abit];
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    sh[i0[k]] = cmad(u1, y[k], cmul(u0, x[k]));
+    sh[i0[k] | abit] = cmad(u3, y[k], cmul(u2, x[k]));
+  }
+}
+
+template <typename T, int TB>
+__device__ inline void fop_dense2(cplx<T>* sh, int a, int c, const cplx<T>* __restrict__ m) {
+  constexpr int NQ = (1 << (TB - 2)) / kFixedThreads;
+  const int lo = a < c ? a : c, hi = a < c ? c : a;
+  const int ba = 1 << a, bc = 1 << c;
+  cplx<T> v[NQ][4];
+  int ix[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    ix[k] = (int)insert_zero(insert_zero((uint64_t)(k * kFixedThreads + threadIdx.x), lo), hi);
+    v[k][0] = sh[ix[k]];
+    v[k][1] = sh[ix[k] | ba];
+    v[k][2] = sh[ix[k] | bc];
+    v[k][3] = sh[ix[k] | ba | bc];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const cplx<T> m0 = m[4 * r], m1 = m[4 * r + 1], m2 = m[4 * r + 2], m3 = m[4 * r + 3];
+    const int off = ((r & 1) ? ba : 0) | ((r & 2) ? bc : 0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      cplx<T> acc = cmul(m0, v[k][0]);
+      acc = cmad(m1, v[k][1], acc);
+      acc = cmad(m2, v[k][2], acc);
+      acc = cmad(m3, v[k][3], acc);
+      sh[ix[k] | off] = acc;
+    }
+  }
+}
+
+template <typename T, int TB>
+__device__ inline void fop_diag2(cplx<T>* sh, int a, int c, const cplx<T>* __restrict__ m) {
+  constexpr int NE = (1 << TB) / kFixedThreads;
+  const cplx<T> d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = k * kFixedThreads + threadIdx.x;
+    sh[e] = cmul(diag_pick(e, a, c, d0, d1, d2, d3), sh[e]);
+  }
+}
+
+// Base index of tile tau: tau's bits fill the non-tile positions in order.
+__device__ inline uint64_t tile_base_lds(uint64_t tau, int L, int H, const int* hb) {
+  uint64_t base = tau << L;
+  for (int j = 0; j < H; ++j) base = insert_zero(base, hb[j]);
+  return base;
+}
+
+template <typename T, int TB>
+__global__ __launch_bounds__(kFixedThreads) void k_tile_fixed(cplx<T>* __restrict__ psi, TileGeom g,
+                                                              const TileOp* __restrict__ ops,
+                                                              int nops,
+                                                              const cplx<T>* __restrict__ mats) {
+  constexpr int NA = 1 << TB, PER = NA / kFixedThreads;
+  __shared__ cplx<T> sh[NA];
+  __shared__ uint64_t choff[1 << kMaxGather];
+  __shared__ int hb[kHbitsCap];
+  const int H = g.H, L = g.L, lmask = (1 << L) - 1;
+  if (threadIdx.x < kHbitsCap) hb[threadIdx.x] = threadIdx.x < H ? g.hbits[threadIdx.x] : 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < (1 << H); c += kFixedThreads) {
+    uint64_t o = 0;
+    for (int j = 0; j < H; ++j) o |= (uint64_t)((c >> j) & 1) << hb[j];
+    choff[c] = o;
+  }
+  __syncthreads();
+  const uint64_t ntiles = uint64_t(1) << (g.n - TB);
+  // the grid never exceeds ntiles, so blockIdx.x is a valid first tile.
+  // (a native 2-vector keeps the buffer in registers; an array of the cplx
+  // struct is demoted to scratch for FP64)
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2* gp = reinterpret_cast<v2*>(psi);
+  v2* sp = reinterpret_cast<v2*>(sh);
+  v2 v[PER];
+  uint64_t tau = blockIdx.x;
+  {
+    const uint64_t base = tile_base_lds(tau, L, H, hb);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = k * kFixedThreads + threadIdx.x;
+      v[k] = gp[base + choff[e >> L] + (e & lmask)];
+    }
+  }
+  for (; tau < ntiles; tau += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sp[k * kFixedThreads + threadIdx.x] = v[k];
+    __syncthreads();
+    // prefetch the next tile while this one is on chip; after the last tile
+    // the current one is read again (in bounds, values unused), which keeps
+    // the buffer in registers
+    const uint64_t nxt = tau + gridDim.x;
+    const uint64_t pf = nxt < ntiles ? nxt : tau;
+    {
+      const uint64_t nb = tile_base_lds(pf, L, H, hb);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = k * kFixedThreads + threadIdx.x;
+        v[k] = gp[nb + choff[e >> L] + (e & lmask)];
+      }
+    }
+    for (int o = 0; o < nops; ++o) {
+      const TileOp op = ops[o];
+      const cplx<T>* m = mats + op.moff;
+      if (op.kind == TOP_DENSE2) fop_dense2<T, TB>(sh, op.a, op.b, m);
+      else if (op.kind == TOP_DENSE1) fop_dense1<T, TB>(sh, op.a, m);
+      else fop_diag2<T, TB>(sh, op.a, op.b, m);
+      __syncthreads();
+    }
+    const uint64_t base = tile_base_lds(tau, L, H, hb);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = k * kFixedThreads + threadIdx.x;
+      gp[base + choff[e >> L] + (e & lmask)] = sp[e];
+    }
     __syncthreads();
   }
 }
@@ -272,6 +393,23 @@ __global__ __launch_bounds__(kThreads) void k_tile_enc2(int8_t* __restrict__ cod
   }
 }
 
+// Workgroups of a kernel that fit on the device at once (cached per kernel).
+uint64_t resident_blocks(const void* kern, int threads) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, uint64_t> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kern);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 256, per = 1;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, 0) != hipSuccess || per < 1)
+    per = 1;
+  const uint64_t r = (uint64_t)cus * (uint64_t)per;
+  cache[kern] = r;
+  return r;
+}
+
 inline unsigned tile_grid(uint64_t ntiles) {
   return (unsigned)(ntiles < (1u << 20) ? ntiles : (1u << 20));
 }
@@ -285,21 +423,36 @@ int tile_max_bits(juqcs_dtype dt) {
 hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom& g,
                        const TileOp* d_ops, int nops, const void* d_mats, hipStream_t s) {
   const uint64_t ntiles = uint64_t(1) << (g.n - g.b);
-  const dim3 grid(tile_grid(ntiles)), block(kThreads);
+  const dim3 grid(tile_grid(ntiles)), block(kThreads), fblock(kFixedThreads);
+  // persistent grid for the pipelined kernels: every resident workgroup slot
+  auto pgrid_for = [&](const void* kern) {
+    const uint64_t slots = resident_blocks(kern, kFixedThreads);
+    return dim3((unsigned)(ntiles < slots ? ntiles : slots));
+  };
   if (dt == JUQCS_C128) {
-    if (g.b <= 12)
-      hipLaunchKernelGGL((k_tile<double, 12>), grid, block, 0, s, (cplx<double>*)amps, g, d_ops,
-                         nops, (const cplx<double>*)d_mats);
+    auto* p = (cplx<double>*)amps;
+    auto* m = (const cplx<double>*)d_mats;
+    if (g.b == 12)
+      hipLaunchKernelGGL((k_tile_fixed<double, 12>), pgrid_for((const void*)k_tile_fixed<double, 12>), fblock, 0, s, p, g, d_ops, nops, m);
+    else if (g.b == 11)
+      hipLaunchKernelGGL((k_tile_fixed<double, 11>), pgrid_for((const void*)k_tile_fixed<double, 11>), fblock, 0, s, p, g, d_ops, nops, m);
+    else if (g.b <= 12)
+      hipLaunchKernelGGL((k_tile<double, 12>), grid, block, 0, s, p, g, d_ops, nops, m);
     else
-      hipLaunchKernelGGL((k_tile<double, 13>), grid, block, 0, s, (cplx<double>*)amps, g, d_ops,
-                         nops, (const cplx<double>*)d_mats);
+      hipLaunchKernelGGL((k_tile<double, 13>), grid, block, 0, s, p, g, d_ops, nops, m);
   } else if (dt == JUQCS_C64) {
-    if (g.b <= 13)
-      hipLaunchKernelGGL((k_tile<float, 13>), grid, block, 0, s, (cplx<float>*)amps, g, d_ops,
-                         nops, (const cplx<float>*)d_mats);
+    auto* p = (cplx<float>*)amps;
+    auto* m = (const cplx<float>*)d_mats;
+    if (g.b == 13)
+      hipLaunchKernelGGL((k_tile_fixed<float, 13>), pgrid_for((const void*)k_tile_fixed<float, 13>), fblock, 0, s, p, g, d_ops, nops, m);
+    else if (g.b == 12)
+      hipLaunchKernelGGL((k_tile_fixed<float, 12>), pgrid_for((const void*)k_tile_fixed<float, 12>), fblock, 0, s, p, g, d_ops, nops, m);
+    else if (g.b == 11)
+      hipLaunchKernelGGL((k_tile_fixed<float, 11>), pgrid_for((const void*)k_tile_fixed<float, 11>), fblock, 0, s, p, g, d_ops, nops, m);
+    else if (g.b <= 13)
+      hipLaunchKernelGGL((k_tile<float, 13>), grid, block, 0, s, p, g, d_ops, nops, m);
     else
-      hipLaunchKernelGGL((k_tile<float, 14>), grid, block, 0, s, (cplx<float>*)amps, g, d_ops,
-                         nops, (const cplx<float>*)d_mats);
+      hipLaunchKernelGGL((k_tile<float, 14>), grid, block, 0, s, p, g, d_ops, nops, m);
   } else {
     hipLaunchKernelGGL(k_tile_enc2, grid, block, 0, s, (int8_t*)amps, (float*)scales, g, d_ops,
                        nops, (const cplx<float>*)d_mats);

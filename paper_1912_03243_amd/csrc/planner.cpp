@@ -258,10 +258,6 @@ void emit_ops(const std::vector<Cluster>& cl, const TileGeom& geom, TilePlan* pl
       op.a = local(c.q[0]);
       op.b = local(c.q[1]);
       for (int i = 0; i < 16; ++i) plan->mats.push_back(c.m[i]);
-    } else {
-      op.kind = TOP_DENSEK;
-      for (int j = 0; j < k; ++j) op.bits[j] = local(c.q[j]);
-      for (int i = 0; i < dim * dim; ++i) plan->mats.push_back(c.m[i]);
     }
     plan->ops.push_back(op);
   }

@@ -1,0 +1,74 @@
+"""Writes the stored expected amplitudes used by the full-size GPU tests.
+
+Calls only the CPU oracle (and the seeded workload generators).  The
+amplitudes of a 28-36 qubit layered circuit are far too many for the oracle's
+full state-vector path, so each requested coefficient is computed with the
+paper's entangling-gate decomposition (Section 4, Eq. (3)): the qubits are cut
+into a low and a high half, every CZ across the cut is split with Eq. (2),
+and <z|C|0> = 2^-S sum_s A_s(z_low) B_s(z_high) in FP64.  The decomposition
+is pinned against the full state vector in tests/test_oracle_pins.py.
+
+usage: python tests/golden/make_golden.py brick30 [brick28 brick34 brick36]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import decomposition  # noqa: E402
+from paper_1912_03243_amd import workloads as W  # noqa: E402
+
+# name: (n, layers, circuit seed, bitstring seed, count)
+SETS = {
+    "brick30": (30, 20, 2, 1002, 256),
+    "brick28": (28, 16, 3, 1003, 256),
+    "brick34": (34, 16, 3, 1003, 256),
+    "brick36": (36, 16, 3, 1003, 256),
+}
+
+
+def path_for(name):
+    return os.path.join(HERE, f"{name}_amplitudes.txt")
+
+
+def make(name):
+    n, layers, cseed, zseed, count = SETS[name]
+    circ = W.layered_brick(n, layers, seed=cseed)
+    z = W.bitstrings(n, count, seed=zseed)
+    side = np.array([0] * (n // 2) + [1] * (n - n // 2), dtype=np.uint8)
+    S = len(decomposition.crossing_czs(circ, side))
+    t0 = time.time()
+    amps = decomposition.branch_amplitudes(n, circ, side, z)
+    dt = time.time() - t0
+    with open(path_for(name), "w") as f:
+        f.write(f"# {name}: layered_brick(n={n}, layers={layers}, seed={cseed}); "
+                f"bitstrings(n={n}, count={count}, seed={zseed})\n")
+        f.write(f"# <z|C|0> by Eq. (3) (Section 4) with the cut {n // 2}|{n - n // 2}, "
+                f"S={S} decomposed CZs, FP64 oracle, {dt:.0f} s\n")
+        f.write("# z re im\n")
+        for zi, a in zip(z, amps):
+            f.write(f"{int(zi)} {a.real:.17e} {a.imag:.17e}\n")
+    print(f"{name}: S={S} {dt:.1f}s -> {path_for(name)}", flush=True)
+
+
+def load(name):
+    z, re, im = [], [], []
+    with open(path_for(name)) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            a, b, c = line.split()
+            z.append(int(a))
+            re.append(float(b))
+            im.append(float(c))
+    return np.array(z, dtype=np.uint64), np.array(re) + 1j * np.array(im)
+
+
+if __name__ == "__main__":
+    for nm in sys.argv[1:] or ["brick30"]:
+        make(nm)

@@ -1,0 +1,129 @@
+"""Full-size GPU checks at the benchmark sizes.
+
+The oracle cannot hold these states, so the comparison uses amplitudes it
+computed one by one with the entangling-gate decomposition (Section 4,
+Eq. (3); stored by tests/golden/make_golden.py), plus properties that hold at
+any size: the norm, the GHZ closed form (Section 3) and the uniform state.
+Each test prints its case before touching the GPU.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from _parity import TOL_C128, bf16_bound, bf16x3_bound, enc2_bound, rel_l2
+from paper_1912_03243_amd import workloads as W
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+from make_golden import SETS, load, path_for  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def J():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1912_03243_amd import juqcs
+    return juqcs
+
+
+def announce(*what):
+    print("CASE", *what, flush=True)
+
+
+def golden(name):
+    if not os.path.exists(path_for(name)):
+        pytest.skip(f"stored amplitudes {name} not generated")
+    return load(name)
+
+
+def circuit(name):
+    n, layers, cseed, _, _ = SETS[name]
+    return n, W.layered_brick(n, layers, seed=cseed)
+
+
+def test_brick30_c128_tile_matches_oracle(J):
+    """The benchmark configuration itself: n=30, complex128, tile passes."""
+    name = "brick30"
+    z, want = golden(name)
+    n, circ = circuit(name)
+    announce(name, "c128 tile")
+    with J.State(n, "c128") as s:
+        s.init(0)
+        o = s.run(circ, mode="tile")
+        got = s.amplitudes(z)
+        nrm = s.norm()
+    err = float(np.max(np.abs(got - want)))
+    print(f"brick30 tile: passes={o.passes} max|err|={err:.3e} norm-1={nrm - 1:.3e}")
+    assert err <= TOL_C128
+    assert rel_l2(got, want) <= TOL_C128
+    assert abs(nrm - 1.0) <= TOL_C128
+
+
+@pytest.mark.parametrize("mode", ["plain", "fused"])
+def test_brick30_c128_other_modes(J, mode):
+    name = "brick30"
+    z, want = golden(name)
+    n, circ = circuit(name)
+    announce(name, "c128", mode)
+    with J.State(n, "c128") as s:
+        s.init(0)
+        s.run(circ, mode=mode, fuse_k=5)
+        got = s.amplitudes(z)
+    assert float(np.max(np.abs(got - want))) <= TOL_C128
+
+
+def test_ghz30_closed_form(J):
+    n = 30
+    announce("ghz30 c128 plain")
+    with J.State(n, "c128") as s:
+        s.init(0)
+        s.run(W.ghz(n), mode="plain")
+        a = s.amplitudes([0, (1 << n) - 1, 1, 1 << 29, 12345])
+        nrm = s.norm()
+    r = 1.0 / math.sqrt(2.0)
+    assert abs(a[0] - r) < 1e-15 and abs(a[1] - r) < 1e-15
+    assert np.all(a[2:] == 0) and abs(nrm - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("dtype, mode, mma", [
+    ("c64", "tile", "auto"), ("c64", "fused", "fp32"), ("c64", "fused", "bf16x3"),
+    ("c64", "fused", "bf16"), ("enc2", "tile", "auto")])
+def test_brick28_precision_forms(J, dtype, mode, mma):
+    """Error of the reduced-precision forms against FP64 at n=28."""
+    name = "brick28"
+    z, want = golden(name)
+    n, circ = circuit(name)
+    announce(name, dtype, mode, mma)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        o = s.run(circ, mode=mode, fuse_k=5, mma=mma)
+        got = s.amplitudes(z)
+        nrm = s.norm()
+    err = rel_l2(got, want)
+    print(f"brick28 {dtype} {mode} {mma}: passes={o.passes} relL2={err:.3e} norm-1={nrm - 1:.3e}")
+    if dtype == "enc2":
+        assert err <= enc2_bound(o.passes)
+XX, [("brick34", "c64"), ("brick36", "enc2")])
+def test_largest_states(J, name, dtype):
+    """34 qubits complex64 (128 GiB) and 36 qubits two-byte (128 GiB)."""
+    z, want = golden(name)
+    n, circ = circuit(name)
+    announce(name, dtype, "tile")
+    with J.State(n, dtype) as s:
+        s.init(0)
+        o = s.run(circ, mode="tile")
+        got = s.amplitudes(z)
+        nrm = s.norm()
+    import torch
+    del s
+    torch.cuda.empty_cache()
+    err = rel_l2(got, want)
+    print(f"{name} {dtype}: passes={o.passes} relL2={err:.3e} norm-1={nrm - 1:.3e}")
+    if dtype == "enc2":
+        assert err <= enc2_bound(o.passes)
+    else:
+        assert err <= 1e-5

@@ -7,7 +7,7 @@ import math
 import numpy as np
 import pytest
 
-from _parity import assert_c128, assert_c64, assert_dtype, bf16_bound, rel_l2
+from _parity import assert_c128, assert_c64, assert_dtype, bf16_bound, bf16x3_bound, rel_l2
 from oracle import enc2 as oenc2
 from oracle import observables, statevector as sv
 from paper_1912_03243_amd import workloads as W
@@ -163,7 +163,7 @@ def test_apply_fused_k(J, dtype, mode, targets):
     if mode == "bf16":
         assert rel_l2(got, phi) <= bf16_bound(1)
     elif mode == "bf16x3":
-        assert_c64(got, phi, tol=1e-4)
+        assert rel_l2(got, phi) <= bf16x3_bound(1)
     else:
         assert_dtype(dtype, got, phi)
 
