@@ -171,7 +171,10 @@ typedef struct {
   int32_t low_bits;    /* TILE: contiguous low bits per chunk (0 = default) */
   int32_t profile;     /* 1: time every pass with HIP events on the state's
                           stream (the call then synchronises the stream)   */
-  int32_t reserved[2];
+  int32_t autotune;    /* batches: 1 = pick the on-chip fusion width per
+                          qubit count from timed trial runs (the trials
+                          use the batch's state buffer); 0 = cost model  */
+  int32_t reserved;
   /* outputs */
   int64_t passes;      /* kernel passes over the state that were launched */
   int64_t gates;       /* gate records consumed                           */
@@ -257,22 +260,40 @@ typedef struct juqcs_batch juqcs_batch; /* opaque */
 /* Builds a batch of count circuits: circuit i has n[i] qubits (1..30) and
  * gate records gates[offsets[i] .. offsets[i+1]).  States are C64 in
  * d_states at byte offsets state_offset[i] (each 8 * 2^n[i] bytes, caller
- * allocated, disjoint); every circuit starts from |0...0>.  The planner
- * builds a device work list once (uploaded into library-owned device
- * memory); juqcs_batch_run then executes everything in one persistent
- * kernel launch.  Errors: ARG, QUBIT, NUMERIC, HIP. */
+ * allocated, disjoint, 16-byte aligned); every circuit starts from
+ * |0...0>.  Each circuit is planned into on-chip tile passes (tiles of up
+ * to 2^13 amplitudes); the fusion width inside a pass (1..4 qubits) is
+ * opts->fuse_k, or chosen per circuit when fuse_k is 0: by a cost model, or
+ * by timed trials when opts->autotune is 1.  The work list is uploaded into
+ * library-owned device memory.  Errors: ARG, QUBIT, NUMERIC, HIP. */
 juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
                                 const juqcs_gate* gates, const int64_t* offsets,
                                 void* d_states, const uint64_t* state_offset,
                                 const juqcs_plan_opts* opts);
 
-/* Runs the whole batch on hip_stream (asynchronous; may be captured in a
- * HIP graph). */
+/* Runs the whole batch in one persistent kernel launch on hip_stream
+ * (asynchronous).  On a non-default stream the launch is captured once into
+ * a HIP graph and replayed on later calls. */
 juqcs_status juqcs_batch_run(juqcs_batch* b, void* hip_stream);
 
-/* Work-list statistics: passes (tile tasks) and total gate applications. */
+/* Synchronises the stream of the last run and reports a dependency wait
+ * that hit its spin limit (JUQCS_ERR_HIP). */
+juqcs_status juqcs_batch_wait(juqcs_batch* b);
+
+/* Work-list statistics: tile tasks, gate records and tile passes. */
 juqcs_status juqcs_batch_stats(const juqcs_batch* b, int64_t* tasks,
                                int64_t* gate_apps, int64_t* passes);
+
+/* Fusion width chosen for every circuit (count ints). */
+juqcs_status juqcs_batch_fusion(const juqcs_batch* b, int* kin);
+
+/* out[2*(c*m+k)], out[2*(c*m+k)+1] = amplitude idx[c*m+k] of circuit c
+ * (host arrays, FP64 pairs; an index >= 2^n gives NaN).  Synchronises. */
+juqcs_status juqcs_batch_amplitudes(juqcs_batch* b, const uint64_t* idx, int m,
+                                    double* out, void* hip_stream);
+
+/* out[c] = FP64 norm of circuit c (fixed-order sum).  Synchronises. */
+juqcs_status juqcs_batch_norms(juqcs_batch* b, double* out, void* hip_stream);
 
 juqcs_status juqcs_batch_destroy(juqcs_batch* b);
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libjuqcs_gpu.so")
 
 SOURCES = ["api.cpp", "planner.cpp", "batch.cpp", "k_gates.hip", "k_tile.hip",
-           "k_fused.hip", "k_codec.hip"]
+           "k_fused.hip", "k_codec.hip", "k_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

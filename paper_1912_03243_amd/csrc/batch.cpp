@@ -1,40 +1,601 @@
-// Batched circuits and the entangling-gate decomposition driver (Section 4).
+// Batches of independent circuits in one persistent launch, the on-chip
+// fusion-width autotuner, and the entangling-gate decomposition driver
+// (Section 4, Eqs. (2) and (3)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "juqcs_internal.hpp"
 
 using namespace juqcs;
 
+namespace {
+
+using C = cplx<double>;
+constexpr int kChunkTiles = 4;
+constexpr uint32_t kSpinLimit = 1u << 25;  // bounded dependency wait
+
+juqcs_status fail(juqcs_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+juqcs_status hip_fail(hipError_t e, const char* where) {
+  set_error(std::string(where) + ": " + hipGetErrorString(e));
+  return JUQCS_ERR_HIP;
+}
+
+int tile_bits_for(int n) { return std::min(n, batch_max_bits()); }
+int low_bits_for(int n) { return std::min(7, tile_bits_for(n)); }
+
+// Modelled time (arbitrary units ~ picoseconds per amplitude) of a plan:
+// every pass moves the state once (the first one only writes it), every op
+// sweeps the tile in LDS and costs 2^k complex MACs per amplitude.
+double plan_cost(const TilePlan& p) {
+  constexpr double kMem = 2.9, kSweep = 0.2, kMac = 0.05;
+  double c = 0.0;
+  for (size_t i = 0; i < p.passes.size(); ++i) {
+    double ops = 0.0;
+    for (int o = 0; o < p.passes[i].op_count; ++o) {
+      const TileOp& op = p.ops[p.passes[i].op_begin + o];
+      const int k = op.kind == TOP_DENSE1 ? 1 : op.kind == TOP_DENSE2 ? 2 : op.kind == TOP_DIAG2 ? 0
+                    : op.kind == TOP_DENSE3 ? 3 : 4;
+      ops += kSweep + kMac * (k ? (4 << k) : 1);
+    }
+    const double mem = i == 0 ? 0.5 * kMem : kMem;
+    c += std::max(mem, ops);
+  }
+  return c;
+}
+
+void plan_circuit(int n, const std::vector<Gate>& g, int kin, TilePlan* plan) {
+  const int b = tile_bits_for(n);
+  plan_tiles(n, low_bits_for(n), b, 0, g, plan, kin);
+  if (plan->passes.empty()) {  // no gates: one pass that writes |0...0>
+    TilePass p{};
+    p.g.n = n;
+    p.g.b = b;
+    p.g.L = b;
+    p.g.H = 0;
+    p.g.maxk = 1;
+    p.op_begin = 0;
+    p.op_count = 0;
+    plan->passes.push_back(p);
+  }
+}
+
+}  // namespace
+
 struct juqcs_batch {
-  int dummy;
+  int count = 0;
+  std::vector<int32_t> n;
+  std::vector<uint64_t> state_off;
+  char* states = nullptr;
+  char* dbuf = nullptr;
+  BatchDevice dev{};
+  uint64_t* d_state_off = nullptr;
+  int32_t* d_nq = nullptr;
+  int64_t tasks = 0, gate_apps = 0, passes = 0;
+  std::vector<int> kin;  // chosen on-chip fusion width per circuit
+  hipStream_t last_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t graph_stream = nullptr;
 };
 
-extern "C" {
+namespace {
 
-juqcs_status juqcs_batch_create(juqcs_batch** out, int, const int*, const juqcs_gate*,
-                                const int64_t*, void*, const uint64_t*, const juqcs_plan_opts*) {
-  if (out) *out = nullptr;
-  set_error("batch execution not built yet");
-  return JUQCS_ERR_UNSUPPORTED;
+void free_batch(juqcs_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->dbuf) (void)hipFree(b->dbuf);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->dbuf = nullptr;
 }
 
-juqcs_status juqcs_batch_run(juqcs_batch*, void*) {
-  set_error("batch execution not built yet");
-  return JUQCS_ERR_UNSUPPORTED;
-}
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-juqcs_status juqcs_batch_stats(const juqcs_batch*, int64_t*, int64_t*, int64_t*) {
-  set_error("batch execution not built yet");
-  return JUQCS_ERR_UNSUPPORTED;
-}
-
-juqcs_status juqcs_batch_destroy(juqcs_batch* b) {
-  delete b;
+// Lays the plans out as one device work list (pass-major groups).
+juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
+  std::vector<BatchPass> passes;
+  std::vector<TileOp> ops;
+  std::vector<cplx<float>> mats;
+  std::vector<BatchGroup> groups;
+  std::vector<int> first_pass(B->count);
+  B->tasks = B->gate_apps = B->passes = 0;
+  for (int c = 0; c < B->count; ++c) {
+    const TilePlan& p = plans[c];
+    first_pass[c] = (int)passes.size();
+    const int64_t op0 = (int64_t)ops.size(), m0 = (int64_t)mats.size();
+    for (const TilePass& tp : p.passes) {
+      BatchPass bp;
+      bp.g = tp.g;
+      bp.op_begin = (int32_t)(op0 + tp.op_begin);
+      bp.op_count = tp.op_count;
+      passes.push_back(bp);
+    }
+    for (TileOp op : p.ops) {
+      op.moff += m0;
+      ops.push_back(op);
+    }
+    for (const C& z : p.mats) mats.push_back({(float)z.re, (float)z.im});
+    const int b = p.passes[0].g.b;
+    const int64_t ntiles = int64_t(1) << (B->n[c] - b);
+    const int chunk = (int)std::min<int64_t>(ntiles, kChunkTiles);
+    for (int i = 0; i < (int)p.passes.size(); ++i) {
+      BatchGroup g{};
+      g.state_off = B->state_off[c];
+      g.circuit = c;
+      g.pass = first_pass[c] + i;
+      g.chunk_tiles = chunk;
+      g.wait_target = (int32_t)(i * ntiles);
+      g.init = i == 0 ? 1 : 0;
+      groups.push_back(g);
+    }
+    B->tasks += ntiles * (int64_t)p.passes.size();
+    B->passes += (int64_t)p.passes.size();
+    B->gate_apps += p.gates;
+  }
+  // pass-major order: pass index within the circuit, then circuit
+  std::stable_sort(groups.begin(), groups.end(), [&](const BatchGroup& a, const BatchGroup& b) {
+    return (a.pass - first_pass[a.circuit]) < (b.pass - first_pass[b.circuit]);
+  });
+  long long next = 0;
+  for (BatchGroup& g : groups) {
+    g.first_chunk = next;
+    const int b = passes[g.pass].g.b;
+    const int64_t ntiles = int64_t(1) << (B->n[g.circuit] - b);
+    next += ntiles / g.chunk_tiles;
+  }
+  // one device buffer for everything
+  const size_t o_groups = 0;
+  const size_t o_passes = align256(o_groups + groups.size() * sizeof(BatchGroup));
+  const size_t o_ops = align256(o_passes + passes.size() * sizeof(BatchPass));
+  const size_t o_mats = align256(o_ops + std::max<size_t>(ops.size(), 1) * sizeof(TileOp));
+  const size_t o_done = align256(o_mats + std::max<size_t>(mats.size(), 1) * sizeof(cplx<float>));
+  const size_t o_ticket = align256(o_done + B->count * sizeof(uint32_t));
+  const size_t o_err = align256(o_ticket + sizeof(uint64_t));
+  const size_t o_soff = align256(o_err + sizeof(uint32_t));
+  const size_t o_nq = align256(o_soff + B->count * sizeof(uint64_t));
+  const size_t total = align256(o_nq + B->count * sizeof(int32_t));
+  std::vector<char> host(total, 0);
+  std::memcpy(host.data() + o_groups, groups.data(), groups.size() * sizeof(BatchGroup));
+  std::memcpy(host.data() + o_passes, passes.data(), passes.size() * sizeof(BatchPass));
+  std::memcpy(host.data() + o_ops, ops.data(), ops.size() * sizeof(TileOp));
+  std::memcpy(host.data() + o_mats, mats.data(), mats.size() * sizeof(cplx<float>));
+  std::memcpy(host.data() + o_soff, B->state_off.data(), B->count * sizeof(uint64_t));
+  std::memcpy(host.data() + o_nq, B->n.data(), B->count * sizeof(int32_t));
+  hipError_t e = hipMalloc((void**)&B->dbuf, total);
+  if (e != hipSuccess) return hip_fail(e, "batch hipMalloc");
+  e = hipMemcpy(B->dbuf, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch upload");
+  BatchDevice& d = B->dev;
+  d.groups = (const BatchGroup*)(B->dbuf + o_groups);
+  d.ngroups = (int)groups.size();
+  d.passes = (const BatchPass*)(B->dbuf + o_passes);
+  d.ops = (const TileOp*)(B->dbuf + o_ops);
+  d.mats = (const cplx<float>*)(B->dbuf + o_mats);
+  d.done = (uint32_t*)(B->dbuf + o_done);
+  d.ticket = (uint64_t*)(B->dbuf + o_ticket);
+  d.err = (uint32_t*)(B->dbuf + o_err);
+  d.count = B->count;
+  d.nchunks = next;
+  d.spin_limit = kSpinLimit;
+  B->d_state_off = (uint64_t*)(B->dbuf + o_soff);
+  B->d_nq = (int32_t*)(B->dbuf + o_nq);
   return JUQCS_OK;
 }
 
-juqcs_status juqcs_branch_amplitudes(int, const juqcs_gate*, size_t, const uint8_t*,
-                                     const uint64_t*, size_t, int, double*, void*) {
-  set_error("branch decomposition not built yet");
-  return JUQCS_ERR_UNSUPPORTED;
+juqcs_status run_device(juqcs_batch* B, hipStream_t s) {
+  hipError_t e = launch_batch(B->states, B->dev, s);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  return JUQCS_OK;
+}
+
+// Timed trial of one circuit's plan (used by the autotuner): runs it as a
+// one-circuit batch on the circuit's own state buffer.
+double time_plan(char* states, uint64_t off, int n, const TilePlan& plan, hipStream_t s) {
+  juqcs_batch B;
+  B.count = 1;
+  B.n = {n};
+  B.state_off = {off};
+  B.states = states;
+  std::vector<TilePlan> plans{plan};
+  if (build_device(&B, plans) != JUQCS_OK) {
+    free_batch(&B);
+    return 1e30;
+  }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  (void)run_device(&B, s);  // warm
+  (void)hipEventRecord(a, s);
+  (void)run_device(&B, s);
+  (void)hipEventRecord(b, s);
+  (void)hipEventSynchronize(b);
+  float ms = 1e30f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  free_batch(&B);
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
+                                const juqcs_gate* gates, const int64_t* offsets, void* d_states,
+                                const uint64_t* state_offset, const juqcs_plan_opts* opts) {
+  if (!out) return fail(JUQCS_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  if (count < 1) return fail(JUQCS_ERR_ARG, "count must be >= 1");
+  if (!n || !offsets || !d_states || !state_offset) return fail(JUQCS_ERR_ARG, "null argument");
+  if (offsets[0] != 0) return fail(JUQCS_ERR_ARG, "offsets[0] must be 0");
+  for (int c = 0; c < count; ++c) {
+    if (n[c] < 1 || n[c] > 30) return fail(JUQCS_ERR_ARG, "batch circuits need 1 <= n <= 30");
+    if (offsets[c + 1] < offsets[c]) return fail(JUQCS_ERR_ARG, "offsets must not decrease");
+    if (state_offset[c] & 15) return fail(JUQCS_ERR_ARG, "state offsets must be 16-byte aligned");
+  }
+  if (offsets[count] > 0 && !gates) return fail(JUQCS_ERR_ARG, "null gate array");
+  const int fuse = opts ? opts->fuse_k : 0;
+  const bool autotune = opts && opts->autotune;
+  if (fuse < 0 || fuse > 4) return fail(JUQCS_ERR_ARG, "batch fuse_k must be 0 (auto) or 1..4");
+  auto* B = new juqcs_batch();
+  B->count = count;
+  B->n.assign(n, n + count);
+  B->state_off.assign(state_offset, state_offset + count);
+  B->states = (char*)d_states;
+  B->kin.assign(count, 2);
+  std::vector<TilePlan> plans(count);
+  std::vector<std::vector<Gate>> dec(count);
+  std::string err;
+  for (int c = 0; c < count; ++c) {
+    dec[c].resize(offsets[c + 1] - offsets[c]);
+    for (int64_t i = offsets[c]; i < offsets[c + 1]; ++i)
+      if (!decode_gate(gates[i], n[c], &dec[c][i - offsets[c]], &err)) {
+        delete B;
+        const bool numeric = err.find("non-finite") != std::string::npos;
+        return fail(numeric ? JUQCS_ERR_NUMERIC : JUQCS_ERR_QUBIT,
+                    "circuit " + std::to_string(c) + ": " + err);
+      }
+  }
+  // fusion width: fixed, modelled, or measured (one trial per qubit count)
+  std::map<int, int> measured;
+  for (int c = 0; c < count; ++c) {
+    if (fuse > 0) {
+      plan_circuit(n[c], dec[c], fuse, &plans[c]);
+      B->kin[c] = fuse;
+      continue;
+    }
+    if (autotune) {
+      auto it = measured.find(n[c]);
+      if (it == measured.end()) {
+        double best = 1e30;
+        int bk = 2;
+        for (int k = 1; k <= 4; ++k) {
+          TilePlan p;
+          plan_circuit(n[c], dec[c], k, &p);
+          const double t = time_plan(B->states, B->state_off[c], n[c], p, nullptr);
+          if (t < best) {
+            best = t;
+            bk = k;
+          }
+        }
+        it = measured.emplace(n[c], bk).first;
+      }
+      B->kin[c] = it->second;
+      plan_circuit(n[c], dec[c], it->second, &plans[c]);
+      continue;
+    }
+    double best = 1e300;
+    for (int k = 2; k <= 4; ++k) {
+      TilePlan p;
+      plan_circuit(n[c], dec[c], k, &p);
+      const double cst = plan_cost(p);
+      if (cst < best) {
+        best = cst;
+        plans[c] = std::move(p);
+        B->kin[c] = k;
+      }
+    }
+  }
+  juqcs_status rc = build_device(B, plans);
+  if (rc != JUQCS_OK) {
+    free_batch(B);
+    delete B;
+    return rc;
+  }
+  *out = B;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_run(juqcs_batch* B, void* hip_stream) {
+  if (!B) return fail(JUQCS_ERR_ARG, "null batch");
+  hipStream_t s = (hipStream_t)hip_stream;
+  B->last_stream = s;
+  if (!s) return run_device(B, s);  // the legacy default stream cannot be captured
+  if (!B->gexec || B->graph_stream != s) {
+    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->gexec = nullptr;
+    B->graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    juqcs_status rc = run_device(B, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (rc != JUQCS_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    B->graph = g;
+    e = hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    B->graph_stream = s;
+  }
+  hipError_t e = hipGraphLaunch(B->gexec, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_wait(juqcs_batch* B) {
+  if (!B) return fail(JUQCS_ERR_ARG, "null batch");
+  hipError_t e = hipStreamSynchronize(B->last_stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  uint32_t flag = 0;
+  e = hipMemcpy(&flag, B->dev.err, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "error flag read");
+  if (flag) return fail(JUQCS_ERR_HIP, "a batch dependency wait exceeded its spin limit");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_stats(const juqcs_batch* B, int64_t* tasks, int64_t* gate_apps,
+                               int64_t* passes) {
+  if (!B) return fail(JUQCS_ERR_ARG, "null batch");
+  if (tasks) *tasks = B->tasks;
+  if (gate_apps) *gate_apps = B->gate_apps;
+  if (passes) *passes = B->passes;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_fusion(const juqcs_batch* B, int* kin) {
+  if (!B || !kin) return fail(JUQCS_ERR_ARG, "null argument");
+  for (int c = 0; c < B->count; ++c) kin[c] = B->kin[c];
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_amplitudes(juqcs_batch* B, const uint64_t* idx, int m, double* out,
+                                    void* hip_stream) {
+  if (!B) return fail(JUQCS_ERR_ARG, "null batch");
+  if (m < 0 || (m > 0 && (!idx || !out))) return fail(JUQCS_ERR_ARG, "bad index list");
+  const size_t total = (size_t)B->count * m;
+  if (total == 0) return JUQCS_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  uint64_t* d_idx = nullptr;
+  double* d_out = nullptr;
+  hipError_t e = hipMalloc((void**)&d_idx, total * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_out, total * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(d_idx, idx, total * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_batch_gather(B->states, B->d_state_off, B->d_nq, B->count, m, d_idx, d_out, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, d_out, total * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_idx);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(e, "batch amplitudes");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_norms(juqcs_batch* B, double* out, void* hip_stream) {
+  if (!B || !out) return fail(JUQCS_ERR_ARG, "null argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* d_out = nullptr;
+  hipError_t e = hipMalloc((void**)&d_out, B->count * sizeof(double));
+  if (e == hipSuccess) e = launch_batch_norms(B->states, B->d_state_off, B->d_nq, B->count, d_out, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, d_out, B->count * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(e, "batch norms");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_destroy(juqcs_batch* B) {
+  if (!B) return JUQCS_OK;
+  if (B->last_stream) (void)hipStreamSynchronize(B->last_stream);
+  free_batch(B);
+  delete B;
+  return JUQCS_OK;
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Entangling-gate decomposition (Section 4)
+// ---------------------------------------------------------------------------
+namespace {
+
+// One term factor of Eq. (2) on a single qubit: exp(i sigma^z (x s - pi/4)),
+// x = pi/4 - (i/2) asinh(1) (a solution of cos(2x) = i).
+void branch_diag(int s, C* d) {
+  const std::complex<double> x(M_PI / 4.0, -0.5 * std::asinh(1.0));
+  const std::complex<double> a = std::complex<double>(0.0, 1.0) * (x * (double)s - M_PI / 4.0);
+  const std::complex<double> e0 = std::exp(a), e1 = std::exp(-a);
+  d[0] = {e0.real(), e0.imag()};
+  d[1] = {0, 0};
+  d[2] = {0, 0};
+  d[3] = {e1.real(), e1.imag()};
+}
+
+}  // namespace
+
+extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count,
+                                                const uint8_t* side, const uint64_t* z,
+                                                size_t count, int group_size, double* out,
+                                                void* hip_stream) {
+  if (n < 2 || n > 62) return fail(JUQCS_ERR_ARG, "n must be in [2, 62]");
+  if (!side || (count > 0 && (!z || !out)) || (gate_count > 0 && !gates))
+    return fail(JUQCS_ERR_ARG, "null argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  // parts and local qubit numbers (ascending order inside a part)
+  int local[64], nloc[2] = {0, 0};
+  for (int q = 0; q < n; ++q) {
+    if (side[q] > 1) return fail(JUQCS_ERR_ARG, "side[q] must be 0 or 1");
+    local[q] = nloc[side[q]]++;
+  }
+  if (nloc[0] < 1 || nloc[1] < 1 || nloc[0] > 30 || nloc[1] > 30)
+    return fail(JUQCS_ERR_ARG, "each part needs 1..30 qubits");
+  for (size_t k = 0; k < count; ++k)
+    if ((z[k] >> n) != 0) return fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
+  // half circuits with placeholder diagonals at every crossing CZ
+  std::vector<Gate> half[2];
+  std::vector<std::pair<int, int>> slot[2];  // (gate index in half, crossing number)
+  int m = 0;
+  std::string err;
+  for (size_t i = 0; i < gate_count; ++i) {
+    Gate g;
+    if (!decode_gate(gates[i], n, &g, &err)) {
+      const bool numeric = err.find("non-finite") != std::string::npos;
+      return fail(numeric ? JUQCS_ERR_NUMERIC : JUQCS_ERR_QUBIT,
+                  "gate " + std::to_string(i) + ": " + err);
+    }
+    if (g.nq == 2 && side[g.q[0]] != side[g.q[1]]) {
+      if (gates[i].op != JUQCS_OP_CZ)
+        return fail(JUQCS_ERR_UNSUPPORTED, "only CZ gates may cross the cut");
+      for (int j = 0; j < 2; ++j) {
+        const int q = g.q[j], p = side[q];
+        Gate d{};
+        d.nq = 1;
+        d.q[0] = local[q];
+        d.q[1] = -1;
+        branch_diag(1, d.m);
+        d.diag = true;
+        slot[p].push_back({(int)half[p].size(), m});
+        half[p].push_back(d);
+      }
+      ++m;
+      continue;
+    }
+    const int p = side[g.q[0]];
+    for (int j = 0; j < g.nq; ++j) g.q[j] = local[g.q[j]];
+    half[p].push_back(g);
+  }
+  if (m > 20) return fail(JUQCS_ERR_UNSUPPORTED, "at most 20 crossing CZ gates");
+  const long long nb = 1ll << m;
+  // template plans, one per half; branches only change the diagonal values
+  TilePlan tmpl[2];
+  for (int p = 0; p < 2; ++p) plan_circuit(nloc[p], half[p], 2, &tmpl[p]);
+  // bitstring halves
+  std::vector<uint64_t> zh[2];
+  for (int p = 0; p < 2; ++p) zh[p].resize(count);
+  for (size_t k = 0; k < count; ++k) {
+    uint64_t a = 0, b = 0;
+    for (int q = 0; q < n; ++q) {
+      const uint64_t bit = (z[k] >> q) & 1;
+      if (side[q]) b |= bit << local[q];
+      else a |= bit << local[q];
+    }
+    zh[0][k] = a;
+    zh[1][k] = b;
+  }
+  // group size: half-states resident at a time (two per branch)
+  const size_t sbytes[2] = {(size_t)8 << nloc[0], (size_t)8 << nloc[1]};
+  size_t per_branch = align256(sbytes[0]) + align256(sbytes[1]);
+  long long G = group_size > 0 ? group_size : 0;
+  if (G == 0) {
+    size_t freeb = 0, totalb = 0;
+    (void)hipMemGetInfo(&freeb, &totalb);
+    const size_t budget = std::min<size_t>(freeb / 2, (size_t)64 << 30);
+    G = std::max<long long>(1, (long long)(budget / per_branch));
+  }
+  G = std::min(G, nb);
+  char* states = nullptr;
+  double *dA = nullptr, *dB = nullptr, *dOut = nullptr;
+  uint64_t* dz = nullptr;
+  hipError_t e = hipMalloc((void**)&states, per_branch * G);
+  if (e == hipSuccess) e = hipMalloc((void**)&dA, nb * std::max<size_t>(count, 1) * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dB, nb * std::max<size_t>(count, 1) * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dOut, std::max<size_t>(count, 1) * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dz, 2 * G * std::max<size_t>(count, 1) * sizeof(uint64_t));
+  juqcs_status rc = JUQCS_OK;
+  if (e != hipSuccess) rc = hip_fail(e, "branch hipMalloc");
+  std::vector<uint64_t> zlist;
+  for (long long b0 = 0; rc == JUQCS_OK && b0 < nb; b0 += G) {
+    const long long g = std::min(G, nb - b0);
+    juqcs_batch B;
+    B.count = (int)(2 * g);
+    std::vector<TilePlan> plans(B.count);
+    zlist.assign((size_t)B.count * count, 0);
+    for (long long j = 0; j < g; ++j) {
+      const long long br = b0 + j;
+      for (int p = 0; p < 2; ++p) {
+        std::vector<Gate> hg = half[p];
+        for (auto& sl : slot[p]) branch_diag(((br >> sl.second) & 1) ? -1 : 1, hg[sl.first].m);
+        TilePlan pl = tmpl[p];
+        rebuild_mats(hg, &pl);
+        // circuits [0, g): first part of each branch, [g, 2g): second part
+        const int c = (int)(p * g + j);
+        plans[c] = std::move(pl);
+        std::memcpy(zlist.data() + (size_t)c * count, zh[p].data(), count * sizeof(uint64_t));
+      }
+    }
+    B.n.assign(B.count, 0);
+    B.state_off.assign(B.count, 0);
+    uint64_t off = 0;
+    for (int c = 0; c < B.count; ++c) {
+      const int p = c < g ? 0 : 1;
+      B.n[c] = nloc[p];
+      B.state_off[c] = off;
+      off += align256(sbytes[p]);
+    }
+    B.states = states;
+    rc = build_device(&B, plans);
+    if (rc == JUQCS_OK) rc = run_device(&B, s);
+    if (rc == JUQCS_OK && count > 0) {
+      e = hipMemcpyAsync(dz, zlist.data(), zlist.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+      // gather into a temporary, then scatter rows to A / B (branch-major)
+      double* tmp = nullptr;
+      if (e == hipSuccess) e = hipMalloc((void**)&tmp, (size_t)B.count * count * 2 * sizeof(double));
+      if (e == hipSuccess)
+        e = launch_batch_gather(B.states, B.d_state_off, B.d_nq, B.count, (int)count, dz, tmp, s);
+      const size_t rows = (size_t)g * count * 2 * sizeof(double);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dA + (size_t)b0 * count * 2, tmp, rows, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dB + (size_t)b0 * count * 2, tmp + (size_t)g * count * 2, rows,
+                           hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (tmp) (void)hipFree(tmp);
+      if (e != hipSuccess) rc = hip_fail(e, "branch gather");
+    }
+    if (rc == JUQCS_OK) {
+      e = hipStreamSynchronize(s);
+      uint32_t flag = 0;
+      if (e == hipSuccess) e = hipMemcpy(&flag, B.dev.err, sizeof(flag), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) rc = hip_fail(e, "branch batch");
+      else if (flag) rc = fail(JUQCS_ERR_HIP, "a batch dependency wait exceeded its spin limit");
+    }
+    free_batch(&B);
+  }
+  if (rc == JUQCS_OK && count > 0) {
+    e = launch_branch_reduce(dA, dB, nb, (int)count, std::ldexp(1.0, -m), dOut, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out, dOut, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "branch reduce");
+  }
+  (void)hipFree(states);
+  (void)hipFree(dA);
+  (void)hipFree(dB);
+  (void)hipFree(dOut);
+  (void)hipFree(dz);
+  return rc;
+}

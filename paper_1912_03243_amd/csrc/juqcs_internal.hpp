@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -27,11 +28,13 @@ template <typename T>
 __host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
-// acc + a*b
+// acc + a*b as four fused multiply-adds (one rounding each)
 template <typename T>
 __host__ __device__ inline cplx<T> cmad(cplx<T> a, cplx<T> b, cplx<T> acc) {
-  acc.re += a.re * b.re - a.im * b.im;
-  acc.im += a.re * b.im + a.im * b.re;
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
   return acc;
 }
 
@@ -62,13 +65,15 @@ struct TileGeom {
   int32_t n, L, H, b;
   int32_t hbits[kHbitsCap];      // ascending physical positions (>= L)
   int32_t block_bits;            // ENC2 only
-  int32_t pad;
+  int32_t maxk;                  // widest op of the pass (1..4)
 };
 
 enum TileOpKind : int32_t {
   TOP_DENSE1 = 0,  // 2x2 on local bit a
   TOP_DENSE2 = 1,  // 4x4 on local bits (a, b), index b_a + 2 b_b
   TOP_DIAG2 = 2,   // phases d[b_a + 2 b_b] (b may equal -1: d[b_a])
+  TOP_DENSE3 = 3,  // 8x8 on local bits bits[0..3) (matrix order)
+  TOP_DENSE4 = 4,  // 16x16 on local bits bits[0..4)
 };
 
 struct TileOp {
@@ -130,6 +135,48 @@ hipError_t launch_pauli(juqcs_dtype dt, const void* amps, const void* scales, in
                         hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Batches (k_batch.hip, batch.cpp)
+// ---------------------------------------------------------------------------
+struct BatchPass {  // one tile pass of one circuit
+  TileGeom g;
+  int32_t op_begin, op_count;
+};
+
+struct BatchGroup {  // every tile of one pass of one circuit
+  uint64_t state_off;    // byte offset of the circuit's C64 state
+  int64_t first_chunk;   // first ticket of this group
+  int32_t circuit;
+  int32_t pass;          // index into the BatchPass array
+  int32_t chunk_tiles;   // tiles claimed per ticket
+  int32_t wait_target;   // finished tiles of the circuit required first
+  int32_t init;          // 1: start from |0...0> instead of loading
+  int32_t pad;
+};
+
+struct BatchDevice {
+  const BatchGroup* groups;
+  int ngroups;
+  const BatchPass* passes;
+  const TileOp* ops;
+  const cplx<float>* mats;
+  uint32_t* done;
+  uint64_t* ticket;
+  uint32_t* err;
+  int count;
+  long long nchunks;
+  uint32_t spin_limit;
+};
+
+int batch_max_bits();
+hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s);
+hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, const int32_t* nq,
+                               int count, int m, const uint64_t* idx, double* out, hipStream_t s);
+hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, const int32_t* nq,
+                              int count, double* out, hipStream_t s);
+hipError_t launch_branch_reduce(const double* A, const double* B, long long nb, int m,
+                                double scale, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Host-side planning (planner.cpp)
 // ---------------------------------------------------------------------------
 struct Gate {  // decoded gate: matrix on 1 or 2 qubits (physical positions)
@@ -145,13 +192,20 @@ struct TilePlan {
   std::vector<TilePass> passes;
   std::vector<TileOp> ops;
   std::vector<cplx<double>> mats;
+  // for every op: the gates folded into it, in merge order, so the matrices
+  // can be rebuilt for gates with other values but the same structure
+  std::vector<std::vector<int>> op_gates;
   int64_t gates = 0;
 };
+
+// Recomputes every op matrix of plan from gates (same qubits and zero
+// pattern as the gates the plan was made for).
+void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan);
 
 // Plans tile passes for gates (physical qubits).  L, b: low contiguous bits
 // and total tile bits.  fixed_low: the low L bits are always tile bits.
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan);
+                TilePlan* plan, int kin = 2);
 
 struct FusedBlock {
   std::vector<int> targets;           // physical

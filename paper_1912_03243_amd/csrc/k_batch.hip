@@ -1,0 +1,254 @@
+// One persistent launch for many independent circuits (and for the branch
+// simulations of the entangling-gate decomposition, Section 4, whose terms
+// are independent: the paper spreads them over MPI ranks and OpenMP threads,
+// here they are work items of one kernel).
+//
+// Work list: a "group" is one tile pass of one circuit (2^(n-b) tiles); its
+// tiles are claimed in chunks through a global ticket counter.  Groups are
+// ordered pass-major (every circuit's pass 0, then every pass 1, ...), so a
+// chunk of pass p only waits for pass p-1 of its own circuit, which was
+// claimed earlier by a running workgroup: the wait always ends.  A per-
+// circuit counter of finished tiles carries the dependency (agent-scope
+// release after the stores, acquire before the loads); the wait is bounded
+// and raises an error flag instead of spinning forever.
+#include "tile_ops.hpp"
+
+namespace juqcs {
+
+namespace {
+
+using tileops::kThreads;
+using tileops::run_ops;
+
+constexpr int kBatchMaxBits = 13;  // 64 KiB of C64 amplitudes per tile
+
+__device__ inline uint64_t tile_base_hb(uint64_t tau, int L, int H, const int* hb) {
+  uint64_t base = tau << L;
+  for (int j = 0; j < H; ++j) base = insert_zero(base, hb[j]);
+  return base;
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_reset(uint32_t* __restrict__ done, int count,
+                                                          unsigned long long* __restrict__ ticket,
+                                                          uint32_t* __restrict__ err) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < count) done[i] = 0u;
+  if (i == 0) {
+    *ticket = 0ull;
+    *err = 0u;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch(
+    char* __restrict__ states, const BatchGroup* __restrict__ groups, int ngroups,
+    const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
+    const cplx<float>* __restrict__ mats, uint32_t* __restrict__ done,
+    unsigned long long* __restrict__ ticket, long long nchunks, uint32_t* __restrict__ err,
+    uint32_t spin_limit) {
+  __shared__ cplx<float> sh[1 << kBatchMaxBits];
+  __shared__ uint64_t choff[1 << kMaxGather];
+  __shared__ int hb[kHbitsCap];
+  __shared__ long long s_t;
+  __shared__ int s_g;
+  int cur_pass = -1;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const long long t = (long long)atomicAdd(ticket, 1ull);
+      int g = -1;
+      if (t < nchunks) {  // last group whose first chunk is <= t
+        int lo = 0, hi = ngroups - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (groups[mid].first_chunk <= t) lo = mid;
+          else hi = mid - 1;
+        }
+        g = lo;
+      }
+      s_t = t;
+      s_g = g;
+    }
+    __syncthreads();
+    const long long t = s_t;
+    const int gi = s_g;
+    if (gi < 0) break;  // every workgroup leaves once the tickets run out
+    const BatchGroup grp = groups[gi];
+    // wait for the circuit's previous pass (bounded)
+    if (grp.wait_target > 0) {
+      if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&done[grp.circuit], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+               (uint32_t)grp.wait_target) {
+          if (++spins > spin_limit) {
+            atomicOr(err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(4);
+        }
+      }
+      __syncthreads();
+      __threadfence();
+    }
+    const BatchPass ps = passes[grp.pass];
+    const int b = ps.g.b, L = ps.g.L, H = ps.g.H, lmask = (1 << L) - 1;
+    if (grp.pass != cur_pass) {
+      if (threadIdx.x < kHbitsCap) hb[threadIdx.x] = threadIdx.x < H ? ps.g.hbits[threadIdx.x] : 0;
+      __syncthreads();
+      for (int c = threadIdx.x; c < (1 << H); c += kThreads) {
+        uint64_t o = 0;
+        for (int j = 0; j < H; ++j) o |= (uint64_t)((c >> j) & 1) << hb[j];
+        choff[c] = o;
+      }
+      __syncthreads();
+      cur_pass = grp.pass;
+    }
+    cplx<float>* psi = reinterpret_cast<cplx<float>*>(states + grp.state_off);
+    const int tile_amps = 1 << b;
+    const long long chunk = t - grp.first_chunk;
+    for (int j = 0; j < grp.chunk_tiles; ++j) {
+      const uint64_t tau = (uint64_t)chunk * grp.chunk_tiles + j;
+      const uint64_t base = tile_base_hb(tau, L, H, hb);
+      if (grp.init) {  // first pass: the state is |0...0>
+        for (int e = threadIdx.x; e < tile_amps; e += kThreads)
+          sh[e] = cplx<float>{(base == 0 && e == 0) ? 1.0f : 0.0f, 0.0f};
+      } else {
+        for (int e = threadIdx.x; e < tile_amps; e += kThreads)
+          sh[e] = psi[base + choff[e >> L] + (e & lmask)];
+      }
+      __syncthreads();
+      run_ops<float>(sh, b, ops + ps.op_begin, ps.op_count, mats);
+      for (int e = threadIdx.x; e < tile_amps; e += kThreads)
+        psi[base + choff[e >> L] + (e & lmask)] = sh[e];
+      __syncthreads();
+    }
+    // publish the finished tiles (release at agent scope)
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(&done[grp.circuit], (uint32_t)grp.chunk_tiles, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// out[c * m + k] = amplitude idx[c * m + k] of circuit c (FP64 pairs).
+__global__ __launch_bounds__(kThreads) void k_batch_gather(const char* __restrict__ states,
+                                                           const uint64_t* __restrict__ state_off,
+                                                           const int32_t* __restrict__ nq, int count,
+                                                           int m, const uint64_t* __restrict__ idx,
+                                                           double* __restrict__ out) {
+  const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= (long long)count * m) return;
+  const int c = (int)(k / m);
+  const uint64_t z = idx[k];
+  if ((z >> nq[c]) != 0) {
+    out[2 * k] = out[2 * k + 1] = __builtin_nan("");
+    return;
+  }
+  const cplx<float> v = reinterpret_cast<const cplx<float>*>(states + state_off[c])[z];
+  out[2 * k] = (double)v.re;
+  out[2 * k + 1] = (double)v.im;
+}
+
+// One block per circuit: sum |psi|^2 in FP64 with a fixed order.
+__global__ __launch_bounds__(kThreads) void k_batch_norms(const char* __restrict__ states,
+                                                          const uint64_t* __restrict__ state_off,
+                                                          const int32_t* __restrict__ nq,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[kThreads / 64];
+  const int c = blockIdx.x;
+  const cplx<float>* psi = reinterpret_cast<const cplx<float>*>(states + state_off[c]);
+  const uint64_t count = uint64_t(1) << nq[c];
+  double acc = 0.0;
+  for (uint64_t i = threadIdx.x; i < count; i += kThreads) {
+    const cplx<float> v = psi[i];
+    acc += (double)v.re * v.re + (double)v.im * v.im;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
+    out[c] = r;
+  }
+}
+
+// Eq. (3) with two parts: out[k] = scale * sum_b A[b][k] * B[b][k] (complex,
+// FP64), one block per requested coefficient, fixed-order tree over b.
+__global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __restrict__ A,
+                                                            const double* __restrict__ B,
+                                                            long long nb, int m, double scale,
+                                                            double* __restrict__ out) {
+  __shared__ double sre[kThreads], sim[kThreads];
+  const int k = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (long long b = threadIdx.x; b < nb; b += kThreads) {
+    const double ar = A[2 * (b * m + k)], ai = A[2 * (b * m + k) + 1];
+    const double br = B[2 * (b * m + k)], bi = B[2 * (b * m + k) + 1];
+    re += ar * br - ai * bi;
+    im += ar * bi + ai * br;
+  }
+  sre[threadIdx.x] = re;
+  sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sre[threadIdx.x] += sre[threadIdx.x + s];
+      sim[threadIdx.x] += sim[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * k] = scale * sre[0];
+    out[2 * k + 1] = scale * sim[0];
+  }
+}
+
+}  // namespace
+
+int batch_max_bits() { return kBatchMaxBits; }
+
+hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3((d.count + kThreads - 1) / kThreads + 1), dim3(kThreads), 0,
+                     s, d.done, d.count, (unsigned long long*)d.ticket, d.err);
+  static uint64_t slots = 0;
+  if (slots == 0) {
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch, kThreads, 0) !=
+            hipSuccess ||
+        per < 1)
+      per = 1;
+    slots = (uint64_t)cus * per;
+  }
+  const uint64_t grid = d.nchunks < (long long)slots ? (uint64_t)d.nchunks : slots;
+  hipLaunchKernelGGL(k_batch, dim3((unsigned)(grid ? grid : 1)), dim3(kThreads), 0, s, states,
+                     d.groups, d.ngroups, d.passes, d.ops, d.mats, d.done,
+                     (unsigned long long*)d.ticket, d.nchunks, d.err, d.spin_limit);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, const int32_t* nq,
+                               int count, int m, const uint64_t* idx, double* out, hipStream_t s) {
+  const long long total = (long long)count * m;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)((total + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, states, state_off, nq, count, m, idx, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, const int32_t* nq,
+                              int count, double* out, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_norms, dim3(count), dim3(kThreads), 0, s, states, state_off, nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_branch_reduce(const double* A, const double* B, long long nb, int m, double scale,
+                                double* out, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_branch_reduce, dim3(m), dim3(kThreads), 0, s, A, B, nb, m, scale, out);
+  return hipGetLastError();
+}
+
+}  // namespace juqcs

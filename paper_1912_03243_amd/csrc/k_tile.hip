@@ -12,13 +12,15 @@
 #include <mutex>
 #include <unordered_map>
 
-#include "juqcs_internal.hpp"
+#include "tile_ops.hpp"
 
 namespace juqcs {
 
 namespace {
 
-constexpr int kThreads = 256;
+using tileops::kThreads;
+using tileops::run_ops;
+using tileops::diag_pick;
 
 template <typename T>
 struct TileCfg;
@@ -35,86 +37,6 @@ __device__ inline uint64_t tile_base(uint64_t tau, const TileGeom& g) {
   uint64_t base = tau << g.L;
   for (int j = 0; j < g.H; ++j) base = insert_zero(base, g.hbits[j]);
   return base;
-}
-
-// ---------------------------------------------------------------- ops ----
-// d[b_a + 2 b_c] with selects only (a table lookup would go through scratch).
-template <typename T>
-__device__ inline cplx<T> diag_pick(int e, int a, int c, cplx<T> d0, cplx<T> d1, cplx<T> d2,
-                                    cplx<T> d3) {
-  const bool x = (e >> a) & 1;
-  const bool y = c >= 0 && ((e >> c) & 1);
-  cplx<T> lo, hi;
-  lo.re = x ? d1.re : d0.re;
-  lo.im = x ? d1.im : d0.im;
-  hi.re = x ? d3.re : d2.re;
-  hi.im = x ? d3.im : d2.im;
-  cplx<T> r;
-  r.re = y ? hi.re : lo.re;
-  r.im = y ? hi.im : lo.im;
-  return r;
-}
-
-template <typename T>
-__device__ inline void op_dense1(cplx<T>* sh, int b, int a, const cplx<T>* __restrict__ m) {
-  const cplx<T> u0 = m[0], u1 = m[1], u2 = m[2], u3 = m[3];
-  const int npairs = 1 << (b - 1);
-  const int abit = 1 << a;
-  for (int p = threadIdx.x; p < npairs; p += kThreads) {
-    const int i0 = (int)insert_zero((uint64_t)p, a);
-    const cplx<T> x = sh[i0], y = sh[i0 | abit];
-    sh[i0] = cmad(u1, y, cmul(u0, x));
-    sh[i0 | abit] = cmad(u3, y, cmul(u2, x));
-  }
-}
-
-template <typename T>
-__device__ inline void op_dense2(cplx<T>* sh, int b, int a, int c, const cplx<T>* __restrict__ m) {
-  cplx<T> u[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) u[i] = m[i];
-  const int lo = a < c ? a : c, hi = a < c ? c : a;
-  const int ba = 1 << a, bc = 1 << c;
-  const int nq = 1 << (b - 2);
-  for (int p = threadIdx.x; p < nq; p += kThreads) {
-    const int i = (int)insert_zero(insert_zero((uint64_t)p, lo), hi);
-    const int idx[4] = {i, i | ba, i | bc, i | ba | bc};
-    cplx<T> v[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = sh[idx[r]];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      cplx<T> acc = cmul(u[4 * r], v[0]);
-#pragma unroll
-      for (int s = 1; s < 4; ++s) acc = cmad(u[4 * r + s], v[s], acc);
-      sh[idx[r]] = acc;
-    }
-  }
-}
-
-template <typename T>
-__device__ inline void op_diag2(cplx<T>* sh, int b, int a, int c, const cplx<T>* __restrict__ m) {
-  const cplx<T> d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
-  const int n = 1 << b;
-  for (int e = threadIdx.x; e < n; e += kThreads) {
-    sh[e] = cmul(diag_pick(e, a, c, d0, d1, d2, d3), sh[e]);
-  }
-}
-
-template <typename T>
-__device__ inline void run_ops(cplx<T>* sh, int b, const TileOp* __restrict__ ops, int nops,
-                               const cplx<T>* __restrict__ mats) {
-  for (int o = 0; o < nops; ++o) {
-    const TileOp op = ops[o];
-    const cplx<T>* m = mats + op.moff;
-    switch (op.kind) {
-      case TOP_DENSE1: op_dense1<T>(sh, b, op.a, m); break;
-      case TOP_DENSE2: op_dense2<T>(sh, b, op.a, op.b, m); break;
-      case TOP_DIAG2: op_diag2<T>(sh, b, op.a, op.b, m); break;
-      default: break;
-    }
-    __syncthreads();
-  }
 }
 
 // ------------------------------------------------------- C128 / C64 -------
@@ -429,12 +351,13 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
     const uint64_t slots = resident_blocks(kern, kFixedThreads);
     return dim3((unsigned)(ntiles < slots ? ntiles : slots));
   };
+  const bool fixed_ok = g.maxk <= 2;  // the pipelined kernels run 1- and 2-qubit ops
   if (dt == JUQCS_C128) {
     auto* p = (cplx<double>*)amps;
     auto* m = (const cplx<double>*)d_mats;
-    if (g.b == 12)
+    if (fixed_ok && g.b == 12)
       hipLaunchKernelGGL((k_tile_fixed<double, 12>), pgrid_for((const void*)k_tile_fixed<double, 12>), fblock, 0, s, p, g, d_ops, nops, m);
-    else if (g.b == 11)
+    else if (fixed_ok && g.b == 11)
       hipLaunchKernelGGL((k_tile_fixed<double, 11>), pgrid_for((const void*)k_tile_fixed<double, 11>), fblock, 0, s, p, g, d_ops, nops, m);
     else if (g.b <= 12)
       hipLaunchKernelGGL((k_tile<double, 12>), grid, block, 0, s, p, g, d_ops, nops, m);
@@ -443,11 +366,11 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
   } else if (dt == JUQCS_C64) {
     auto* p = (cplx<float>*)amps;
     auto* m = (const cplx<float>*)d_mats;
-    if (g.b == 13)
+    if (fixed_ok && g.b == 13)
       hipLaunchKernelGGL((k_tile_fixed<float, 13>), pgrid_for((const void*)k_tile_fixed<float, 13>), fblock, 0, s, p, g, d_ops, nops, m);
-    else if (g.b == 12)
+    else if (fixed_ok && g.b == 12)
       hipLaunchKernelGGL((k_tile_fixed<float, 12>), pgrid_for((const void*)k_tile_fixed<float, 12>), fblock, 0, s, p, g, d_ops, nops, m);
-    else if (g.b == 11)
+    else if (fixed_ok && g.b == 11)
       hipLaunchKernelGGL((k_tile_fixed<float, 11>), pgrid_for((const void*)k_tile_fixed<float, 11>), fblock, 0, s, p, g, d_ops, nops, m);
     else if (g.b <= 13)
       hipLaunchKernelGGL((k_tile<float, 13>), grid, block, 0, s, p, g, d_ops, nops, m);

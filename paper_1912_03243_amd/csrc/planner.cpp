@@ -70,6 +70,7 @@ bool is_diag(const C* m, int dim) {
 struct Cluster {
   std::vector<int> q;
   std::vector<C> m;
+  std::vector<int> gates;  // merge order
 };
 
 bool touches(const Cluster& c, const Gate& g) {
@@ -131,6 +132,7 @@ void fuse(const std::vector<Gate>& gates, const std::vector<int>& order, int kma
       chosen = (int)cl.size() - 1;
     }
     merge_into(cl[chosen], g);
+    cl[chosen].gates.push_back(gi);
   }
 }
 
@@ -258,19 +260,26 @@ void emit_ops(const std::vector<Cluster>& cl, const TileGeom& geom, TilePlan* pl
       op.a = local(c.q[0]);
       op.b = local(c.q[1]);
       for (int i = 0; i < 16; ++i) plan->mats.push_back(c.m[i]);
+    } else {
+      op.kind = k == 3 ? TOP_DENSE3 : TOP_DENSE4;
+      op.a = op.b = -1;
+      for (int j = 0; j < k; ++j) op.bits[j] = local(c.q[j]);
+      for (int i = 0; i < dim * dim; ++i) plan->mats.push_back(c.m[i]);
     }
     plan->ops.push_back(op);
+    plan->op_gates.push_back(c.gates);
   }
 }
 
 }  // namespace
 
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan) {
+                TilePlan* plan, int kin) {
   (void)block_bits;
   plan->passes.clear();
   plan->ops.clear();
   plan->mats.clear();
+  plan->op_gates.clear();
   plan->gates = (int64_t)gates.size();
   if (n <= b) {
     L = n;
@@ -280,7 +289,7 @@ void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& ga
   std::vector<int> rem(gates.size());
   for (size_t i = 0; i < gates.size(); ++i) rem[i] = (int)i;
   constexpr int kCandidates = 24;
-  const int kin = 2;  // on-chip fusion width
+  kin = std::max(1, std::min(kin, 4));  // on-chip fusion width
   while (!rem.empty()) {
     std::vector<char> in_tile(n, 0);
     for (int q = 0; q < L; ++q) in_tile[q] = 1;
@@ -352,8 +361,25 @@ void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& ga
     pass.op_begin = (int32_t)plan->ops.size();
     emit_ops(cl, pass.g, plan);
     pass.op_count = (int32_t)plan->ops.size() - pass.op_begin;
+    pass.g.maxk = 1;
+    for (const Cluster& c : cl) pass.g.maxk = std::max(pass.g.maxk, (int32_t)c.q.size());
     plan->passes.push_back(pass);
     rem.swap(keep);
+  }
+}
+
+void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan) {
+  for (size_t o = 0; o < plan->ops.size(); ++o) {
+    Cluster c;
+    for (int gi : plan->op_gates[o]) merge_into(c, gates[gi]);
+    const TileOp& op = plan->ops[o];
+    const int k = (int)c.q.size(), dim = 1 << k;
+    C* dst = plan->mats.data() + op.moff;
+    if (op.kind == TOP_DIAG2) {
+      for (int r = 0; r < 4; ++r) dst[r] = c.m[(r % dim) * dim + (r % dim)];
+    } else {
+      for (int i = 0; i < dim * dim; ++i) dst[i] = c.m[i];
+    }
   }
 }
 

@@ -40,7 +40,8 @@ PLANS = {"plain": PLAN_PLAIN, "tile": PLAN_TILE, "fused": PLAN_FUSED, "auto": PL
 class PlanOpts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("fuse_k", ct.c_int32), ("mma", ct.c_int32),
                 ("tile_bits", ct.c_int32), ("low_bits", ct.c_int32), ("profile", ct.c_int32),
-                ("reserved", ct.c_int32 * 2), ("passes", ct.c_int64), ("gates", ct.c_int64),
+                ("autotune", ct.c_int32), ("reserved", ct.c_int32), ("passes", ct.c_int64),
+                ("gates", ct.c_int64),
                 ("kernel_ms", ct.c_double), ("bytes", ct.c_double)]
 
 
@@ -81,6 +82,10 @@ _SIGS = {
     "juqcs_batch_create": [ct.POINTER(_P), _I, ct.POINTER(_I), _P, ct.POINTER(ct.c_int64), _P,
                            ct.POINTER(_U64), ct.POINTER(PlanOpts)],
     "juqcs_batch_run": [_P, _P],
+    "juqcs_batch_wait": [_P],
+    "juqcs_batch_fusion": [_P, ct.POINTER(_I)],
+    "juqcs_batch_amplitudes": [_P, ct.POINTER(_U64), _I, _DP, _P],
+    "juqcs_batch_norms": [_P, _DP, _P],
     "juqcs_batch_stats": [_P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
                           ct.POINTER(ct.c_int64)],
     "juqcs_batch_destroy": [_P],
@@ -311,8 +316,8 @@ class State:
 class Batch:
     """Many independent C64 circuits executed by one persistent launch."""
 
-    def __init__(self, circuits, device="cuda", states=None, tile_bits: int = 0,
-                 low_bits: int = 0):
+    def __init__(self, circuits, device="cuda", states=None, fuse_k: int = 0,
+                 autotune: bool = False):
         import torch
         ns = np.array([n for n, _ in circuits], dtype=np.int32)
         offs = np.zeros(len(circuits) + 1, dtype=np.int64)
@@ -330,7 +335,7 @@ class Batch:
         self.state_offset = soff
         self.states = states if states is not None else torch.empty(max(run, 256), dtype=torch.uint8,
                                                                      device=device)
-        o = PlanOpts(mode=PLAN_TILE, tile_bits=tile_bits, low_bits=low_bits)
+        o = PlanOpts(mode=PLAN_TILE, fuse_k=fuse_k, autotune=int(autotune))
         h = _P()
         _check(_lib.juqcs_batch_create(ct.byref(h), len(circuits),
                                        ns.ctypes.data_as(ct.POINTER(_I)), allg.ctypes.data,
@@ -342,6 +347,30 @@ class Batch:
 
     def run(self, stream=None):
         _check(_lib.juqcs_batch_run(self.h, _stream_handle(stream)), "juqcs_batch_run")
+
+    def wait(self):
+        _check(_lib.juqcs_batch_wait(self.h), "juqcs_batch_wait")
+
+    def fusion(self) -> np.ndarray:
+        k = (ct.c_int * len(self.n))()
+        _check(_lib.juqcs_batch_fusion(self.h, k), "juqcs_batch_fusion")
+        return np.array(list(k))
+
+    def amplitudes(self, idx, stream=None) -> np.ndarray:
+        """idx: (count, m) uint64 -> (count, m) complex128."""
+        z = np.ascontiguousarray(idx, dtype=np.uint64)
+        m = z.shape[1]
+        out = np.empty(2 * z.size, dtype=np.float64)
+        _check(_lib.juqcs_batch_amplitudes(self.h, z.ctypes.data_as(ct.POINTER(_U64)), m,
+                                           _dptr(out), _stream_handle(stream)),
+               "juqcs_batch_amplitudes")
+        return (out[0::2] + 1j * out[1::2]).reshape(z.shape)
+
+    def norms(self, stream=None) -> np.ndarray:
+        out = np.empty(len(self.n), dtype=np.float64)
+        _check(_lib.juqcs_batch_norms(self.h, _dptr(out), _stream_handle(stream)),
+               "juqcs_batch_norms")
+        return out
 
     def stats(self):
         a, b, c = ct.c_int64(), ct.c_int64(), ct.c_int64()

@@ -24,6 +24,9 @@ from oracle import decomposition  # noqa: E402
 from paper_1912_03243_amd import workloads as W  # noqa: E402
 
 # name: (n, layers, circuit seed, bitstring seed, count)
+# grid48m2: the 6x8 grid circuit (depth 8, seed 5) keeping only its first two
+# cut-crossing CZs, amplitudes by Eq. (3) over the 24|24 column cut.
+GRID_SETS = {"grid48m2": (6, 8, 8, 5, 2, 1005, 64)}
 SETS = {
     "brick30": (30, 20, 2, 1002, 256),
     "brick28": (28, 16, 3, 1003, 256),
@@ -36,7 +39,29 @@ def path_for(name):
     return os.path.join(HERE, f"{name}_amplitudes.txt")
 
 
+def make_grid(name):
+    rows, cols, depth, cseed, mcross, zseed, count = GRID_SETS[name]
+    circ, side = W.grid_circuit(rows, cols, depth, cseed, max_cross=mcross)
+    n = rows * cols
+    z = W.bitstrings(n, count, seed=zseed)
+    S = len(decomposition.crossing_czs(circ, side))
+    t0 = time.time()
+    amps = decomposition.branch_amplitudes(n, circ, side, z)
+    dt = time.time() - t0
+    with open(path_for(name), "w") as f:
+        f.write(f"# {name}: grid_circuit(rows={rows}, cols={cols}, depth={depth}, seed={cseed}, "
+                f"max_cross={mcross}); bitstrings(n={n}, count={count}, seed={zseed})\n")
+        f.write(f"# <z|C|0> by Eq. (3) (Section 4) over the column cut, S={S}, FP64 oracle, "
+                f"{dt:.0f} s\n")
+        f.write("# z re im\n")
+        for zi, a in zip(z, amps):
+            f.write(f"{int(zi)} {a.real:.17e} {a.imag:.17e}\n")
+    print(f"{name}: S={S} {dt:.1f}s -> {path_for(name)}", flush=True)
+
+
 def make(name):
+    if name in GRID_SETS:
+        return make_grid(name)
     n, layers, cseed, zseed, count = SETS[name]
     circ = W.layered_brick(n, layers, seed=cseed)
     z = W.bitstrings(n, count, seed=zseed)

@@ -1,0 +1,176 @@
+"""GPU parity of the batched persistent launch and of the Eq. (3) branch
+driver against the oracle."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from _parity import assert_c64, rel_l2
+from oracle import decomposition as odec
+from oracle import statevector as sv
+from paper_1912_03243_amd import workloads as W
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+from make_golden import GRID_SETS, load, path_for  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def J():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1912_03243_amd import juqcs
+    return juqcs
+
+
+def announce(*what):
+    print("CASE", *what, flush=True)
+
+
+def mixed_batch(seed=0):
+    rng = np.random.default_rng(seed)
+    circuits = []
+    for i, n in enumerate([1, 3, 5, 8, 12, 13, 14, 15, 17, 13, 16]):
+        if i % 2:
+            circ = W.layered_random_pairs(n, int(rng.integers(2, 6)), rng)
+        else:
+            circ = W.random_mixed(n, 60, seed=100 + i, p1=1.0 if n == 1 else 0.6)
+        circuits.append((n, circ))
+    circuits.append((9, W.empty_circuit(0)))            # no gates: |0...0>
+    return circuits
+
+
+@pytest.mark.parametrize("fuse_k", [0, 1, 2, 3, 4])
+def test_batch_matches_oracle(J, fuse_k):
+    announce("batch", fuse_k)
+    circuits = mixed_batch()
+    b = J.Batch(circuits, fuse_k=fuse_k)
+    b.run()
+    b.wait()
+    st = b.stats()
+    assert st["gate_apps"] == sum(len(c) for _, c in circuits)
+    for i, (n, circ) in enumerate(circuits):
+        assert_c64(b.state_vector(i), sv.run_circuit(n, circ))
+    if fuse_k:
+        assert np.all(b.fusion() == fuse_k)
+    b.close()
+
+
+def test_batch_graph_replay_and_readout(J):
+    import torch
+    announce("batch-graph")
+    circuits = mixed_batch(1)
+    s = torch.cuda.Stream()
+    b = J.Batch(circuits)
+    with torch.cuda.stream(s):
+        b.run(s)
+        b.wait()
+        first = [b.state_vector(i) for i in range(len(circuits))]
+        b.states.fill_(7)                       # garbage: every run starts from |0...0>
+        for _ in range(3):                      # graph replays
+            b.run(s)
+            b.wait()
+            torch.cuda.synchronize()
+            for i in range(len(circuits)):
+                assert np.array_equal(b.state_vector(i), first[i])
+        idx = np.stack([np.arange(8, dtype=np.uint64) % (1 << n) for n, _ in circuits])
+        amps = b.amplitudes(idx, s)
+        norms = b.norms(s)
+    for i, (n, circ) in enumerate(circuits):
+        phi = sv.run_circuit(n, circ)
+        assert np.allclose(amps[i], phi[idx[i].astype(np.int64)], atol=1e-6)
+        assert abs(norms[i] - 1.0) < 1e-5
+    b.close()
+
+
+def test_batch_order_does_not_change_results(J):
+    announce("batch-order")
+    circuits = mixed_batch(2)
+    perm = np.random.default_rng(3).permutation(len(circuits))
+    b1 = J.Batch(circuits, fuse_k=2)
+    b2 = J.Batch([circuits[i] for i in perm], fuse_k=2)
+    b1.run()
+    b2.run()
+    b1.wait()
+    b2.wait()
+    for j, i in enumerate(perm):
+        assert np.array_equal(b1.state_vector(int(i)), b2.state_vector(j))
+
+
+def test_batch_autotune(J):
+    announce("batch-autotune")
+    rng = np.random.default_rng(9)
+    circuits = [(n, W.layered_random_pairs(n, 6, rng)) for n in (12, 14, 16, 12, 14)]
+    b = J.Batch(circuits, autotune=True)
+    k = b.fusion()
+    assert np.all((k >= 1) & (k <= 4))
+    assert k[0] == k[3] and k[1] == k[4]      # one choice per qubit count
+    b.run()
+    b.wait()
+    for i, (n, circ) in enumerate(circuits):
+        assert_c64(b.state_vector(i), sv.run_circuit(n, circ))
+
+
+def test_batch_rejects_bad_input(J):
+    with pytest.raises(J.JuqcsError) as e:
+        J.Batch([(3, W.concat(W.gate(W.OP_CZ, 0, 3)))])
+    assert e.value.status == J.ERR_QUBIT
+    with pytest.raises(J.JuqcsError):
+        J.Batch([(31, W.empty_circuit(0))], states=__import__("torch").empty(16, device="cuda"))
+
+
+# ---- Eq. (3): branch sums -------------------------------------------------------------
+@pytest.mark.parametrize("rows, cols, depth, seed, group", [(2, 4, 4, 3, 0), (4, 4, 8, 9, 3),
+                                                           (2, 6, 6, 1, 0), (4, 6, 6, 2, 5)])
+def test_branch_amplitudes_small_grids(J, rows, cols, depth, seed, group):
+    announce("branch", rows, cols, depth, seed, group)
+    circ, side = W.grid_circuit(rows, cols, depth, seed, max_cross=None)
+    n = rows * cols
+    z = np.random.default_rng(seed).integers(0, 1 << n, 40, dtype=np.uint64)
+    got = J.juqcs_branch_amplitudes(n, circ, side, z, group_size=group)
+    ob = odec.branch_amplitudes(n, circ, side, z[:8])
+    scale = np.abs(ob).max()
+    assert np.max(np.abs(got[:8] - ob)) / scale < 1e-5
+    if n <= 16:  # and to the full state vector
+        full = sv.run_circuit(n, circ)
+        want = full[z.astype(np.int64)]
+        assert np.max(np.abs(got - want)) / np.abs(full).max() < 1e-5
+
+
+def test_branch_ghz48_closed_form(J, golden):
+    n = 48
+    announce("branch-ghz48")
+    recs = [W.gate(W.OP_H, 0)]
+    for i in range(n - 1):
+        if i == n // 2 - 1:                      # the crossing CNOT as H_t CZ H_t
+            recs += [W.gate(W.OP_H, i + 1), W.gate(W.OP_CZ, i, i + 1), W.gate(W.OP_H, i + 1)]
+        else:
+            recs.append(W.gate(W.OP_CNOT, i, i + 1))
+    side = np.array([0] * 24 + [1] * 24, dtype=np.uint8)
+    z = np.array([0, (1 << n) - 1, 1, 1 << 47, 12345], dtype=np.uint64)
+    got = J.juqcs_branch_amplitudes(n, W.concat(*recs), side, z)
+    assert abs(got[0] - golden["ghz.amp_all_zero"]) < 1e-6
+    assert abs(got[1] - golden["ghz.amp_all_one"]) < 1e-6
+    assert np.all(np.abs(got[2:]) < 1e-7)
+
+
+def test_branch_grid48_against_stored_oracle_values(J):
+    name = "grid48m2"
+    if not os.path.exists(path_for(name)):
+        pytest.skip("stored amplitudes not generated")
+    rows, cols, depth, seed, mcross, _, _ = GRID_SETS[name]
+    z, want = load(name)
+    circ, side = W.grid_circuit(rows, cols, depth, seed, max_cross=mcross)
+    announce(name)
+    got = J.juqcs_branch_amplitudes(rows * cols, circ, side, z)
+    assert rel_l2(got, want) < 1e-5
+
+
+def test_branch_rejects_non_cz_crossing(J):
+    side = np.array([0, 0, 1, 1], dtype=np.uint8)
+    with pytest.raises(J.JuqcsError) as e:
+        J.juqcs_branch_amplitudes(4, W.concat(W.gate(W.OP_CNOT, 1, 2)), side, [0])
+    assert e.value.status == J.ERR_UNSUPPORTED
