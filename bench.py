@@ -97,6 +97,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only the reference copy kernel (counter calibration)")
+    ap.add_argument("--workload", default="brick30",
+                    choices=["brick30", "batch4096", "grid48", "large34", "large36"],
+                    help="brick30 is the headline configuration; the others are the batched, "
+                         "decomposition and large-state configurations")
+    ap.add_argument("--count", type=int, default=4096, help="batch4096: number of circuits")
+    ap.add_argument("--autotune", type=int, default=0, help="batch4096: timed-trial autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -122,6 +128,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 launches of {nbytes} bytes")
         return
+
+    if args.workload != "brick30":
+        return other_workload(args, juqcs, W, dev, stream)
 
     n, gates, z = W.workload_brick30()
     zd = torch.from_numpy(z.astype(np.int64)).to(dev)
@@ -243,6 +252,116 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_budget)
     print(json.dumps(result), flush=True)
+
+
+def _timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def other_workload(args, juqcs, W, dev, stream):
+    """Secondary configurations (not the headline line): many small circuits
+    in one persistent launch, the entangling-gate decomposition, and the
+    largest single states in complex64 and two-byte form."""
+    import numpy as np
+    import torch
+    res = {"metric": METRIC, "unit": "gate-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "batch4096":
+        t0 = time.perf_counter()
+        inst = W.batch_instances(args.count)
+        t_gen = time.perf_counter() - t0
+        s = torch.cuda.Stream(dev)
+        t0 = time.perf_counter()
+        b = juqcs.Batch(inst, device=dev, autotune=bool(args.autotune))
+        t_plan = time.perf_counter() - t0
+        st = b.stats()
+        log(f"batch: {len(inst)} circuits, {st}, generation {t_gen:.1f}s, planning {t_plan:.1f}s")
+
+        def run():
+            b.run(s)
+
+        with torch.cuda.stream(s):
+            ms = _timed(run, args.steps, args.warmup, s)
+            b.wait()
+            idx = np.stack([W.bitstrings(n, 64, seed=10_000 + i) for i, (n, _) in enumerate(inst)])
+            norms = b.norms(s)
+        gates = sum(len(g) for _, g in inst)
+        amp_updates = sum(len(g) * float(1 << n) for n, g in inst)
+        kin = b.fusion()
+        # algorithmic bytes: the first pass of a circuit writes its state, later passes
+        # read and write it (8 bytes per amplitude)
+        res.update({
+            "value": gates / (ms / 1e3), "ms_per_step": ms, "dtype": "f32",
+            "config": {"workload": f"batch{len(inst)}: independent layered circuits, n ~ U{{12..24}}, "
+                                   "depth ~ U{10..40} (Haar U(2) + random CZ pairs), complex64, "
+                                   "one persistent graph-captured launch",
+                       "circuits": len(inst), "gates": gates, "tile_tasks": st["tasks"],
+                       "tile_passes": st["passes"],
+                       "fusion_width_counts": {int(k): int((kin == k).sum()) for k in set(kin.tolist())},
+                       "autotune": bool(args.autotune)},
+            "amp_updates_per_s": amp_updates / (ms / 1e3),
+            "planning_s": t_plan,
+            "check": {"max_abs_norm_minus_1": float(np.max(np.abs(norms - 1.0)))},
+        })
+        b.close()
+    elif args.workload == "grid48":
+        circ, side = W.grid_circuit()
+        z = W.bitstrings(48, 1024, seed=1005)
+        out = {}
+
+        def run():
+            out["a"] = juqcs.juqcs_branch_amplitudes(48, circ, side, z, stream=stream)
+
+        ms = _timed(run, args.steps, args.warmup, stream)
+        m = 10
+        half_gates = len(circ) - m + 2 * m   # every crossing CZ becomes a diagonal in each half
+        res.update({
+            "value": (1 << m) * half_gates / (ms / 1e3), "ms_per_step": ms, "dtype": "f32",
+            "config": {"workload": "grid48: 6x8 grid, depth 8, Haar U(2) + 4 CZ edge patterns, "
+                                   "24|24 cut with m=10 decomposed CZs -> 1024 branch pairs of "
+                                   "24-qubit complex64 half-states; 1024 amplitudes summed over "
+                                   "branches in FP64 (value counts half-circuit gates of every branch)",
+                       "gates": int(len(circ)), "branches": 1 << m, "bitstrings": int(z.size)},
+            "check": {"sum_abs2_of_1024_amps": float(np.sum(np.abs(out["a"]) ** 2))},
+        })
+    else:
+        n, dtype = (34, "c64") if args.workload == "large34" else (36, "enc2")
+        circ = W.layered_brick(n, 16, seed=3)
+        st = juqcs.State(n, dtype, device=dev, stream=stream)
+        info = {}
+
+        def run():
+            st.init(0)
+            o = st.run(circ, mode="tile", profile=True)
+            info["o"] = (o.passes, o.kernel_ms, o.bytes)
+
+        ms = _timed(run, args.steps, args.warmup, stream)
+        passes, kms, kb = info["o"]
+        nrm = st.norm()
+        achieved = kb / (kms / 1e3) / 1e9
+        res.update({
+            "value": len(circ) / (ms / 1e3), "ms_per_step": ms, "dtype": "f32",
+            "config": {"workload": f"{args.workload}: n={n} {dtype}, 16 brick layers ({len(circ)} gates, "
+                                   "seed 3), tile passes", "n": n, "passes_per_step": passes},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                         "bytes_per_launch": kb / passes, "avg_launch_ms": kms / passes},
+            "amp_updates_per_s": len(circ) * float(1 << n) / (ms / 1e3),
+            "check": {"norm_minus_1": nrm - 1.0},
+        })
+        st.close()
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -4,12 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "juqcs_internal.hpp"
@@ -54,20 +56,43 @@ double plan_cost(const TilePlan& p) {
   return c;
 }
 
-void plan_circuit(int n, const std::vector<Gate>& g, int kin, TilePlan* plan) {
+void schedule_circuit(int n, const std::vector<Gate>& g, TileSchedule* sched) {
   const int b = tile_bits_for(n);
-  plan_tiles(n, low_bits_for(n), b, 0, g, plan, kin);
-  if (plan->passes.empty()) {  // no gates: one pass that writes |0...0>
+  select_tiles(n, low_bits_for(n), b, 0, g, sched);
+  if (sched->passes.empty()) {  // no gates: one pass that writes |0...0>
     TilePass p{};
     p.g.n = n;
     p.g.b = b;
     p.g.L = b;
     p.g.H = 0;
     p.g.maxk = 1;
-    p.op_begin = 0;
-    p.op_count = 0;
-    plan->passes.push_back(p);
+    sched->passes.push_back(p);
+    sched->taken.emplace_back();
   }
+}
+
+void plan_circuit(int n, const std::vector<Gate>& g, int kin, TilePlan* plan) {
+  TileSchedule sched;
+  schedule_circuit(n, g, &sched);
+  emit_schedule(sched, g, kin, plan);
+}
+
+// Runs f(i) for i in [0, count) on the host's cores.
+template <typename F>
+void parallel_for(int count, F f) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int nt = (int)std::min<unsigned>(hw, (unsigned)count);
+  if (nt <= 1) {
+    for (int i = 0; i < count; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (int i = next++; i < count; i = next++) f(i);
+    });
+  for (auto& x : th) x.join();
 }
 
 }  // namespace
@@ -269,14 +294,31 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
       }
   }
   // fusion width: fixed, modelled, or measured (one trial per qubit count)
+  if (!autotune) {
+    parallel_for(count, [&](int c) {
+      TileSchedule sched;
+      schedule_circuit(n[c], dec[c], &sched);
+      if (fuse > 0) {
+        emit_schedule(sched, dec[c], fuse, &plans[c]);
+        B->kin[c] = fuse;
+        return;
+      }
+      double best = 1e300;
+      for (int k = 2; k <= 4; ++k) {
+        TilePlan p;
+        emit_schedule(sched, dec[c], k, &p);
+        const double cst = plan_cost(p);
+        if (cst < best) {
+          best = cst;
+          plans[c] = std::move(p);
+          B->kin[c] = k;
+        }
+      }
+    });
+  }
   std::map<int, int> measured;
-  for (int c = 0; c < count; ++c) {
-    if (fuse > 0) {
-      plan_circuit(n[c], dec[c], fuse, &plans[c]);
-      B->kin[c] = fuse;
-      continue;
-    }
-    if (autotune) {
+  for (int c = 0; autotune && c < count; ++c) {
+    {
       auto it = measured.find(n[c]);
       if (it == measured.end()) {
         double best = 1e30;
@@ -293,21 +335,10 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
         it = measured.emplace(n[c], bk).first;
       }
       B->kin[c] = it->second;
-      plan_circuit(n[c], dec[c], it->second, &plans[c]);
-      continue;
-    }
-    double best = 1e300;
-    for (int k = 2; k <= 4; ++k) {
-      TilePlan p;
-      plan_circuit(n[c], dec[c], k, &p);
-      const double cst = plan_cost(p);
-      if (cst < best) {
-        best = cst;
-        plans[c] = std::move(p);
-        B->kin[c] = k;
-      }
     }
   }
+  if (autotune)
+    parallel_for(count, [&](int c) { plan_circuit(n[c], dec[c], B->kin[c], &plans[c]); });
   juqcs_status rc = build_device(B, plans);
   if (rc != JUQCS_OK) {
     free_batch(B);

@@ -202,8 +202,20 @@ struct TilePlan {
 // pattern as the gates the plan was made for).
 void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan);
 
+// Tile selection alone: the passes (geometry) and the gates each absorbs.
+struct TileSchedule {
+  std::vector<TilePass> passes;
+  std::vector<std::vector<int>> taken;
+  int64_t gates = 0;
+};
+void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
+                  TileSchedule* sched);
+// Fuses every pass's gates into ops of at most kin qubits.
+void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, int kin,
+                   TilePlan* plan);
+
 // Plans tile passes for gates (physical qubits).  L, b: low contiguous bits
-// and total tile bits.  fixed_low: the low L bits are always tile bits.
+// and total tile bits; the low L bits are always tile bits.
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
                 TilePlan* plan, int kin = 2);
 

@@ -273,14 +273,11 @@ void emit_ops(const std::vector<Cluster>& cl, const TileGeom& geom, TilePlan* pl
 
 }  // namespace
 
-void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan, int kin) {
-  (void)block_bits;
-  plan->passes.clear();
-  plan->ops.clear();
-  plan->mats.clear();
-  plan->op_gates.clear();
-  plan->gates = (int64_t)gates.size();
+void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
+                  TileSchedule* sched) {
+  sched->passes.clear();
+  sched->taken.clear();
+  sched->gates = (int64_t)gates.size();
   if (n <= b) {
     L = n;
     b = n;
@@ -289,7 +286,6 @@ void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& ga
   std::vector<int> rem(gates.size());
   for (size_t i = 0; i < gates.size(); ++i) rem[i] = (int)i;
   constexpr int kCandidates = 24;
-  kin = std::max(1, std::min(kin, 4));  // on-chip fusion width
   while (!rem.empty()) {
     std::vector<char> in_tile(n, 0);
     for (int q = 0; q < L; ++q) in_tile[q] = 1;
@@ -356,16 +352,39 @@ void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& ga
     pass.g.b = b;
     pass.g.block_bits = block_bits;
     for (int j = 0; j < H; ++j) pass.g.hbits[j] = chosen[j];
+    pass.g.maxk = 1;
+    sched->passes.push_back(pass);
+    sched->taken.push_back(std::move(taken));
+    rem.swap(keep);
+  }
+}
+
+void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, int kin,
+                   TilePlan* plan) {
+  plan->passes.clear();
+  plan->ops.clear();
+  plan->mats.clear();
+  plan->op_gates.clear();
+  plan->gates = sched.gates;
+  kin = std::max(1, std::min(kin, 4));  // on-chip fusion width
+  for (size_t i = 0; i < sched.passes.size(); ++i) {
+    TilePass pass = sched.passes[i];
     std::vector<Cluster> cl;
-    fuse(gates, taken, kin, &cl);
+    fuse(gates, sched.taken[i], kin, &cl);
     pass.op_begin = (int32_t)plan->ops.size();
     emit_ops(cl, pass.g, plan);
     pass.op_count = (int32_t)plan->ops.size() - pass.op_begin;
     pass.g.maxk = 1;
     for (const Cluster& c : cl) pass.g.maxk = std::max(pass.g.maxk, (int32_t)c.q.size());
     plan->passes.push_back(pass);
-    rem.swap(keep);
   }
+}
+
+void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
+                TilePlan* plan, int kin) {
+  TileSchedule sched;
+  select_tiles(n, L, b, block_bits, gates, &sched);
+  emit_schedule(sched, gates, kin, plan);
 }
 
 void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan) {

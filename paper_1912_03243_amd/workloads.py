@@ -85,6 +85,16 @@ def _u_record(m: np.ndarray) -> np.ndarray:
     return np.stack([m.real, m.imag], axis=-1).reshape(8)
 
 
+def haar_u2_many(rng: np.random.Generator, count: int) -> np.ndarray:
+    """count Haar-distributed 2x2 unitaries at once (same construction as
+    haar_u2, stacked QR), returned as (count, 8) gate-record rows."""
+    z = (rng.standard_normal((count, 2, 2)) + 1j * rng.standard_normal((count, 2, 2))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r, axis1=1, axis2=2)
+    u = q * (d / np.abs(d))[:, None, :]
+    return np.stack([u.real, u.imag], axis=-1).reshape(count, 8)
+
+
 # --------------------------------------------------------------------------
 # Circuit families
 # --------------------------------------------------------------------------
@@ -142,8 +152,7 @@ def layered_random_pairs(n: int, depth: int, rng: np.random.Generator) -> np.nda
         g = empty_circuit(n)
         g["op"] = OP_U
         g["q0"] = np.arange(n)
-        for q in range(n):
-            g["u"][q] = _u_record(haar_u2(rng))
+        g["u"] = haar_u2_many(rng, n)
         out.append(g)
         perm = rng.permutation(n)
         npair = n // 2
