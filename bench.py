@@ -103,6 +103,9 @@ def main():
                          "decomposition and large-state configurations")
     ap.add_argument("--count", type=int, default=4096, help="batch4096: number of circuits")
     ap.add_argument("--autotune", type=int, default=0, help="batch4096: timed-trial autotuner")
+    ap.add_argument("--tile-fuse", type=int, default=0, help="in-pass fusion width (0 = default)")
+    ap.add_argument("--tile-bits", type=int, default=0, help="tile bits (0 = default)")
+    ap.add_argument("--low-bits", type=int, default=0, help="contiguous low tile bits (0 = default)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -141,7 +144,11 @@ def main():
 
     def step(mode, profile):
         st.init(0)
-        o = st.run(gates, mode=mode, profile=profile, fuse_k=5)
+        if mode == "tile":
+            o = st.run(gates, mode=mode, profile=profile, fuse_k=args.tile_fuse,
+                       tile_bits=args.tile_bits, low_bits=args.low_bits)
+        else:
+            o = st.run(gates, mode=mode, profile=profile, fuse_k=5)
         st.amplitudes_device(zd, outd)
         nrm = st.norm()
         return o, nrm
@@ -205,11 +212,12 @@ def main():
                                "on every qubit + brick CZ (890 gates, seed 2); init, all gates, "
                                "4096 amplitudes (seed 1002) and the norm per step",
                    "n": n, "gates": ngates, "bitstrings": int(z.size), "mode": args.mode,
+                   "tile_fuse": args.tile_fuse, "tile_bits": args.tile_bits,
                    "passes_per_step": passes // args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic_for("k_tile.hip") if args.mode == "tile" else None,
-                     "kernel": "k_tile<double,12>" if args.mode == "tile" else args.mode,
+                     "kernel": "k_tile_fixed<double,13,1024>" if args.mode == "tile" else args.mode,
                      "bytes_per_launch": per_launch, "avg_launch_ms": pass_ms},
         "amp_updates_per_s": value * float(1 << n),
         "check": check,
@@ -343,7 +351,8 @@ def other_workload(args, juqcs, W, dev, stream):
 
         def run():
             st.init(0)
-            o = st.run(circ, mode="tile", profile=True)
+            o = st.run(circ, mode="tile", profile=True, fuse_k=args.tile_fuse,
+                       tile_bits=args.tile_bits, low_bits=args.low_bits)
             info["o"] = (o.passes, o.kernel_ms, o.bytes)
 
         ms = _timed(run, args.steps, args.warmup, stream)

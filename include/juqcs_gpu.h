@@ -165,7 +165,8 @@ typedef enum {
 
 typedef struct {
   int32_t mode;        /* juqcs_plan_mode                                */
-  int32_t fuse_k;      /* FUSED: block width 2..6 (0 = 5)                 */
+  int32_t fuse_k;      /* FUSED: block width 2..6 (0 = 5).  TILE: widest
+                          fused op inside a pass, 1..4 (0 = 3)            */
   int32_t mma;         /* FUSED: juqcs_mma                                */
   int32_t tile_bits;   /* TILE: total tile bits (0 = default for dtype)   */
   int32_t low_bits;    /* TILE: contiguous low bits per chunk (0 = default) */

@@ -176,10 +176,12 @@ juqcs_status run_tile_plan(juqcs_state* st, const TilePlan& plan) {
   return JUQCS_OK;
 }
 
+// Defaults measured on MI355X for layered circuits (2^b-amplitude tiles,
+// chunks of 2^L contiguous amplitudes).
 void default_tile_bits(juqcs_dtype dt, int B, int* L, int* b) {
   if (dt == JUQCS_C128) {
-    *b = 12;
-    *L = 6;
+    *b = 13;
+    *L = 5;
   } else if (dt == JUQCS_C64) {
     *b = 13;
     *L = 7;
@@ -190,7 +192,7 @@ void default_tile_bits(juqcs_dtype dt, int B, int* L, int* b) {
 }
 
 juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, int b,
-                        int64_t* passes) {
+                        int64_t* passes, int kin = 0) {
   const int maxb = tile_max_bits(st->dt);
   if (b <= 0 || L <= 0) default_tile_bits(st->dt, st->B, &L, &b);
   if (b > maxb) return fail(JUQCS_ERR_ARG, "tile_bits above the LDS limit");
@@ -198,8 +200,10 @@ juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, 
   if (b - L > kMaxGather) return fail(JUQCS_ERR_ARG, "too many gathered tile bits");
   if (st->dt == JUQCS_ENC2 && L < st->B) L = st->B;
   if (st->dt == JUQCS_ENC2 && b < L) b = L;
+  if (kin <= 0) kin = 3;
+  if (kin > 4) return fail(JUQCS_ERR_ARG, "in-pass fusion width must be 1..4");
   TilePlan plan;
-  plan_tiles(st->n, std::min(L, st->n), b, st->B, gates, &plan);
+  plan_tiles(st->n, std::min(L, st->n), b, st->B, gates, &plan, kin);
   if (passes) *passes = (int64_t)plan.passes.size();
   return run_tile_plan(st, plan);
 }
@@ -576,7 +580,7 @@ juqcs_status run_planned(juqcs_state* st, const std::vector<Gate>& g, int mode,
   }
   if (mode == JUQCS_PLAN_TILE) {
     int64_t passes = 0;
-    juqcs_status rc = tile_gates(st, g, o->low_bits, o->tile_bits, &passes);
+    juqcs_status rc = tile_gates(st, g, o->low_bits, o->tile_bits, &passes, o->fuse_k);
     o->passes = passes;
     return rc;
   }

@@ -21,7 +21,7 @@ using namespace juqcs;
 namespace {
 
 using C = cplx<double>;
-constexpr int kChunkTiles = 4;
+constexpr int kChunkTiles = 8;
 constexpr uint32_t kSpinLimit = 1u << 25;  // bounded dependency wait
 
 juqcs_status fail(juqcs_status st, const std::string& msg) {

@@ -17,10 +17,13 @@ namespace juqcs {
 
 namespace {
 
-using tileops::kThreads;
-using tileops::run_ops;
+using tileops::Fixed;
+using tileops::lds;
+using tileops::Var;
 
-constexpr int kBatchMaxBits = 13;  // 64 KiB of C64 amplitudes per tile
+constexpr int kThreads = 256;       // helper kernels
+constexpr int kBatchThreads = 1024;  // the persistent batch kernel
+constexpr int kBatchMaxBits = 13;   // 64 KiB of C64 amplitudes per tile
 
 __device__ inline uint64_t tile_base_hb(uint64_t tau, int L, int H, const int* hb) {
   uint64_t base = tau << L;
@@ -39,7 +42,82 @@ __global__ __launch_bounds__(kThreads) void k_batch_reset(uint32_t* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_batch(
+// One chunk of tiles of a pass with a compile-time tile size: the next tile
+// of the chunk is prefetched into registers while the current one is on chip.
+template <int TB>
+__device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64_t tau0, int ntile,
+                                       bool init, int L, int H, const int* hb,
+                                       const uint64_t* choff, const TileOp* ops, int nops,
+                                       const cplx<float>* mats) {
+  constexpr int NA = 1 << TB, PER = NA / kBatchThreads;
+  const int lmask = (1 << L) - 1;
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  v2* gp = reinterpret_cast<v2*>(psi);
+  v2* sp = reinterpret_cast<v2*>(sh);
+  v2 v[PER];
+  if (!init) {
+    const uint64_t base = tile_base_hb(tau0, L, H, hb);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = k * kBatchThreads + threadIdx.x;
+      v[k] = gp[base + choff[e >> L] + (e & lmask)];
+    }
+  }
+  for (int j = 0; j < ntile; ++j) {
+    const uint64_t tau = tau0 + j;
+    const uint64_t base = tile_base_hb(tau, L, H, hb);
+    if (init) {  // first pass: the state is |0...0>
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = k * kBatchThreads + threadIdx.x;
+        sp[lds<float>(e)] = v2{(base == 0 && e == 0) ? 1.0f : 0.0f, 0.0f};
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) sp[lds<float>(k * kBatchThreads + threadIdx.x)] = v[k];
+    }
+    __syncthreads();
+    if (!init) {  // prefetch the chunk's next tile (or this one again, unused)
+      const uint64_t nb = tile_base_hb(j + 1 < ntile ? tau + 1 : tau, L, H, hb);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = k * kBatchThreads + threadIdx.x;
+        v[k] = gp[nb + choff[e >> L] + (e & lmask)];
+      }
+    }
+    Fixed<float, TB, kBatchThreads>::run(sh, ops, nops, mats);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = k * kBatchThreads + threadIdx.x;
+      gp[base + choff[e >> L] + (e & lmask)] = sp[lds<float>(e)];
+    }
+    __syncthreads();
+  }
+}
+
+__device__ inline void run_chunk_var(cplx<float>* sh, cplx<float>* psi, uint64_t tau0, int ntile,
+                                     bool init, int b, int L, int H, const int* hb,
+                                     const uint64_t* choff, const TileOp* ops, int nops,
+                                     const cplx<float>* mats) {
+  const int tile_amps = 1 << b, lmask = (1 << L) - 1;
+  for (int j = 0; j < ntile; ++j) {
+    const uint64_t base = tile_base_hb(tau0 + j, L, H, hb);
+    if (init) {
+      for (int e = threadIdx.x; e < tile_amps; e += kBatchThreads)
+        sh[lds<float>(e)] = cplx<float>{(base == 0 && e == 0) ? 1.0f : 0.0f, 0.0f};
+    } else {
+      for (int e = threadIdx.x; e < tile_amps; e += kBatchThreads)
+        sh[lds<float>(e)] = psi[base + choff[e >> L] + (e & lmask)];
+    }
+    __syncthreads();
+    Var<float, kBatchThreads>::run(sh, b, ops, nops, mats);
+    for (int e = threadIdx.x; e < tile_amps; e += kBatchThreads)
+      psi[base + choff[e >> L] + (e & lmask)] = sh[lds<float>(e)];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch(
     char* __restrict__ states, const BatchGroup* __restrict__ groups, int ngroups,
     const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
     const cplx<float>* __restrict__ mats, uint32_t* __restrict__ done,
@@ -89,11 +167,11 @@ __global__ __launch_bounds__(kThreads) void k_batch(
       __threadfence();
     }
     const BatchPass ps = passes[grp.pass];
-    const int b = ps.g.b, L = ps.g.L, H = ps.g.H, lmask = (1 << L) - 1;
+    const int b = ps.g.b, L = ps.g.L, H = ps.g.H;
     if (grp.pass != cur_pass) {
-      if (threadIdx.x < kHbitsCap) hb[threadIdx.x] = threadIdx.x < H ? ps.g.hbits[threadIdx.x] : 0;
+      if (threadIdx.x < kHbitsCap) hb[threadIdx.x] = (int)threadIdx.x < H ? ps.g.hbits[threadIdx.x] : 0;
       __syncthreads();
-      for (int c = threadIdx.x; c < (1 << H); c += kThreads) {
+      for (int c = threadIdx.x; c < (1 << H); c += kBatchThreads) {
         uint64_t o = 0;
         for (int j = 0; j < H; ++j) o |= (uint64_t)((c >> j) & 1) << hb[j];
         choff[c] = o;
@@ -102,23 +180,14 @@ __global__ __launch_bounds__(kThreads) void k_batch(
       cur_pass = grp.pass;
     }
     cplx<float>* psi = reinterpret_cast<cplx<float>*>(states + grp.state_off);
-    const int tile_amps = 1 << b;
-    const long long chunk = t - grp.first_chunk;
-    for (int j = 0; j < grp.chunk_tiles; ++j) {
-      const uint64_t tau = (uint64_t)chunk * grp.chunk_tiles + j;
-      const uint64_t base = tile_base_hb(tau, L, H, hb);
-      if (grp.init) {  // first pass: the state is |0...0>
-        for (int e = threadIdx.x; e < tile_amps; e += kThreads)
-          sh[e] = cplx<float>{(base == 0 && e == 0) ? 1.0f : 0.0f, 0.0f};
-      } else {
-        for (int e = threadIdx.x; e < tile_amps; e += kThreads)
-          sh[e] = psi[base + choff[e >> L] + (e & lmask)];
-      }
-      __syncthreads();
-      run_ops<float>(sh, b, ops + ps.op_begin, ps.op_count, mats);
-      for (int e = threadIdx.x; e < tile_amps; e += kThreads)
-        psi[base + choff[e >> L] + (e & lmask)] = sh[e];
-      __syncthreads();
+    const uint64_t tau0 = (uint64_t)(t - grp.first_chunk) * grp.chunk_tiles;
+    const TileOp* pops = ops + ps.op_begin;
+    const bool init = grp.init != 0;
+    switch (ps.g.maxk <= 3 ? b : 0) {  // the fixed-size paths run ops of up to 3 qubits
+      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats); break;
+      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats); break;
+      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats); break;
+      default: run_chunk_var(sh, psi, tau0, grp.chunk_tiles, init, b, L, H, hb, choff, pops, ps.op_count, mats); break;
     }
     // publish the finished tiles (release at agent scope)
     __threadfence();
@@ -215,14 +284,14 @@ hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s) {
     int dev = 0, cus = 256, per = 1;
     if (hipGetDevice(&dev) == hipSuccess)
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch, kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch, kBatchThreads, 0) !=
             hipSuccess ||
         per < 1)
       per = 1;
     slots = (uint64_t)cus * per;
   }
   const uint64_t grid = d.nchunks < (long long)slots ? (uint64_t)d.nchunks : slots;
-  hipLaunchKernelGGL(k_batch, dim3((unsigned)(grid ? grid : 1)), dim3(kThreads), 0, s, states,
+  hipLaunchKernelGGL(k_batch, dim3((unsigned)(grid ? grid : 1)), dim3(kBatchThreads), 0, s, states,
                      d.groups, d.ngroups, d.passes, d.ops, d.mats, d.done,
                      (unsigned long long*)d.ticket, d.nchunks, d.err, d.spin_limit);
   return hipGetLastError();

@@ -71,7 +71,7 @@ def test_brick30_c128_other_modes(J, mode):
     announce(name, "c128", mode)
     with J.State(n, "c128") as s:
         s.init(0)
-        s.run(circ, mode=mode, fuse_k=5)
+        s.run(circ, mode=mode, fuse_k=5 if mode == "fused" else 0)
         got = s.amplitudes(z)
     assert float(np.max(np.abs(got - want))) <= TOL_C128
 
@@ -100,7 +100,7 @@ def test_brick28_precision_forms(J, dtype, mode, mma):
     announce(name, dtype, mode, mma)
     with J.State(n, dtype) as s:
         s.init(0)
-        o = s.run(circ, mode=mode, fuse_k=5, mma=mma)
+        o = s.run(circ, mode=mode, fuse_k=5 if mode == "fused" else 0, mma=mma)
         got = s.amplitudes(z)
         nrm = s.norm()
     err = rel_l2(got, want)
