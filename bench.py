@@ -69,16 +69,26 @@ def cpu_baseline(n, gates, budget_s):
                        f"host: {cpu_model()}, {os.cpu_count()} logical CPUs")}
 
 
-def traffic_for(kernel_src):
+TILE_SOURCES = ("k_tile.hip", "tile_ops.hpp", "juqcs_internal.hpp")
+
+
+def sources_sha256(names):
+    """One digest over the kernel's source files, in the given order."""
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_1912_03243_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_for(names):
     """HBM bytes per launch measured with rocprofv3 counters (profiles/), used
-    only while the kernel source is unchanged since the measurement."""
+    only while the kernel's sources are unchanged since the measurement."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_1912_03243_amd", "csrc", kernel_src), "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()
-        if rec.get("source_sha256") == h:
+        if rec.get("source_sha256") == sources_sha256(names):
             return rec.get("traffic_bytes_per_launch")
     except (OSError, ValueError):
         pass
@@ -216,7 +226,7 @@ def main():
                    "passes_per_step": passes // args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": traffic_for("k_tile.hip") if args.mode == "tile" else None,
+                     "traffic": traffic_for(TILE_SOURCES) if args.mode == "tile" else None,
                      "kernel": "k_tile_fixed<double,13,1024>" if args.mode == "tile" else args.mode,
                      "bytes_per_launch": per_launch, "avg_launch_ms": pass_ms},
         "amp_updates_per_s": value * float(1 << n),
