@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only the reference copy kernel (counter calibration)")
     ap.add_argument("--workload", default="brick30",
-                    choices=["brick30", "batch4096", "grid48", "large34", "large36"],
+                    choices=["brick30", "batch4096", "grid48", "large34", "large36", "ghz33", "ghz36"],
                     help="brick30 is the headline configuration; the others are the batched, "
                          "decomposition and large-state configurations")
     ap.add_argument("--count", type=int, default=4096, help="batch4096: number of circuits")
@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--tile-fuse", type=int, default=0, help="in-pass fusion width (0 = default)")
     ap.add_argument("--tile-bits", type=int, default=0, help="tile bits (0 = default)")
     ap.add_argument("--low-bits", type=int, default=0, help="contiguous low tile bits (0 = default)")
+    ap.add_argument("--pass-gates", type=int, default=0,
+                    help="most gates per tile pass (0 = planner's cost model, -1 = no limit)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -156,7 +158,8 @@ def main():
         st.init(0)
         if mode == "tile":
             o = st.run(gates, mode=mode, profile=profile, fuse_k=args.tile_fuse,
-                       tile_bits=args.tile_bits, low_bits=args.low_bits)
+                       tile_bits=args.tile_bits, low_bits=args.low_bits,
+                       pass_gates=args.pass_gates)
         else:
             o = st.run(gates, mode=mode, profile=profile, fuse_k=5)
         st.amplitudes_device(zd, outd)
@@ -223,6 +226,7 @@ def main():
                                "4096 amplitudes (seed 1002) and the norm per step",
                    "n": n, "gates": ngates, "bitstrings": int(z.size), "mode": args.mode,
                    "tile_fuse": args.tile_fuse, "tile_bits": args.tile_bits,
+                   "pass_gates": args.pass_gates,
                    "passes_per_step": passes // args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
@@ -353,6 +357,49 @@ def other_workload(args, juqcs, W, dev, stream):
                        "gates": int(len(circ)), "branches": 1 << m, "bitstrings": int(z.size)},
             "check": {"sum_abs2_of_1024_amps": float(np.sum(np.abs(out["a"]) ** 2))},
         })
+    elif args.workload in ("ghz33", "ghz36"):
+        # the paper's benchmark circuit (Section 3): H on qubit 0, CNOT(i, i+1)
+        # for i < n-1, then the expectation values of all qubits; the paper
+        # reports the elapsed time per gate
+        n, dtype = (33, "c128") if args.workload == "ghz33" else (36, "enc2")
+        circ = W.ghz(n)
+        st = juqcs.State(n, dtype, device=dev, stream=stream)
+        q = {}
+        modes = {}
+        for mode in ("tile", "plain"):
+            def run(mode=mode):
+                st.init(0)
+                st.run(circ, mode=mode)
+            steps = args.steps if mode == "tile" else 1
+            ms = _timed(run, steps, args.warmup if mode == "tile" else 0, stream)
+            st.init(0)
+            o = st.run(circ, mode=mode, profile=True)
+            modes[mode] = {"ms_per_circuit": ms, "ms_per_gate": ms / len(circ), "passes": o.passes,
+                           "avg_pass_ms": o.kernel_ms / max(o.passes, 1),
+                           "achieved_GBps": o.bytes / (o.kernel_ms / 1e3) / 1e9}
+            log(f"ghz {mode}: {ms:.1f} ms, {o.passes} passes")
+
+        def expect():
+            q["v"] = st.expectations()
+
+        ms_q = _timed(expect, args.steps, args.warmup, stream)
+        amps = st.amplitudes(np.array([0, (1 << n) - 1, 1, 1 << (n - 1)], dtype=np.uint64))
+        t = modes["tile"]
+        res.update({
+            "value": len(circ) / ((t["ms_per_circuit"] + ms_q) / 1e3),
+            "ms_per_step": t["ms_per_circuit"] + ms_q, "dtype": "f64" if dtype == "c128" else "enc2",
+            "config": {"workload": f"{args.workload}: n={n} {dtype} GHZ circuit (H(0) + {n - 1} "
+                                   "CNOT(i,i+1)) + expectation values of all qubits; init, gates "
+                                   "and expectations per step", "n": n, "gates": len(circ)},
+            "tile": t, "plain": modes["plain"],
+            "expectations_ms": ms_q,
+            "amp_updates_per_s": len(circ) * float(1 << n) / (t["ms_per_circuit"] / 1e3),
+            "check": {"amp0_minus_inv_sqrt2": float(abs(amps[0] - 2 ** -0.5)),
+                      "amp_last_minus_inv_sqrt2": float(abs(amps[1] - 2 ** -0.5)),
+                      "max_abs_other": float(np.abs(amps[2:]).max()),
+                      "max_abs_Q_minus_half": float(np.abs(q["v"] - 0.5).max())},
+        })
+        st.close()
     else:
         n, dtype = (34, "c64") if args.workload == "large34" else (36, "enc2")
         circ = W.layered_brick(n, 16, seed=3)
@@ -362,7 +409,8 @@ def other_workload(args, juqcs, W, dev, stream):
         def run():
             st.init(0)
             o = st.run(circ, mode="tile", profile=True, fuse_k=args.tile_fuse,
-                       tile_bits=args.tile_bits, low_bits=args.low_bits)
+                       tile_bits=args.tile_bits, low_bits=args.low_bits,
+                       pass_gates=args.pass_gates)
             info["o"] = (o.passes, o.kernel_ms, o.bytes)
 
         ms = _timed(run, args.steps, args.warmup, stream)

@@ -175,7 +175,10 @@ typedef struct {
   int32_t autotune;    /* batches: 1 = pick the on-chip fusion width per
                           qubit count from timed trial runs (the trials
                           use the batch's state buffer); 0 = cost model  */
-  int32_t reserved;
+  int32_t pass_gates;  /* TILE: most gates one pass may absorb; -1 = no
+                          limit; 0 = the planner's choice (no limit for
+                          C128; for C64 and ENC2 the limit its cost model
+                          prefers, which spreads on-chip work over passes) */
   /* outputs */
   int64_t passes;      /* kernel passes over the state that were launched */
   int64_t gates;       /* gate records consumed                           */

@@ -191,8 +191,41 @@ void default_tile_bits(juqcs_dtype dt, int B, int* L, int* b) {
   }
 }
 
+// Modelled duration (ms) of a tile plan on MI355X: a pass costs the longer of
+// its HBM traffic and its on-chip ops (the pipelined kernels overlap the
+// two).  Per-pass and per-op figures are measured durations per 2^30
+// amplitudes with the fixed-size kernels.
+double tile_plan_ms(const TilePlan& p, juqcs_dtype dt, int n) {
+  struct Costs {
+    double mem, dense1, dense2, diag2, dense3, dense4;
+  };
+  static constexpr Costs kC128{7.9, 0.50, 0.70, 0.45, 1.33, 4.0};
+  static constexpr Costs kC64{4.0, 0.34, 0.56, 0.40, 1.20, 3.0};
+  static constexpr Costs kEnc2{4.8, 0.34, 0.56, 0.40, 1.20, 3.0};
+  const Costs& c = dt == JUQCS_C128 ? kC128 : dt == JUQCS_C64 ? kC64 : kEnc2;
+  double total = 0.0;
+  for (const TilePass& ps : p.passes) {
+    double ops = 0.0;
+    for (int o = 0; o < ps.op_count; ++o) {
+      switch (p.ops[ps.op_begin + o].kind) {
+        case TOP_DENSE1: ops += c.dense1; break;
+        case TOP_DENSE2: ops += c.dense2; break;
+        case TOP_DIAG2:
+        case TOP_PERM: ops += c.diag2; break;
+        case TOP_DENSE3: ops += c.dense3; break;
+        default: ops += c.dense4; break;
+      }
+    }
+    total += std::max(c.mem, ops);
+  }
+  return total * std::ldexp(1.0, n - 30);
+}
+
+// pass_gates: > 0 caps the gates per pass, -1 lifts the cap, 0 is the
+// planner's choice: no cap for C128 (measured fastest: capped plans carry
+// more, less dense ops), for C64 and ENC2 the cap the cost model prefers.
 juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, int b,
-                        int64_t* passes, int kin = 0) {
+                        int64_t* passes, int kin = 0, int pass_gates = -1) {
   const int maxb = tile_max_bits(st->dt);
   if (b <= 0 || L <= 0) default_tile_bits(st->dt, st->B, &L, &b);
   if (b > maxb) return fail(JUQCS_ERR_ARG, "tile_bits above the LDS limit");
@@ -202,8 +235,25 @@ juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, 
   if (st->dt == JUQCS_ENC2 && b < L) b = L;
   if (kin <= 0) kin = 3;
   if (kin > 4) return fail(JUQCS_ERR_ARG, "in-pass fusion width must be 1..4");
+  if (pass_gates < -1) return fail(JUQCS_ERR_ARG, "pass_gates must be >= -1");
+  const int cap = tile_mat_cap(st->dt, std::min(b, st->n));
+  const int l = std::min(L, st->n);
   TilePlan plan;
-  plan_tiles(st->n, std::min(L, st->n), b, st->B, gates, &plan, kin);
+  if (pass_gates != 0 || st->dt == JUQCS_C128) {
+    plan_tiles(st->n, l, b, st->B, gates, &plan, kin, cap, std::max(pass_gates, 0));
+  } else {
+    double best = 0.0;
+    for (int take : {0, 90, 60, 40}) {
+      if (take > 0 && (int64_t)gates.size() <= take) continue;  // same as no cap
+      TilePlan cand;
+      plan_tiles(st->n, l, b, st->B, gates, &cand, kin, cap, take);
+      const double ms = tile_plan_ms(cand, st->dt, st->n);
+      if (plan.passes.empty() || ms < best) {
+        best = ms;
+        plan = std::move(cand);
+      }
+    }
+  }
   if (passes) *passes = (int64_t)plan.passes.size();
   return run_tile_plan(st, plan);
 }
@@ -580,7 +630,7 @@ juqcs_status run_planned(juqcs_state* st, const std::vector<Gate>& g, int mode,
   }
   if (mode == JUQCS_PLAN_TILE) {
     int64_t passes = 0;
-    juqcs_status rc = tile_gates(st, g, o->low_bits, o->tile_bits, &passes, o->fuse_k);
+    juqcs_status rc = tile_gates(st, g, o->low_bits, o->tile_bits, &passes, o->fuse_k, o->pass_gates);
     o->passes = passes;
     return rc;
   }
@@ -664,19 +714,38 @@ juqcs_status juqcs_scale(juqcs_state* st, double factor) {
 juqcs_status juqcs_expectations(juqcs_state* st, double* out) {
   if (check_state(st)) return JUQCS_ERR_ARG;
   if (!out) return fail(JUQCS_ERR_ARG, "null output");
-  double* partials = (double*)(st->work + kPartialOff);
-  double* res = (double*)(st->work + kResultOff);
-  std::vector<double> sums(3 * st->n);
-  for (int q = 0; q < st->n; ++q) {
-    hipError_t e = launch_pauli(st->dt, st->amps, st->scales, st->n, st->B, st->phys[q], partials,
-                                res + 3 * q, st->stream);
-    if (e != hipSuccess) return hip_fail(e, "Pauli launch");
+  const int n = st->n;
+  double* partials = (double*)ring_alloc(st, expect_partials_bytes());
+  if (!partials) return fail(JUQCS_ERR_SIZE, "workspace too small for expectation partials");
+  double* res = (double*)(st->work + kResultOff);  // 3 sums per physical bit
+  // first pass: the low b bits; then L contiguous bits plus up to b - L
+  // gathered bits not covered yet per pass
+  const int b = std::min(n, expect_max_bits());
+  const int L = st->dt == JUQCS_C128 ? 5 : st->dt == JUQCS_C64 ? 6 : st->B;
+  TileGeom g{};
+  g.n = n;
+  g.block_bits = st->B;
+  g.L = b;
+  g.H = 0;
+  g.b = b;
+  hipError_t e = launch_expect(st->dt, st->amps, st->scales, g, 0, partials, res, st->stream);
+  if (e != hipSuccess) return hip_fail(e, "expectation launch");
+  for (int covered = b; covered < n;) {
+    const int H = std::min(b - L, n - covered);
+    g.L = L;
+    g.H = H;
+    g.b = L + H;
+    for (int i = 0; i < H; ++i) g.hbits[i] = covered + i;
+    e = launch_expect(st->dt, st->amps, st->scales, g, L, partials, res + 3 * covered, st->stream);
+    if (e != hipSuccess) return hip_fail(e, "expectation launch");
+    covered += H;
   }
-  hipError_t e = hipMemcpyAsync(sums.data(), res, 3 * st->n * sizeof(double),
-                                hipMemcpyDeviceToHost, st->stream);
+  std::vector<double> sums(3 * n);
+  e = hipMemcpyAsync(sums.data(), res, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
   if (juqcs_status rc = sync(st)) return rc;
-  for (int i = 0; i < 3 * st->n; ++i) out[i] = 0.5 * (1.0 - sums[i]);
+  for (int q = 0; q < n; ++q)
+    for (int c = 0; c < 3; ++c) out[3 * q + c] = 0.5 * (1.0 - sums[3 * st->phys[q] + c]);
   return JUQCS_OK;
 }
 

@@ -46,7 +46,8 @@ double plan_cost(const TilePlan& p) {
     double ops = 0.0;
     for (int o = 0; o < p.passes[i].op_count; ++o) {
       const TileOp& op = p.ops[p.passes[i].op_begin + o];
-      const int k = op.kind == TOP_DENSE1 ? 1 : op.kind == TOP_DENSE2 ? 2 : op.kind == TOP_DIAG2 ? 0
+      const int k = op.kind == TOP_DENSE1 ? 1 : op.kind == TOP_DENSE2 ? 2
+                    : op.kind == TOP_DIAG2 || op.kind == TOP_PERM ? 0
                     : op.kind == TOP_DENSE3 ? 3 : 4;
       ops += kSweep + kMac * (k ? (4 << k) : 1);
     }
@@ -74,7 +75,7 @@ void schedule_circuit(int n, const std::vector<Gate>& g, TileSchedule* sched) {
 void plan_circuit(int n, const std::vector<Gate>& g, int kin, TilePlan* plan) {
   TileSchedule sched;
   schedule_circuit(n, g, &sched);
-  emit_schedule(sched, g, kin, plan);
+  emit_schedule(sched, g, kin, plan, batch_mat_cap());
 }
 
 // Runs f(i) for i in [0, count) on the host's cores.
@@ -299,14 +300,14 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
       TileSchedule sched;
       schedule_circuit(n[c], dec[c], &sched);
       if (fuse > 0) {
-        emit_schedule(sched, dec[c], fuse, &plans[c]);
+        emit_schedule(sched, dec[c], fuse, &plans[c], batch_mat_cap());
         B->kin[c] = fuse;
         return;
       }
       double best = 1e300;
       for (int k = 2; k <= 4; ++k) {
         TilePlan p;
-        emit_schedule(sched, dec[c], k, &p);
+        emit_schedule(sched, dec[c], k, &p, batch_mat_cap());
         const double cst = plan_cost(p);
         if (cst < best) {
           best = cst;

@@ -47,6 +47,30 @@ struct Mat4 {
   cplx<T> m[16];  // row-major, index b_q0 + 2 b_q1
 };
 
+// Streaming accesses to state vectors: non-temporal, so data a pass touches
+// once does not evict from L2 the coefficients and tables it keeps
+// re-reading.  V is a scalar or a clang vector type.
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename V>
+__device__ __forceinline__ void st_stream(V* p, V v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> ld_amp(const cplx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return cplx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_amp(cplx<T>* p, cplx<T> a) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2{a.re, a.im}, reinterpret_cast<v2*>(p));
+}
+
 // Insert a zero bit at position pos of x (bits >= pos move up by one).
 __host__ __device__ inline uint64_t insert_zero(uint64_t x, int pos) {
   const uint64_t low = x & ((uint64_t(1) << pos) - 1);
@@ -66,6 +90,7 @@ struct TileGeom {
   int32_t hbits[kHbitsCap];      // ascending physical positions (>= L)
   int32_t block_bits;            // ENC2 only
   int32_t maxk;                  // widest op of the pass (1..4)
+  int32_t mat_count;             // coefficients of the pass's ops, from ops[0].moff on
 };
 
 enum TileOpKind : int32_t {
@@ -74,6 +99,8 @@ enum TileOpKind : int32_t {
   TOP_DIAG2 = 2,   // phases d[b_a + 2 b_b] (b may equal -1: d[b_a])
   TOP_DENSE3 = 3,  // 8x8 on local bits bits[0..3) (matrix order)
   TOP_DENSE4 = 4,  // 16x16 on local bits bits[0..4)
+  TOP_PERM = 5,    // monomial on local bits bits[0..k), k <= 3: out[r] =
+                   // c[r] in[sigma(r)], sigma(r) in bits 3r..3r+2 of a
 };
 
 struct TileOp {
@@ -117,6 +144,17 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales,
                        const TileGeom& g, const TileOp* d_ops, int nops,
                        const void* d_mats, hipStream_t s);
 int tile_max_bits(juqcs_dtype dt);
+// Expectation values of sigma^x,y,z for the tile bits jlo..b-1 of geometry
+// g (b <= expect_max_bits(), at most 16 bits per launch):
+// out3[3 (j - jlo) + c].  partials: expect_partials_bytes() of device memory.
+int expect_max_bits();
+size_t expect_partials_bytes();
+hipError_t launch_expect(juqcs_dtype dt, const void* amps, const void* scales, const TileGeom& g,
+                         int jlo, double* partials, double* out3, hipStream_t s);
+
+// Coefficients a pass of 2^b-amplitude tiles may carry so that it runs on
+// the pipelined kernel (which stages them in LDS); 0 = no limit.
+int tile_mat_cap(juqcs_dtype dt, int b);
 
 hipError_t launch_fused(juqcs_dtype dt, void* amps, int n, int k,
                         const int* targets, const void* d_mat, juqcs_mma mode,
@@ -128,12 +166,6 @@ hipError_t launch_encode2(const void* src, juqcs_dtype sdt, uint64_t count,
 hipError_t launch_decode2(const void* codes, const void* scales,
                           uint64_t count, int block_bits, void* dst,
                           juqcs_dtype ddt, hipStream_t s);
-// Sums over the pairs of target bit t: (2 Re conj(a0) a1, 2 Im conj(a0) a1,
-// |a0|^2 - |a1|^2) = (<sigma^x_t>, <sigma^y_t>, <sigma^z_t>), FP64, fixed order.
-hipError_t launch_pauli(juqcs_dtype dt, const void* amps, const void* scales, int n,
-                        int block_bits, int t, double* partials, double* out3,
-                        hipStream_t s);
-
 // ---------------------------------------------------------------------------
 // Batches (k_batch.hip, batch.cpp)
 // ---------------------------------------------------------------------------
@@ -168,6 +200,7 @@ struct BatchDevice {
 };
 
 int batch_max_bits();
+int batch_mat_cap();  // coefficients per pass staged in LDS by the batch kernel
 hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s);
 hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, const int32_t* nq,
                                int count, int m, const uint64_t* idx, double* out, hipStream_t s);
@@ -208,16 +241,20 @@ struct TileSchedule {
   std::vector<std::vector<int>> taken;
   int64_t gates = 0;
 };
+// max_take > 0 caps the gates one pass absorbs (later gates wait for the
+// next pass), which moves on-chip work from crowded passes to light ones.
 void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                  TileSchedule* sched);
-// Fuses every pass's gates into ops of at most kin qubits.
+                  TileSchedule* sched, int max_take = 0);
+// Fuses every pass's gates into ops of at most kin qubits.  A pass whose
+// coefficients would exceed max_mats (> 0) is split into consecutive passes
+// of the same geometry.
 void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, int kin,
-                   TilePlan* plan);
+                   TilePlan* plan, int max_mats = 0);
 
 // Plans tile passes for gates (physical qubits).  L, b: low contiguous bits
 // and total tile bits; the low L bits are always tile bits.
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan, int kin = 2);
+                TilePlan* plan, int kin = 2, int max_mats = 0, int max_take = 0);
 
 struct FusedBlock {
   std::vector<int> targets;           // physical

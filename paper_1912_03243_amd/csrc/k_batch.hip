@@ -19,11 +19,13 @@ namespace {
 
 using tileops::Fixed;
 using tileops::lds;
+using tileops::stage_mats;
 using tileops::Var;
 
 constexpr int kThreads = 256;       // helper kernels
 constexpr int kBatchThreads = 1024;  // the persistent batch kernel
 constexpr int kBatchMaxBits = 13;   // 64 KiB of C64 amplitudes per tile
+constexpr int kBatchMats = 8192;    // 64 KiB of C64 coefficients per pass
 
 __device__ inline uint64_t tile_base_hb(uint64_t tau, int L, int H, const int* hb) {
   uint64_t base = tau << L;
@@ -48,7 +50,7 @@ template <int TB>
 __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64_t tau0, int ntile,
                                        bool init, int L, int H, const int* hb,
                                        const uint64_t* choff, const TileOp* ops, int nops,
-                                       const cplx<float>* mats) {
+                                       const cplx<float>* mats, const cplx<float>* lmats) {
   constexpr int NA = 1 << TB, PER = NA / kBatchThreads;
   const int lmask = (1 << L) - 1;
   typedef float v2 __attribute__((ext_vector_type(2)));
@@ -85,7 +87,7 @@ __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64
         v[k] = gp[nb + choff[e >> L] + (e & lmask)];
       }
     }
-    Fixed<float, TB, kBatchThreads>::run(sh, ops, nops, mats);
+    Fixed<float, TB, kBatchThreads>::run(sh, ops, nops, mats, lmats);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = k * kBatchThreads + threadIdx.x;
@@ -125,6 +127,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     uint32_t spin_limit) {
   __shared__ cplx<float> sh[1 << kBatchMaxBits];
   __shared__ uint64_t choff[1 << kMaxGather];
+  __shared__ cplx<float> smat[kBatchMats];  // the current pass's coefficients
   __shared__ int hb[kHbitsCap];
   __shared__ long long s_t;
   __shared__ int s_g;
@@ -169,13 +172,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     const BatchPass ps = passes[grp.pass];
     const int b = ps.g.b, L = ps.g.L, H = ps.g.H;
     if (grp.pass != cur_pass) {
-      if (threadIdx.x < kHbitsCap) hb[threadIdx.x] = (int)threadIdx.x < H ? ps.g.hbits[threadIdx.x] : 0;
+      // (straight from the pass table: indexing the local copy by thread
+      // would put it in scratch)
+      if (threadIdx.x < kHbitsCap)
+        hb[threadIdx.x] = (int)threadIdx.x < H ? passes[grp.pass].g.hbits[threadIdx.x] : 0;
       __syncthreads();
       for (int c = threadIdx.x; c < (1 << H); c += kBatchThreads) {
         uint64_t o = 0;
         for (int j = 0; j < H; ++j) o |= (uint64_t)((c >> j) & 1) << hb[j];
         choff[c] = o;
       }
+      if (ps.g.mat_count <= kBatchMats)
+        stage_mats<float, kBatchThreads>(smat, mats + (ps.op_count > 0 ? ops[ps.op_begin].moff : 0),
+                                         ps.g.mat_count);
       __syncthreads();
       cur_pass = grp.pass;
     }
@@ -183,10 +192,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     const uint64_t tau0 = (uint64_t)(t - grp.first_chunk) * grp.chunk_tiles;
     const TileOp* pops = ops + ps.op_begin;
     const bool init = grp.init != 0;
-    switch (ps.g.maxk <= 3 ? b : 0) {  // the fixed-size paths run ops of up to 3 qubits
-      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats); break;
-      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats); break;
-      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats); break;
+    // the fixed-size paths run ops of up to 3 qubits with the coefficients in LDS
+    switch (ps.g.maxk <= 3 && ps.g.mat_count <= kBatchMats ? b : 0) {
+      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, smat); break;
+      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, smat); break;
+      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, smat); break;
       default: run_chunk_var(sh, psi, tau0, grp.chunk_tiles, init, b, L, H, hb, choff, pops, ps.op_count, mats); break;
     }
     // publish the finished tiles (release at agent scope)
@@ -275,6 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __rest
 }  // namespace
 
 int batch_max_bits() { return kBatchMaxBits; }
+int batch_mat_cap() { return kBatchMats; }
 
 hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3((d.count + kThreads - 1) / kThreads + 1), dim3(kThreads), 0,

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(
       if (c < ncols) {
         uint64_t base = c;
         for (int j = 0; j < k; ++j) base = insert_zero(base, tg.hbits[k + j]);
-        v = psi[base | off[r]];
+        v = ld_amp(&psi[base | off[r]]);
       }
       sB[(2 * r) * kCols + col] = v.re;
       sB[(2 * r + 1) * kCols + col] = v.im;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(
         cplx<T> v;
         v.re = sB[(2 * r) * kCols + col];
         v.im = sB[(2 * r + 1) * kCols + col];
-        psi[base | off[r]] = v;
+        st_amp(&psi[base | off[r]], v);
       }
     }
     __syncthreads();

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kThreads) void k_init(cplx<T>* __restrict__ psi,
     cplx<T> v;
     v.re = (i == idx) ? T(1) : T(0);
     v.im = T(0);
-    psi[i] = v;
+    st_amp(&psi[i], v);
   }
 }
 
@@ -41,10 +41,10 @@ __global__ __launch_bounds__(kThreads) void k_init_enc2(uint32_t* __restrict__ c
     // one 32-bit word holds the codes of two amplitudes
     uint32_t v = 0;
     if ((idx >> 1) == w) v = (idx & 1) ? (127u << 16) : 127u;
-    codes4[w] = v;
+    st_stream(&codes4[w], v);
   }
   for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < nblocks; b += stride)
-    scales[b] = (b == (idx >> block_bits)) ? 1.0f : 0.0f;
+    st_stream(&scales[b], (b == (idx >> block_bits)) ? 1.0f : 0.0f);
 }
 
 // ------------------------------------------------------------------ 1q ----
@@ -66,8 +66,8 @@ __global__ __launch_bounds__(kThreads) void k_1q(cplx<T>* __restrict__ psi, uint
     if (z1 >= 0) i = insert_zero(i, z1);
     ix[k] = i | cmask;
     if (p < npairs) {
-      a[k] = psi[ix[k]];
-      b[k] = psi[ix[k] | tbit];
+      a[k] = ld_amp(&psi[ix[k]]);
+      b[k] = ld_amp(&psi[ix[k] | tbit]);
     }
   }
 #pragma unroll
@@ -78,8 +78,8 @@ __global__ __launch_bounds__(kThreads) void k_1q(cplx<T>* __restrict__ psi, uint
       r0 = cmad(u.m[1], b[k], r0);
       cplx<T> r1 = cmul(u.m[2], a[k]);
       r1 = cmad(u.m[3], b[k], r1);
-      psi[ix[k]] = r0;
-      psi[ix[k] | tbit] = r1;
+      st_amp(&psi[ix[k]], r0);
+      st_amp(&psi[ix[k] | tbit], r1);
     }
   }
 }
@@ -101,12 +101,12 @@ __global__ __launch_bounds__(kThreads) void k_diag(cplx<T>* __restrict__ psi, ui
     uint64_t i = insert_zero(p, z0);
     if (z1 >= 0) i = insert_zero(i, z1);
     ix[k] = i | mask;
-    if (p < count) a[k] = psi[ix[k]];
+    if (p < count) a[k] = ld_amp(&psi[ix[k]]);
   }
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const uint64_t p = base + (uint64_t)k * kThreads;
-    if (p < count) psi[ix[k]] = cmul(ph, a[k]);
+    if (p < count) st_amp(&psi[ix[k]], cmul(ph, a[k]));
   }
 }
 
@@ -124,13 +124,13 @@ __global__ __launch_bounds__(kThreads) void k_2q(cplx<T>* __restrict__ psi, uint
     const uint64_t idx[4] = {i, i | b0, i | b1, i | b0 | b1};
     cplx<T> v[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = psi[idx[r]];
+    for (int r = 0; r < 4; ++r) v[r] = ld_amp(&psi[idx[r]]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       cplx<T> acc = cmul(m.m[4 * r], v[0]);
 #pragma unroll
       for (int c = 1; c < 4; ++c) acc = cmad(m.m[4 * r + c], v[c], acc);
-      psi[idx[r]] = acc;
+      st_amp(&psi[idx[r]], acc);
     }
   }
 }
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_norm_partial(const cplx<T>* __rest
   const uint64_t hi = lo + chunk < count ? lo + chunk : count;
   double acc = 0.0;
   for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const cplx<T> v = psi[i];
+    const cplx<T> v = ld_amp(&psi[i]);
     acc += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
   }
   const double r = block_sum(acc, sh);
@@ -252,10 +252,10 @@ __global__ __launch_bounds__(kThreads) void k_scale(cplx<T>* __restrict__ psi, u
                                                     T f) {
   const uint64_t stride = (uint64_t)gridDim.x * kThreads;
   for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < count; i += stride) {
-    cplx<T> v = psi[i];
+    cplx<T> v = ld_amp(&psi[i]);
     v.re *= f;
     v.im *= f;
-    psi[i] = v;
+    st_amp(&psi[i], v);
   }
 }
 
@@ -267,22 +267,26 @@ __global__ __launch_bounds__(kThreads) void k_scale_f32(float* __restrict__ x, u
 }
 
 // ---------------------------------------------------------------- copy ----
-// Reference streaming copy: each thread moves 4 x 16 bytes per iteration.
+// Reference streaming copy: each thread moves 4 x 16 bytes per iteration,
+// with the same non-temporal accesses as the state passes.
 __global__ __launch_bounds__(kThreads) void k_copy(uint4* __restrict__ dst,
                                                    const uint4* __restrict__ src,
                                                    uint64_t count) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
   constexpr int U = 4;
   const uint64_t base = (uint64_t)blockIdx.x * (kThreads * U) + threadIdx.x;
-  uint4 v[U];
+  const v4u* s4 = reinterpret_cast<const v4u*>(src);
+  v4u* d4 = reinterpret_cast<v4u*>(dst);
+  v4u v[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const uint64_t i = base + (uint64_t)k * kThreads;
-    if (i < count) v[k] = src[i];
+    if (i < count) v[k] = ld_stream(&s4[i]);
   }
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const uint64_t i = base + (uint64_t)k * kThreads;
-    if (i < count) dst[i] = v[k];
+    if (i < count) st_stream(&d4[i], v[k]);
   }
 }
 

@@ -12,8 +12,11 @@
 //
 // The fixed-size kernels (tile size known at compile time, 512 or 1024 threads) run
 // on a persistent grid and prefetch the next tile into registers while the
-// current one is processed on chip; the generic kernels cover small states.
+// current one is processed on chip; they stage the pass's coefficients in LDS
+// (the 8x8 ops run on the matrix cores).  The generic kernels cover small
+// states and passes with 4-qubit ops.
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "tile_ops.hpp"
@@ -24,7 +27,11 @@ namespace {
 
 using tileops::Fixed;
 using tileops::lds;
+using tileops::mat_slots;
+using tileops::stage_mats;
 using tileops::Var;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;       // generic kernels
 constexpr int kFixedThreads = 512;  // pipelined kernels
@@ -48,6 +55,22 @@ struct GeomLds {
   uint64_t choff[1 << kMaxGather];
 };
 
+// LDS coefficient slots of the pipelined kernels (512-thread kernels run
+// two workgroups per CU); only the FP32 kernels stage coefficients.
+template <typename T, int TB, int NT>
+struct FixedMats {
+  static constexpr int kSlots =
+      Fixed<T, TB, NT>::kMma ? mat_slots((int)sizeof(cplx<T>) << TB, (int)sizeof(GeomLds),
+                                         (int)sizeof(cplx<T>), NT == 512 ? 2 : 1)
+                             : 0;
+};
+template <int TB>
+struct Enc2Mats {
+  static constexpr int kSlots = mat_slots((int)sizeof(cplx<float>) << TB,
+                                          (int)sizeof(GeomLds) + (4 << TB) / 8,
+                                          (int)sizeof(cplx<float>), 2);
+};
+
 template <int NT>
 __device__ inline void load_geom(const TileGeom& g, GeomLds& s) {
   if (threadIdx.x < kHbitsCap) s.hb[threadIdx.x] = (int)threadIdx.x < g.H ? g.hbits[threadIdx.x] : 0;
@@ -58,6 +81,15 @@ __device__ inline void load_geom(const TileGeom& g, GeomLds& s) {
     s.choff[c] = o;
   }
   __syncthreads();
+}
+
+// Tiles [lo, hi) of this workgroup in a persistent grid of at most ntiles
+// workgroups: a contiguous run, so that consecutive tiles of a CU touch the
+// same memory pages and the CU keeps reusing its address translations.
+__device__ inline void tile_run(uint64_t ntiles, uint64_t* lo, uint64_t* hi) {
+  const uint64_t per = ntiles / gridDim.x, extra = ntiles % gridDim.x, b = blockIdx.x;
+  *lo = b * per + (b < extra ? b : extra);
+  *hi = *lo + per + (b < extra ? 1 : 0);
 }
 
 // Base index of tile tau: tau's bits fill the non-tile positions in order.
@@ -89,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(cplx<T>* __restrict__ psi, Ti
       for (int k = 0; k < 8; ++k) {
         const int e = e0 + k * kThreads + threadIdx.x;
         const int ec = e < tile_amps ? e : 0;
-        v[k] = gp[base + gs.choff[ec >> L] + (ec & lmask)];
+        v[k] = ld_stream(&gp[base + gs.choff[ec >> L] + (ec & lmask)]);
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
@@ -100,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(cplx<T>* __restrict__ psi, Ti
     __syncthreads();
     Var<T, kThreads>::run(sh, b, ops, nops, mats);
     for (int e = threadIdx.x; e < tile_amps; e += kThreads)
-      gp[base + gs.choff[e >> L] + (e & lmask)] = sp[lds<T>(e)];
+      st_stream(&gp[base + gs.choff[e >> L] + (e & lmask)], sp[lds<T>(e)]);
     __syncthreads();
   }
 }
@@ -115,7 +147,10 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
   constexpr int NA = 1 << TB, PER = NA / NT;
   __shared__ cplx<T> sh[NA];
   __shared__ GeomLds gs;
-  load_geom<NT>(g, gs);
+  constexpr int kSlots = FixedMats<T, TB, NT>::kSlots;
+  __shared__ cplx<T> smat[kSlots > 0 ? kSlots : 1];
+  if (kSlots > 0) stage_mats<T, NT>(smat, mats + (nops > 0 ? ops[0].moff : 0), g.mat_count);
+  load_geom<NT>(g, gs);  // synchronises
   const int H = g.H, L = g.L, lmask = (1 << L) - 1;
   const uint64_t ntiles = uint64_t(1) << (g.n - TB);
   // a native 2-vector keeps the prefetch buffer in registers (an array of
@@ -124,37 +159,37 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
   v2* gp = reinterpret_cast<v2*>(psi);
   v2* sp = reinterpret_cast<v2*>(sh);
   v2 v[PER];
-  uint64_t tau = blockIdx.x;  // the grid never exceeds ntiles
+  uint64_t tau, tau_end;
+  tile_run(ntiles, &tau, &tau_end);
   {
     const uint64_t base = tile_base(tau, L, H, gs.hb);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = k * NT + threadIdx.x;
-      v[k] = gp[base + gs.choff[e >> L] + (e & lmask)];
+      v[k] = ld_stream(&gp[base + gs.choff[e >> L] + (e & lmask)]);
     }
   }
-  for (; tau < ntiles; tau += gridDim.x) {
+  for (; tau < tau_end; ++tau) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) sp[lds<T>(k * NT + threadIdx.x)] = v[k];
     __syncthreads();
     // prefetch the next tile while this one is on chip; after the last tile
     // the current one is read again (in bounds, values unused)
-    const uint64_t nxt = tau + gridDim.x;
-    const uint64_t pf = nxt < ntiles ? nxt : tau;
+    const uint64_t pf = tau + 1 < tau_end ? tau + 1 : tau;
     {
       const uint64_t nb = tile_base(pf, L, H, gs.hb);
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const int e = k * NT + threadIdx.x;
-        v[k] = gp[nb + gs.choff[e >> L] + (e & lmask)];
+        v[k] = ld_stream(&gp[nb + gs.choff[e >> L] + (e & lmask)]);
       }
     }
-    Fixed<T, TB, NT>::run(sh, ops, nops, mats);
+    Fixed<T, TB, NT>::run(sh, ops, nops, mats, smat);
     const uint64_t base = tile_base(tau, L, H, gs.hb);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = k * NT + threadIdx.x;
-      gp[base + gs.choff[e >> L] + (e & lmask)] = sp[lds<T>(e)];
+      st_stream(&gp[base + gs.choff[e >> L] + (e & lmask)], sp[lds<T>(e)]);
     }
     __syncthreads();
   }
@@ -214,8 +249,9 @@ __device__ inline void store_enc2(const cplx<float>* sh, uint32_t* bmax, int til
     const uint64_t gi = base + choff[e >> L] + (e & lmask);
     const float s = __uint_as_float(bmax[e >> B]);
     const bool zero = !(s >= kTiny);
-    *reinterpret_cast<int4*>(codes + 2 * gi) = zero ? make_int4(0, 0, 0, 0) : encode8(sh, e, 127.0f / s);
-    if ((e & ((1 << B) - 1)) == 0) scales[gi >> B] = zero ? 0.0f : s;
+    const int4 w = zero ? make_int4(0, 0, 0, 0) : encode8(sh, e, 127.0f / s);
+    st_stream(reinterpret_cast<v4i*>(codes + 2 * gi), v4i{w.x, w.y, w.z, w.w});
+    if ((e & ((1 << B) - 1)) == 0) st_stream(&scales[gi >> B], zero ? 0.0f : s);
   }
 }
 
@@ -237,7 +273,8 @@ __global__ __launch_bounds__(kThreads) void k_tile_enc2(int8_t* __restrict__ cod
     for (int gq = threadIdx.x; gq < ngroups; gq += kThreads) {
       const int e = gq << 3;
       const uint64_t gi = base + gs.choff[e >> L] + (e & lmask);
-      decode8(*reinterpret_cast<const int4*>(codes + 2 * gi), scales[gi >> B] / 127.0f, sh, e);
+      const v4i w = ld_stream(reinterpret_cast<const v4i*>(codes + 2 * gi));
+      decode8(make_int4(w.x, w.y, w.z, w.w), ld_stream(&scales[gi >> B]) / 127.0f, sh, e);
     }
     __syncthreads();
     Var<float, kThreads>::run(sh, b, ops, nops, mats);
@@ -256,7 +293,9 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
   __shared__ cplx<float> sh[NA];
   __shared__ GeomLds gs;
   __shared__ uint32_t bmax[NA / 8];
-  load_geom<kFixedThreads>(g, gs);
+  __shared__ cplx<float> smat[Enc2Mats<TB>::kSlots];
+  stage_mats<float, kFixedThreads>(smat, mats + (nops > 0 ? ops[0].moff : 0), g.mat_count);
+  load_geom<kFixedThreads>(g, gs);  // synchronises
   const int H = g.H, L = g.L, B = g.block_bits, lmask = (1 << L) - 1;
   const int nblk = NA >> B;
   const uint64_t ntiles = uint64_t(1) << (g.n - TB);
@@ -269,13 +308,15 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
       const int gq = k * kFixedThreads + threadIdx.x;
       const int e = (NG % kFixedThreads == 0 || gq < NG) ? gq << 3 : 0;
       const uint64_t gi = base + gs.choff[e >> L] + (e & lmask);
-      raw[k] = *reinterpret_cast<const int4*>(codes + 2 * gi);
-      sc[k] = scales[gi >> B];
+      const v4i w = ld_stream(reinterpret_cast<const v4i*>(codes + 2 * gi));
+      raw[k] = make_int4(w.x, w.y, w.z, w.w);
+      sc[k] = ld_stream(&scales[gi >> B]);
     }
   };
-  uint64_t tau = blockIdx.x;  // the grid never exceeds ntiles
+  uint64_t tau, tau_end;
+  tile_run(ntiles, &tau, &tau_end);
   fetch(tau);
-  for (; tau < ntiles; tau += gridDim.x) {
+  for (; tau < tau_end; ++tau) {
     for (int q = threadIdx.x; q < nblk; q += kFixedThreads) bmax[q] = 0u;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -283,13 +324,150 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
       if (NG % kFixedThreads == 0 || gq < NG) decode8(raw[k], sc[k] / 127.0f, sh, gq << 3);
     }
     __syncthreads();
-    const uint64_t nxt = tau + gridDim.x;
-    fetch(nxt < ntiles ? nxt : tau);
-    Fixed<float, TB, kFixedThreads>::run(sh, ops, nops, mats);
+    fetch(tau + 1 < tau_end ? tau + 1 : tau);
+    Fixed<float, TB, kFixedThreads>::run(sh, ops, nops, mats, smat);
     store_enc2<kFixedThreads>(sh, bmax, NA, B, L, lmask, tile_base(tau, L, H, gs.hb), gs.choff,
                               codes, scales);
     __syncthreads();
   }
+}
+
+// ------------------------------------------------- expectation values ----
+// <sigma^x_j>, <sigma^y_j>, <sigma^z_j> for the tile bits jlo..b-1 of one
+// tile geometry: sums over the amplitude pairs that differ in bit j, of
+// (2 Re conj(a0) a1, 2 Im conj(a0) a1, |a0|^2 - |a1|^2), in FP64.  Both
+// members of every such pair lie in one tile, so one read pass covers b bits
+// (Section 3: the expectation values of all qubits).  With nb = b - jlo new
+// bits, wave w reduces bit jlo + w % nb over the share w / nb of the pairs
+// (a power-of-two number of shares, at most 16 / nb); every sum runs over a
+// fixed set of pairs in a fixed order.  The next tile is prefetched into registers while one is reduced.
+constexpr int kExpectThreads = 1024;
+constexpr int kExpectBits = 13;
+constexpr int kExpectWaves = kExpectThreads / 64;
+
+template <typename S>  // storage: double (C128), float (C64), int8_t (ENC2)
+__global__ __launch_bounds__(kExpectThreads) void k_expect(const void* __restrict__ amps,
+                                                           const float* __restrict__ scales,
+                                                           TileGeom g, int jlo,
+                                                           double* __restrict__ partials) {
+  using T = typename std::conditional<sizeof(S) == 8, double, float>::type;
+  constexpr int NA = 1 << kExpectBits;
+  constexpr int CB = (int)sizeof(cplx<T>);
+  __shared__ cplx<T> sh[NA];
+  __shared__ GeomLds gs;
+  load_geom<kExpectThreads>(g, gs);
+  const int b = g.b, L = g.L, lmask = (1 << L) - 1, tile_amps = 1 << b;
+  const uint64_t ntiles = uint64_t(1) << (g.n - b);
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = b - jlo;
+  int shares = 1;  // a power of two (the pair index splits bitwise)
+  while (2 * shares * nb <= kExpectWaves) shares *= 2;
+  const int j = jlo + wave % nb, share = wave / nb;
+  const bool active = share < shares;
+  // pair p = (it * shares + share) * 64 + lane: e0 = spread(p) splits into a
+  // uniform part and the lane's part; offsets in bytes
+  const int pos[1] = {j};
+  const int lane_off = tileops::lds<T>(tileops::spread<1>(lane, pos)) * CB;
+  const int partner = tileops::lds<T>(1 << j) * CB;
+  const int npairs = tile_amps >> 1;
+  const char* base = reinterpret_cast<const char*>(sh);
+  // register prefetch: whole amplitudes (C128/C64) or 16-byte code groups
+  constexpr int PER = sizeof(S) == 1 ? NA / 8 / kExpectThreads : NA / kExpectThreads;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  typedef typename std::conditional<sizeof(S) == 1, v4i, v2>::type Item;
+  Item v[PER];
+  float sc[PER];
+  auto fetch = [&](uint64_t tau) {
+    const uint64_t tb = tile_base(tau, L, g.H, gs.hb);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int q = k * kExpectThreads + threadIdx.x;
+      if constexpr (sizeof(S) == 1) {
+        const int e = (q << 3) < tile_amps ? q << 3 : 0;
+        const uint64_t gi = tb + gs.choff[e >> L] + (e & lmask);
+        v[k] = ld_stream(reinterpret_cast<const v4i*>((const int8_t*)amps + 2 * gi));
+        sc[k] = ld_stream(&scales[gi >> g.block_bits]);
+      } else {
+        const int e = q < tile_amps ? q : 0;
+        v[k] = ld_stream(&reinterpret_cast<const v2*>(amps)[tb + gs.choff[e >> L] + (e & lmask)]);
+      }
+    }
+  };
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  uint64_t tau, tau_end;
+  tile_run(ntiles, &tau, &tau_end);
+  fetch(tau);
+  for (; tau < tau_end; ++tau) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int q = k * kExpectThreads + threadIdx.x;
+      if constexpr (sizeof(S) == 1) {
+        if ((q << 3) < tile_amps) decode8(make_int4(v[k].x, v[k].y, v[k].z, v[k].w), sc[k] / 127.0f, sh, q << 3);
+      } else {
+        if (q < tile_amps) reinterpret_cast<v2*>(sh)[lds<T>(q)] = v[k];
+      }
+    }
+    __syncthreads();
+    fetch(tau + 1 < tau_end ? tau + 1 : tau);
+    if (active) {
+      // rows of 64 pairs, wave-uniform; four rows' reads are issued together
+      const int step = 64 * shares;
+      auto pair = [&](const cplx<T>& x, const cplx<T>& y) {
+        const double ar = x.re, ai = x.im, br = y.re, bi = y.im;
+        sx = fma(ar, br, fma(ai, bi, sx));
+        sy = fma(ar, bi, fma(-ai, br, sy));
+        sz += fma(ar, ar, ai * ai) - fma(br, br, bi * bi);
+      };
+      int p0 = share * 64;
+      if (npairs >= 64) {
+        for (; p0 + 3 * step < npairs; p0 += 4 * step) {
+          cplx<T> x[4], y[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int u = (tileops::lds<T>(tileops::spread<1>(p0 + r * step, pos)) * CB) ^ lane_off;
+            x[r] = *reinterpret_cast<const cplx<T>*>(base + u);
+            y[r] = *reinterpret_cast<const cplx<T>*>(base + (u ^ partner));
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pair(x[r], y[r]);
+        }
+        for (; p0 < npairs; p0 += step) {
+          const int u = (tileops::lds<T>(tileops::spread<1>(p0, pos)) * CB) ^ lane_off;
+          pair(*reinterpret_cast<const cplx<T>*>(base + u),
+               *reinterpret_cast<const cplx<T>*>(base + (u ^ partner)));
+        }
+      } else if (p0 == 0 && lane < npairs) {  // tiles of fewer than 128 amplitudes
+        pair(*reinterpret_cast<const cplx<T>*>(base + lane_off),
+             *reinterpret_cast<const cplx<T>*>(base + (lane_off ^ partner)));
+      }
+    }
+    __syncthreads();
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off, 64);
+    sy += __shfl_xor(sy, off, 64);
+    sz += __shfl_xor(sz, off, 64);
+  }
+  if (lane == 0) {
+    double* o = partials + 3 * ((size_t)wave * gridDim.x + blockIdx.x);
+    o[0] = active ? 2.0 * sx : 0.0;
+    o[1] = active ? 2.0 * sy : 0.0;
+    o[2] = active ? sz : 0.0;
+  }
+}
+
+// out3[3 k + c]: bit jlo + k, summed over its waves (k, k + nb, ...) and
+// over blocks, in that order.
+__global__ __launch_bounds__(64) void k_expect_final(const double* __restrict__ partials, int nblk,
+                                                     int nbits, double* __restrict__ out3) {
+  const int k = threadIdx.x / 3, c = threadIdx.x % 3;
+  if (k >= nbits) return;
+  double s = 0.0;
+  int shares = 1;
+  while (2 * shares * nbits <= kExpectWaves) shares *= 2;
+  for (int w = k; w < shares * nbits; w += nbits)
+    for (int i = 0; i < nblk; ++i) s += partials[3 * ((size_t)w * nblk + i) + c];
+  out3[3 * k + c] = s;
 }
 
 // Workgroups of a kernel that fit on the device at once (cached per kernel).
@@ -319,6 +497,18 @@ int tile_max_bits(juqcs_dtype dt) {
   return dt == JUQCS_C128 ? TileCfg<double>::kMaxBits : TileCfg<float>::kMaxBits;
 }
 
+int tile_mat_cap(juqcs_dtype dt, int b) {
+  if (dt == JUQCS_C64) {
+    if (b == 13) return FixedMats<float, 13, 1024>::kSlots;
+    if (b == 12) return FixedMats<float, 12, 512>::kSlots;
+    if (b == 11) return FixedMats<float, 11, 512>::kSlots;
+  } else if (dt == JUQCS_ENC2) {
+    if (b == 13) return Enc2Mats<13>::kSlots;
+    if (b == 12) return Enc2Mats<12>::kSlots;
+  }
+  return 0;
+}
+
 hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom& g,
                        const TileOp* d_ops, int nops, const void* d_mats, hipStream_t s) {
   const uint64_t ntiles = uint64_t(1) << (g.n - g.b);
@@ -331,23 +521,23 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
 #define JUQCS_FIXED(T, TB, NT)                                                             \
   hipLaunchKernelGGL((k_tile_fixed<T, TB, NT>), pgrid((const void*)k_tile_fixed<T, TB, NT>, NT), \
                      dim3(NT), 0, s, (cplx<T>*)amps, g, d_ops, nops, (const cplx<T>*)d_mats)
-  const bool fixed_ok = g.maxk <= 3;  // the pipelined kernels run ops of up to 3 qubits
+  // the pipelined kernels run ops of up to 3 qubits, with the coefficients in LDS
+  const int cap = tile_mat_cap(dt, g.b);  // 0: coefficients stay in global memory
+  const bool fixed_ok = g.maxk <= 3 && (cap == 0 || g.mat_count <= cap);
   if (dt == JUQCS_C128) {
     auto* p = (cplx<double>*)amps;
     auto* m = (const cplx<double>*)d_mats;
-    if (!fixed_ok) hipLaunchKernelGGL((k_tile<double, 13>), grid, block, 0, s, p, g, d_ops, nops, m);
-    else if (g.b == 13) JUQCS_FIXED(double, 13, 1024);
-    else if (g.b == 12) JUQCS_FIXED(double, 12, 512);
-    else if (g.b == 11) JUQCS_FIXED(double, 11, 512);
+    if (fixed_ok && g.b == 13) JUQCS_FIXED(double, 13, 1024);
+    else if (fixed_ok && g.b == 12) JUQCS_FIXED(double, 12, 512);
+    else if (fixed_ok && g.b == 11) JUQCS_FIXED(double, 11, 512);
     else if (g.b <= 12) hipLaunchKernelGGL((k_tile<double, 12>), grid, block, 0, s, p, g, d_ops, nops, m);
     else hipLaunchKernelGGL((k_tile<double, 13>), grid, block, 0, s, p, g, d_ops, nops, m);
   } else if (dt == JUQCS_C64) {
     auto* p = (cplx<float>*)amps;
     auto* m = (const cplx<float>*)d_mats;
-    if (!fixed_ok) hipLaunchKernelGGL((k_tile<float, 14>), grid, block, 0, s, p, g, d_ops, nops, m);
-    else if (g.b == 13) JUQCS_FIXED(float, 13, 1024);
-    else if (g.b == 12) JUQCS_FIXED(float, 12, 512);
-    else if (g.b == 11) JUQCS_FIXED(float, 11, 512);
+    if (fixed_ok && g.b == 13) JUQCS_FIXED(float, 13, 1024);
+    else if (fixed_ok && g.b == 12) JUQCS_FIXED(float, 12, 512);
+    else if (fixed_ok && g.b == 11) JUQCS_FIXED(float, 11, 512);
     else if (g.b <= 13) hipLaunchKernelGGL((k_tile<float, 13>), grid, block, 0, s, p, g, d_ops, nops, m);
     else hipLaunchKernelGGL((k_tile<float, 14>), grid, block, 0, s, p, g, d_ops, nops, m);
   } else {
@@ -364,6 +554,31 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
       hipLaunchKernelGGL(k_tile_enc2, grid, block, 0, s, c, sc, g, d_ops, nops, m);
   }
 #undef JUQCS_FIXED
+  return hipGetLastError();
+}
+
+int expect_max_bits() { return kExpectBits; }
+
+size_t expect_partials_bytes() {
+  return sizeof(double) * 3 * kExpectWaves *
+         (size_t)resident_blocks((const void*)k_expect<double>, kExpectThreads);
+}
+
+hipError_t launch_expect(juqcs_dtype dt, const void* amps, const void* scales, const TileGeom& g,
+                         int jlo, double* partials, double* out3, hipStream_t s) {
+  const int nbits = g.b - jlo;
+  if (g.b > kExpectBits || nbits < 1 || nbits > kExpectWaves) return hipErrorInvalidValue;
+  const uint64_t ntiles = uint64_t(1) << (g.n - g.b);
+  const uint64_t slots = resident_blocks((const void*)k_expect<double>, kExpectThreads);
+  const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
+  const dim3 block(kExpectThreads);
+  if (dt == JUQCS_C128)
+    hipLaunchKernelGGL(k_expect<double>, dim3(grid), block, 0, s, amps, (const float*)scales, g, jlo, partials);
+  else if (dt == JUQCS_C64)
+    hipLaunchKernelGGL(k_expect<float>, dim3(grid), block, 0, s, amps, (const float*)scales, g, jlo, partials);
+  else
+    hipLaunchKernelGGL(k_expect<int8_t>, dim3(grid), block, 0, s, amps, (const float*)scales, g, jlo, partials);
+  hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(64), 0, s, partials, (int)grid, nbits, out3);
   return hipGetLastError();
 }
 

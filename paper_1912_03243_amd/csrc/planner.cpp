@@ -59,6 +59,27 @@ void expand(const C* g, const int* gq, int gk, const int* space, int k, C* out) 
     }
 }
 
+// One nonzero entry per row, in distinct columns: row r reads column
+// sigma(r), packed 3 bits per row (dim <= 8).
+bool monomial(const C* m, int dim, int* sigma) {
+  int packed = 0, used = 0;
+  for (int r = 0; r < dim; ++r) {
+    int col = -1;
+    for (int c = 0; c < dim; ++c) {
+      const C z = m[r * dim + c];
+      if (z.re != 0.0 || z.im != 0.0) {
+        if (col >= 0) return false;
+        col = c;
+      }
+    }
+    if (col < 0 || (used >> col) & 1) return false;
+    used |= 1 << col;
+    packed |= col << (3 * r);
+  }
+  *sigma = packed;
+  return true;
+}
+
 bool is_diag(const C* m, int dim) {
   for (int r = 0; r < dim; ++r)
     for (int c = 0; c < dim; ++c)
@@ -245,11 +266,20 @@ void emit_ops(const std::vector<Cluster>& cl, const TileGeom& geom, TilePlan* pl
     const int dim = 1 << k;
     op.k = k;
     op.moff = (int64_t)plan->mats.size();
+    int sigma = 0;
     if (is_diag(c.m.data(), dim) && k <= 2) {
       op.kind = TOP_DIAG2;
       op.a = local(c.q[0]);
       op.b = k == 2 ? local(c.q[1]) : -1;
       for (int r = 0; r < 4; ++r) plan->mats.push_back(c.m[(r % dim) * dim + (r % dim)]);
+    } else if (k <= 3 && monomial(c.m.data(), dim, &sigma)) {
+      // permutations with phases (CNOT, X, SWAP, CZ chains, ...): one
+      // coefficient per row instead of a dense matrix
+      op.kind = TOP_PERM;
+      op.a = sigma;
+      op.b = -1;
+      for (int j = 0; j < k; ++j) op.bits[j] = local(c.q[j]);
+      for (int r = 0; r < dim; ++r) plan->mats.push_back(c.m[r * dim + ((sigma >> (3 * r)) & 7)]);
     } else if (k == 1) {
       op.kind = TOP_DENSE1;
       op.a = local(c.q[0]);
@@ -274,7 +304,7 @@ void emit_ops(const std::vector<Cluster>& cl, const TileGeom& geom, TilePlan* pl
 }  // namespace
 
 void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                  TileSchedule* sched) {
+                  TileSchedule* sched, int max_take) {
   sched->passes.clear();
   sched->taken.clear();
   sched->gates = (int64_t)gates.size();
@@ -335,7 +365,7 @@ void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& 
     std::vector<char> blocked(n, 0);
     for (int gi : rem) {
       const Gate& g = gates[gi];
-      bool ok = true;
+      bool ok = max_take <= 0 || (int)taken.size() < max_take;
       for (int j = 0; j < g.nq; ++j)
         if (!in_tile[g.q[j]] || blocked[g.q[j]]) ok = false;
       if (ok) {
@@ -359,8 +389,17 @@ void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& 
   }
 }
 
+// Coefficients emit_ops stores for a cluster.
+int cluster_coefs(const Cluster& c) {
+  const int k = (int)c.q.size();
+  int sigma = 0;
+  if (k <= 2 && is_diag(c.m.data(), 1 << k)) return 4;
+  if (k <= 3 && monomial(c.m.data(), 1 << k, &sigma)) return 1 << k;
+  return (1 << k) * (1 << k);
+}
+
 void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, int kin,
-                   TilePlan* plan) {
+                   TilePlan* plan, int max_mats) {
   plan->passes.clear();
   plan->ops.clear();
   plan->mats.clear();
@@ -368,23 +407,39 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
   plan->gates = sched.gates;
   kin = std::max(1, std::min(kin, 4));  // on-chip fusion width
   for (size_t i = 0; i < sched.passes.size(); ++i) {
-    TilePass pass = sched.passes[i];
     std::vector<Cluster> cl;
     fuse(gates, sched.taken[i], kin, &cl);
-    pass.op_begin = (int32_t)plan->ops.size();
-    emit_ops(cl, pass.g, plan);
-    pass.op_count = (int32_t)plan->ops.size() - pass.op_begin;
-    pass.g.maxk = 1;
-    for (const Cluster& c : cl) pass.g.maxk = std::max(pass.g.maxk, (int32_t)c.q.size());
-    plan->passes.push_back(pass);
+    // consecutive runs of clusters whose coefficients fit max_mats
+    size_t c0 = 0;
+    do {
+      size_t c1 = c0;
+      int coefs = 0;
+      while (c1 < cl.size()) {
+        const int w = cluster_coefs(cl[c1]);
+        if (max_mats > 0 && c1 > c0 && coefs + w > max_mats) break;
+        coefs += w;
+        ++c1;
+      }
+      const std::vector<Cluster> part(cl.begin() + c0, cl.begin() + c1);
+      TilePass pass = sched.passes[i];
+      pass.op_begin = (int32_t)plan->ops.size();
+      const int64_t m0 = (int64_t)plan->mats.size();
+      emit_ops(part, pass.g, plan);
+      pass.op_count = (int32_t)plan->ops.size() - pass.op_begin;
+      pass.g.mat_count = (int32_t)((int64_t)plan->mats.size() - m0);
+      pass.g.maxk = 1;
+      for (const Cluster& c : part) pass.g.maxk = std::max(pass.g.maxk, (int32_t)c.q.size());
+      plan->passes.push_back(pass);
+      c0 = c1;
+    } while (c0 < cl.size());
   }
 }
 
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan, int kin) {
+                TilePlan* plan, int kin, int max_mats, int max_take) {
   TileSchedule sched;
-  select_tiles(n, L, b, block_bits, gates, &sched);
-  emit_schedule(sched, gates, kin, plan);
+  select_tiles(n, L, b, block_bits, gates, &sched, max_take);
+  emit_schedule(sched, gates, kin, plan, max_mats);
 }
 
 void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan) {
@@ -396,6 +451,8 @@ void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan) {
     C* dst = plan->mats.data() + op.moff;
     if (op.kind == TOP_DIAG2) {
       for (int r = 0; r < 4; ++r) dst[r] = c.m[(r % dim) * dim + (r % dim)];
+    } else if (op.kind == TOP_PERM) {
+      for (int r = 0; r < dim; ++r) dst[r] = c.m[r * dim + ((op.a >> (3 * r)) & 7)];
     } else {
       for (int i = 0; i < dim * dim; ++i) dst[i] = c.m[i];
     }

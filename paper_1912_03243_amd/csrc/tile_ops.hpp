@@ -6,7 +6,9 @@
 //  * Fixed<T, TB, NT> compile-time tile size: every loop has a constant trip
 //    count and is unrolled, and each op reads all of its operands before it
 //    writes, so the LDS reads of a thread are issued back to back.
-// Op kinds: dense 2x2 / 4x4 / 8x8 / 16x16 and two-bit diagonals (TileOp).
+// Op kinds: dense 2x2 / 4x4 / 8x8 / 16x16, two-bit diagonals and monomial
+// (permutation times phases) ops on up to three bits (TileOp).
+// In the fixed form the FP32 8x8 ops run on the matrix cores (16x16x4 MFMA).
 #pragma once
 
 #include "juqcs_internal.hpp"
@@ -17,8 +19,9 @@ namespace tileops {
 // LDS slot of tile element e: e XOR a fold of its higher bits into the bits
 // that pick the bank inside a 256-byte row (16 FP64 or 32 FP32 complex
 // amplitudes).  Ops whose lanes step by large powers of two then spread over
-// the banks instead of piling onto a few.  A bijection: the folded bits
-// themselves are left unchanged.
+// the banks instead of piling onto a few.  A bijection (the folded bits
+// themselves are left unchanged), and linear over XOR:
+// lds(a ^ b) = lds(a) ^ lds(b).
 template <typename T>
 __device__ __forceinline__ int lds(int e) {
   constexpr int S = sizeof(T) == 8 ? 4 : 5;
@@ -63,6 +66,17 @@ __device__ inline int group_base(int p, const int* sorted) {
 #pragma unroll
   for (int j = 0; j < K; ++j) i = (int)insert_zero((uint64_t)i, sorted[j]);
   return i;
+}
+
+// 32-bit group_base for tile-local indices.  Spreading is a bit
+// permutation, so spread(x | y) = spread(x) | spread(y) for disjoint x, y;
+// together with the XOR-linear LDS swizzle this splits every element
+// address into a wave-uniform part and a per-lane part fixed for the op.
+template <int K>
+__device__ inline int spread(int x, const int* sorted) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) x = ((x >> sorted[j]) << (sorted[j] + 1)) | (x & ((1 << sorted[j]) - 1));
+  return x;
 }
 
 template <int K>
@@ -130,6 +144,23 @@ struct Var {
     }
   }
 
+  // monomial: out[r] = c[r] in[sigma(r)] on the group of 2^K amplitudes
+  template <int K>
+  __device__ static void perm(cplx<T>* sh, int b, const int32_t* bits, int sigma,
+                              const cplx<T>* __restrict__ m) {
+    constexpr int D = 1 << K;
+    int bt[K], sorted[K];
+    sort_bits<K>(bits, bt, sorted);
+    for (int p = threadIdx.x; p < (1 << (b - K)); p += NT) {
+      const int i = group_base<K>(p, sorted);
+      cplx<T> v[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) v[r] = sh[lds<T>(i | row_offset<K>((sigma >> (3 * r)) & 7, bt))];
+#pragma unroll
+      for (int r = 0; r < D; ++r) sh[lds<T>(i | row_offset<K>(r, bt))] = cmul(m[r], v[r]);
+    }
+  }
+
   __device__ static void run(cplx<T>* sh, int b, const TileOp* __restrict__ ops, int nops,
                              const cplx<T>* __restrict__ mats) {
     for (int o = 0; o < nops; ++o) {
@@ -141,6 +172,11 @@ struct Var {
         case TOP_DIAG2: diag2(sh, b, op.a, op.b, m); break;
         case TOP_DENSE3: densek<3>(sh, b, op.bits, m); break;
         case TOP_DENSE4: densek<4>(sh, b, op.bits, m); break;
+        case TOP_PERM:
+          if (op.k == 1) perm<1>(sh, b, op.bits, op.a, m);
+          else if (op.k == 2) perm<2>(sh, b, op.bits, op.a, m);
+          else perm<3>(sh, b, op.bits, op.a, m);
+          break;
         default: break;
       }
       __syncthreads();
@@ -157,27 +193,34 @@ template <typename T, int TB, int NT>
 struct Fixed {
   static constexpr int NA = 1 << TB;
 
+  // Element addresses below are byte offsets into the tile, split as
+  // lds(spread(k NT + tid)) = lds(spread(k NT)) ^ lds(spread(tid)): the first
+  // part is uniform, the second fixed per thread for the op.
   __device__ static void dense1(cplx<T>* sh, int a, const cplx<T>* __restrict__ m, int tid) {
     constexpr int ITEMS = NA / 2, CNT = (ITEMS + NT - 1) / NT, KB = CNT < 4 ? CNT : 4;
+    constexpr int CB = (int)sizeof(cplx<T>);
     const cplx<T> u0 = m[0], u1 = m[1], u2 = m[2], u3 = m[3];
-    const int abit = 1 << a;
+    const int pos[1] = {a};
+    const int ob = lds<T>(1 << a) * CB;
+    const int lt = lds<T>(spread<1>(tid, pos)) * CB;
+    char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k0 = 0; k0 < CNT; k0 += KB) {
       cplx<T> x[KB], y[KB];
-      int i0[KB];
+      int o[KB];
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
-        const int p = (k0 + kk) * NT + tid;
-        const int pc = (ITEMS % NT == 0 || p < ITEMS) ? p : 0;
-        i0[kk] = (int)insert_zero((uint64_t)pc, a);
-        x[kk] = sh[lds<T>(i0[kk])];
-        y[kk] = sh[lds<T>(i0[kk] | abit)];
+        const int k = k0 + kk;
+        const bool ok = ITEMS % NT == 0 || k * NT + tid < ITEMS;
+        o[kk] = ok ? (lds<T>(spread<1>(k * NT, pos)) * CB) ^ lt : 0;
+        x[kk] = *reinterpret_cast<const cplx<T>*>(base + o[kk]);
+        y[kk] = *reinterpret_cast<const cplx<T>*>(base + (o[kk] ^ ob));
       }
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
         if (ITEMS % NT == 0 || (k0 + kk) * NT + tid < ITEMS) {
-          sh[lds<T>(i0[kk])] = cmad(u1, y[kk], cmul(u0, x[kk]));
-          sh[lds<T>(i0[kk] | abit)] = cmad(u3, y[kk], cmul(u2, x[kk]));
+          *reinterpret_cast<cplx<T>*>(base + o[kk]) = cmad(u1, y[kk], cmul(u0, x[kk]));
+          *reinterpret_cast<cplx<T>*>(base + (o[kk] ^ ob)) = cmad(u3, y[kk], cmul(u2, x[kk]));
         }
       }
     }
@@ -185,89 +228,233 @@ struct Fixed {
 
   __device__ static void dense2(cplx<T>* sh, int a, int c, const cplx<T>* __restrict__ m, int tid) {
     constexpr int ITEMS = NA / 4, CNT = (ITEMS + NT - 1) / NT, KB = CNT < 2 ? CNT : 2;
-    const int lo = a < c ? a : c, hi = a < c ? c : a;
-    const int ba = 1 << a, bc = 1 << c;
+    constexpr int CB = (int)sizeof(cplx<T>);
+    const int pos[2] = {a < c ? a : c, a < c ? c : a};
+    const int oa = lds<T>(1 << a) * CB, oc = lds<T>(1 << c) * CB;
+    const int off[4] = {0, oa, oc, oa ^ oc};
+    const int lt = lds<T>(spread<2>(tid, pos)) * CB;
+    char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k0 = 0; k0 < CNT; k0 += KB) {
       cplx<T> v[KB][4];
-      int ix[KB];
+      int o[KB];
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
-        const int p = (k0 + kk) * NT + tid;
-        const int pc = (ITEMS % NT == 0 || p < ITEMS) ? p : 0;
-        ix[kk] = (int)insert_zero(insert_zero((uint64_t)pc, lo), hi);
-        v[kk][0] = sh[lds<T>(ix[kk])];
-        v[kk][1] = sh[lds<T>(ix[kk] | ba)];
-        v[kk][2] = sh[lds<T>(ix[kk] | bc)];
-        v[kk][3] = sh[lds<T>(ix[kk] | ba | bc)];
+        const int k = k0 + kk;
+        const bool ok = ITEMS % NT == 0 || k * NT + tid < ITEMS;
+        o[kk] = ok ? (lds<T>(spread<2>(k * NT, pos)) * CB) ^ lt : 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[kk][r] = *reinterpret_cast<const cplx<T>*>(base + (o[kk] ^ off[r]));
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const cplx<T> m0 = m[4 * r], m1 = m[4 * r + 1], m2 = m[4 * r + 2], m3 = m[4 * r + 3];
-        const int off = ((r & 1) ? ba : 0) | ((r & 2) ? bc : 0);
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
           cplx<T> acc = cmul(m0, v[kk][0]);
           acc = cmad(m1, v[kk][1], acc);
           acc = cmad(m2, v[kk][2], acc);
           acc = cmad(m3, v[kk][3], acc);
-          if (ITEMS % NT == 0 || (k0 + kk) * NT + tid < ITEMS) sh[lds<T>(ix[kk] | off)] = acc;
+          if (ITEMS % NT == 0 || (k0 + kk) * NT + tid < ITEMS)
+            *reinterpret_cast<cplx<T>*>(base + (o[kk] ^ off[r])) = acc;
         }
       }
     }
   }
 
   __device__ static void diag2(cplx<T>* sh, int a, int c, const cplx<T>* __restrict__ m, int tid) {
-    constexpr int CNT = (NA + NT - 1) / NT;
+    constexpr int CNT = (NA + NT - 1) / NT, CB = (int)sizeof(cplx<T>);
     const cplx<T> d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
+    const int lt = lds<T>(tid) * CB;
+    char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k = 0; k < CNT; ++k) {
       const int e = k * NT + tid;
-      if (NA % NT == 0 || e < NA) sh[lds<T>(e)] = cmul(diag_pick(e, a, c, d0, d1, d2, d3), sh[lds<T>(e)]);
+      if (NA % NT == 0 || e < NA) {
+        cplx<T>* z = reinterpret_cast<cplx<T>*>(base + ((lds<T>(k * NT) * CB) ^ lt));
+        *z = cmul(diag_pick(e, a, c, d0, d1, d2, d3), *z);
+      }
     }
   }
 
-  // 8x8 on three local bits; one group of 8 amplitudes in registers at a time
-  __device__ static void dense3(cplx<T>* sh, const int32_t* bits, const cplx<T>* __restrict__ m,
-                                int tid) {
+  // monomial on K <= 3 local bits: out[r] = c[r] in[sigma(r)]; the reads go
+  // straight to the permuted rows (sigma is uniform), so no selects
+  template <int K>
+  __device__ static void perm(cplx<T>* sh, const int32_t* bits, int sigma,
+                              const cplx<T>* __restrict__ m, int tid) {
+    constexpr int D = 1 << K, ITEMS = NA >> K, CNT = (ITEMS + NT - 1) / NT, KB = CNT < 2 ? CNT : 2;
+    constexpr int CB = (int)sizeof(cplx<T>);
+    int bt[K], sorted[K];
+    sort_bits<K>(bits, bt, sorted);
+    int dst[D], src[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      dst[r] = lds<T>(row_offset<K>(r, bt)) * CB;
+      src[r] = lds<T>(row_offset<K>((sigma >> (3 * r)) & 7, bt)) * CB;
+    }
+    const int lt = lds<T>(spread<K>(tid, sorted)) * CB;
+    char* base = reinterpret_cast<char*>(sh);
+#pragma unroll
+    for (int k0 = 0; k0 < CNT; k0 += KB) {
+      cplx<T> v[KB][D];
+      int o[KB];
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        const int k = k0 + kk;
+        const bool ok = ITEMS % NT == 0 || k * NT + tid < ITEMS;
+        o[kk] = ok ? (lds<T>(spread<K>(k * NT, sorted)) * CB) ^ lt : 0;
+#pragma unroll
+        for (int r = 0; r < D; ++r) v[kk][r] = *reinterpret_cast<const cplx<T>*>(base + (o[kk] ^ src[r]));
+      }
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        if (ITEMS % NT == 0 || (k0 + kk) * NT + tid < ITEMS) {
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+            *reinterpret_cast<cplx<T>*>(base + (o[kk] ^ dst[r])) = cmul(m[r], v[kk][r]);
+        }
+      }
+    }
+  }
+
+  // 8x8 on three local bits on the vector units (FP64: the matrix cores run
+  // FP64 at the vector rate, and the uniform coefficients come through the
+  // scalar cache); one group of 8 amplitudes in registers at a time.
+  __device__ static void dense3_valu(cplx<T>* sh, const int32_t* bits, const cplx<T>* __restrict__ m,
+                                     int tid) {
     constexpr int ITEMS = NA / 8, CNT = (ITEMS + NT - 1) / NT;
     int bt[3], sorted[3];
     sort_bits<3>(bits, bt, sorted);
+    // byte offsets of the 8 rows (uniform), XORed onto each group's base
     int off[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) off[r] = row_offset<3>(r, bt);
+    for (int r = 0; r < 8; ++r) off[r] = lds<T>(row_offset<3>(r, bt)) * (int)sizeof(cplx<T>);
+    char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k = 0; k < CNT; ++k) {
       const int p = k * NT + tid;
       const bool ok = ITEMS % NT == 0 || p < ITEMS;
-      const int ix = group_base<3>(ok ? p : 0, sorted);
+      const int gb = lds<T>(spread<3>(ok ? p : 0, sorted)) * (int)sizeof(cplx<T>);
       cplx<T> v[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = sh[lds<T>(ix | off[r])];
+      for (int r = 0; r < 8; ++r) v[r] = *reinterpret_cast<const cplx<T>*>(base + (gb ^ off[r]));
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         cplx<T> acc = cmul(m[8 * r], v[0]);
 #pragma unroll
         for (int s = 1; s < 8; ++s) acc = cmad(m[8 * r + s], v[s], acc);
-        if (ok) sh[lds<T>(ix | off[r])] = acc;
+        if (ok) *reinterpret_cast<cplx<T>*>(base + (gb ^ off[r])) = acc;
       }
     }
   }
 
+  // 8x8 on three local bits, on the matrix cores (FP32).  The complex product
+  // is the real 16x16 product y = R x over rows and columns 2r + p (p = 0:
+  // real, p = 1: imaginary part of amplitude r of a group), with
+  //   R[2r][2s] = R[2r+1][2s+1] = Re m_rs,  R[2r][2s+1] = -Im m_rs,
+  //   R[2r+1][2s] = Im m_rs.
+  // A wave takes 16 groups at a time as the 16 columns of x; lane 16 q + c
+  // feeds column c.  Four 16x16x4 steps j cover the rows 4j..4j+3 of x: the
+  // lane supplies R[c][4j + q] (A) and x[4j + q][c] (B), i.e. part q & 1 of
+  // amplitude 2j + (q >> 1), and receives rows 4q..4q+3 (amplitudes 2q and
+  // 2q+1 whole).  Groups are disjoint across waves and a wave reads all of
+  // a block before it writes it, so no barrier is needed inside the op.
+  __device__ static void dense3_mma(cplx<T>* sh, const int32_t* bits, const cplx<T>* m, int tid) {
+    static_assert(sizeof(T) == 4, "FP32 matrix-core op");
+    constexpr int ITEMS = NA / 8, NBLK = ITEMS / 16, W = NT / 64, CB = (int)sizeof(cplx<T>);
+    static_assert(ITEMS % 16 == 0 && NBLK % W == 0, "whole 16-group blocks per wave");
+    int bt[3], sorted[3];
+    sort_bits<3>(bits, bt, sorted);
+    const int lane = tid & 63, c = lane & 15, q = lane >> 4, h = q >> 1, pp = q & 1;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = c >> 1, p = c & 1;
+    T a[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const cplx<T> z = m[8 * r + 2 * j + h];
+      a[j] = p == pp ? z.re : (p ? z.im : -z.im);
+    }
+    // per-lane byte offsets: reads (part pp of amplitude 2j + h of group c)
+    // and writes (amplitudes 2q, 2q + 1 of group c)
+    const int lc = spread<3>(c, sorted);
+    int rd[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rd[j] = lds<T>(lc | row_offset<3>(2 * j + h, bt)) * CB + pp * (int)sizeof(T);
+    const int w0 = lds<T>(lc | row_offset<3>(2 * q, bt)) * CB;
+    const int w1 = lds<T>(lc | row_offset<3>(2 * q + 1, bt)) * CB;
+    char* base = reinterpret_cast<char*>(sh);
+    // two blocks per step: all reads, then two independent MFMA chains, then
+    // all writes (measured faster than four per step)
+    constexpr int NB = NBLK / W >= 2 ? 2 : 1;
+#pragma unroll
+    for (int i0 = 0; i0 < NBLK / W; i0 += NB) {
+      int ub[NB];  // block parts (wave-uniform)
+      T x[NB][4];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        ub[u] = lds<T>(spread<3>(((i0 + u) * W + wave) * 16, sorted)) * CB;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[u][j] = *reinterpret_cast<const T*>(base + (ub[u] ^ rd[j]));
+      }
+      typedef float v4f __attribute__((ext_vector_type(4)));
+      v4f acc[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) acc[u] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[u][j], acc[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        *reinterpret_cast<cplx<T>*>(base + (ub[u] ^ w0)) = cplx<T>{acc[u][0], acc[u][1]};
+        *reinterpret_cast<cplx<T>*>(base + (ub[u] ^ w1)) = cplx<T>{acc[u][2], acc[u][3]};
+      }
+    }
+  }
+
+  // The matrix cores pay off for FP32 (twice the vector rate), not for FP64.
+  static constexpr bool kMma = sizeof(T) == 4;
+
+  // mats: every coefficient in global memory (op.moff); lmats (FP32 only):
+  // the pass's coefficients staged in LDS from ops[0].moff on.  The vector
+  // ops take their uniform coefficients through the scalar cache, the
+  // matrix-core op its per-lane operands from LDS.
   __device__ static void run(cplx<T>* sh, const TileOp* __restrict__ ops, int nops,
-                             const cplx<T>* __restrict__ mats) {
+                             const cplx<T>* __restrict__ mats, const cplx<T>* lmats) {
+    const int64_t mbase = nops > 0 ? ops[0].moff : 0;
     for (int o = 0; o < nops; ++o) {
       const TileOp op = ops[o];
-      const cplx<T>* m = mats + op.moff;
       const int tid = (int)threadIdx.x;
-      if (op.kind == TOP_DENSE2) dense2(sh, op.a, op.b, m, tid);
-      else if (op.kind == TOP_DENSE1) dense1(sh, op.a, m, tid);
-      else if (op.kind == TOP_DIAG2) diag2(sh, op.a, op.b, m, tid);
-      else dense3(sh, op.bits, m, tid);  // callers route passes with 4-qubit ops elsewhere
+      if (op.kind == TOP_DENSE2) dense2(sh, op.a, op.b, mats + op.moff, tid);
+      else if (op.kind == TOP_DENSE1) dense1(sh, op.a, mats + op.moff, tid);
+      else if (op.kind == TOP_DIAG2) diag2(sh, op.a, op.b, mats + op.moff, tid);
+      else if (op.kind == TOP_PERM) {
+        if (op.k == 1) perm<1>(sh, op.bits, op.a, mats + op.moff, tid);
+        else if (op.k == 2) perm<2>(sh, op.bits, op.a, mats + op.moff, tid);
+        else perm<3>(sh, op.bits, op.a, mats + op.moff, tid);
+      }
+      else if constexpr (kMma) dense3_mma(sh, op.bits, lmats + (op.moff - mbase), tid);
+      else dense3_valu(sh, op.bits, mats + op.moff, tid);  // callers route 4-qubit ops elsewhere
       __syncthreads();
     }
   }
 };
+
+// Copies the n coefficients of a pass into LDS (the caller synchronises).
+template <typename T, int NT>
+__device__ inline void stage_mats(cplx<T>* dst, const cplx<T>* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+}
+
+// LDS coefficient slots of a fixed-size kernel: what remains of the LDS
+// budget of one workgroup (wgs workgroups per CU) after the tile and the
+// geometry tables, at most 8192, in whole 8x8 matrices.
+constexpr int mat_slots(int tile_bytes, int other_bytes, int coef_bytes, int wgs) {
+  const int left = 163840 / wgs - tile_bytes - other_bytes;
+  const int n = left / coef_bytes;
+  return (n > 8192 ? 8192 : n) & ~63;
+}
 
 }  // namespace tileops
 }  // namespace juqcs

@@ -40,7 +40,7 @@ PLANS = {"plain": PLAN_PLAIN, "tile": PLAN_TILE, "fused": PLAN_FUSED, "auto": PL
 class PlanOpts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("fuse_k", ct.c_int32), ("mma", ct.c_int32),
                 ("tile_bits", ct.c_int32), ("low_bits", ct.c_int32), ("profile", ct.c_int32),
-                ("autotune", ct.c_int32), ("reserved", ct.c_int32), ("passes", ct.c_int64),
+                ("autotune", ct.c_int32), ("pass_gates", ct.c_int32), ("passes", ct.c_int64),
                 ("gates", ct.c_int64),
                 ("kernel_ms", ct.c_double), ("bytes", ct.c_double)]
 
@@ -241,10 +241,11 @@ class State:
                "juqcs_apply_fused_k")
 
     def run(self, gates, mode: str = "auto", fuse_k: int = 0, mma: str = "auto",
-            tile_bits: int = 0, low_bits: int = 0, profile: bool = False) -> PlanOpts:
+            tile_bits: int = 0, low_bits: int = 0, profile: bool = False,
+            pass_gates: int = 0) -> PlanOpts:
         g = _gates(gates)
         o = PlanOpts(mode=PLANS[mode], fuse_k=fuse_k, mma=MMAS[mma], tile_bits=tile_bits,
-                     low_bits=low_bits, profile=int(profile))
+                     low_bits=low_bits, profile=int(profile), pass_gates=pass_gates)
         _check(_lib.juqcs_run_circuit(self.h, g.ctypes.data, g.size, ct.byref(o)),
                "juqcs_run_circuit")
         return o

@@ -84,9 +84,32 @@ def test_ghz30_closed_form(J):
         s.run(W.ghz(n), mode="plain")
         a = s.amplitudes([0, (1 << n) - 1, 1, 1 << 29, 12345])
         nrm = s.norm()
+        q = s.expectations()
     r = 1.0 / math.sqrt(2.0)
     assert abs(a[0] - r) < 1e-15 and abs(a[1] - r) < 1e-15
     assert np.all(a[2:] == 0) and abs(nrm - 1.0) < 1e-15
+    # GHZ: <sigma^alpha_i> = 0 for every qubit and alpha, so every <Q> = 1/2
+    assert np.max(np.abs(q - 0.5)) < 1e-15
+
+
+@pytest.mark.parametrize("n, dtype", [(33, "c128"), (36, "enc2")])
+def test_ghz_tile_closed_form(J, n, dtype):
+    # the paper's benchmark circuit at its largest one-GPU sizes: exact in
+    # both forms (two-byte codes: 1/sqrt(2) and 0 are representable per block)
+    announce("ghz tile", n, dtype)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        o = s.run(W.ghz(n), mode="tile")
+        a = s.amplitudes([0, (1 << n) - 1, 1, 1 << (n - 1), 987654321])
+        q = s.expectations()
+    r = 1.0 / math.sqrt(2.0)
+    tol = 1e-15 if dtype == "c128" else 1e-7
+    # a tile pass advances the CNOT chain by its gathered bits (8 for C128,
+    # 5 for the two-byte form, whose chunks hold whole 2^8-amplitude blocks)
+    assert o.passes <= (4 if dtype == "c128" else 8)
+    assert abs(a[0] - r) < tol and abs(a[1] - r) < tol
+    assert np.all(a[2:] == 0)
+    assert np.max(np.abs(q - 0.5)) < tol
 
 
 @pytest.mark.parametrize("dtype, mode, mma", [

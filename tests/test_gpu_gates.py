@@ -143,6 +143,61 @@ def test_tile_brick_circuit_fewer_passes(J, dtype):
     assert_dtype(dtype, got, sv.run_circuit(n, circ))
 
 
+def monomial_circuit(n, count, seed):
+    # only permutations with phases (X, Y, Z, S, T, CNOT, CZ, CP) after a
+    # layer of H: the in-pass fusion turns them into monomial ops
+    rng = np.random.default_rng(seed)
+    recs = [W.gate(W.OP_H, q) for q in range(n)]
+    for _ in range(count):
+        op = int(rng.choice([W.OP_X, W.OP_Y, W.OP_Z, W.OP_S, W.OP_T, W.OP_CNOT, W.OP_CZ, W.OP_CP]))
+        a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+        recs.append(W.gate(op, a, b if op >= W.OP_CNOT else -1, theta=float(rng.uniform(0, 6.3))))
+    return W.concat(*recs)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64", "enc2"])
+@pytest.mark.parametrize("n", [9, 16])
+def test_tile_monomial_ops(J, dtype, n):
+    announce("tile-monomial", dtype, n)
+    circ = monomial_circuit(n, 150, seed=40 + n)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        o = s.run(circ, mode="tile")
+        got = s.state_vector()
+    phi = sv.run_circuit(n, circ)
+    if dtype == "enc2":
+        assert rel_l2(got, phi) < 0.02 * math.sqrt(o.passes + 1)
+    else:
+        assert_dtype(dtype, got, phi)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64", "enc2"])
+@pytest.mark.parametrize("pass_gates", [-1, 0, 7, 40])
+def test_tile_pass_gate_cap(J, dtype, pass_gates):
+    # a cap only moves gates to later passes (and splits clusters): same state
+    n = 16
+    circ = W.layered_brick(n, 8, seed=4)
+    announce("tile-cap", dtype, pass_gates)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        o = s.run(circ, mode="tile", pass_gates=pass_gates)
+        got = s.state_vector()
+    phi = sv.run_circuit(n, circ)
+    if pass_gates == 7:
+        assert o.passes >= len(circ) / 7
+    if dtype == "enc2":
+        assert rel_l2(got, phi) < 0.02 * math.sqrt(o.passes + 1)
+    else:
+        assert_dtype(dtype, got, phi)
+
+
+def test_tile_pass_gate_cap_rejects_bad_value(J):
+    with J.State(8, "c128") as s:
+        with pytest.raises(J.JuqcsError) as e:
+            s.run(W.layered_brick(8, 2, seed=1), mode="tile", pass_gates=-2)
+    assert e.value.status == J.ERR_ARG
+
+
 # ---- fused k-qubit blocks on the matrix cores --------------------------------------
 @pytest.mark.parametrize("dtype, mode", [("c128", "fp64"), ("c64", "fp32"), ("c64", "bf16x3"),
                                          ("c64", "bf16")])
@@ -232,6 +287,29 @@ def test_norm_expectations_scale(J, dtype):
     tol = 1e-12 if dtype == "c128" else 1e-5
     assert abs(n1 - 1.0) < tol and abs(n2 - 0.25) < tol
     assert np.max(np.abs(ex - want)) < tol
+
+
+@pytest.mark.parametrize("n, dtype, permute", [
+    (22, "c128", False), (22, "c64", False), (22, "enc2", False), (22, "c128", True),
+    (22, "c64", True), (3, "c128", False), (7, "c64", False), (9, "enc2", False),
+    (19, "c128", False), (21, "enc2", False)])
+def test_expectations_multi_pass(J, n, dtype, permute):
+    # n = 22 needs three tile geometries (13 low bits, then gathered bits),
+    # small n a single partial tile; the reference is the oracle's formula
+    # on the state the GPU holds
+    announce("expectations", n, dtype, permute)
+    circ = W.random_mixed(n, 120, seed=11)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        s.run(circ, mode="tile")
+        if permute:
+            s.permute(list(reversed(range(n))))
+        ex = s.expectations()
+        psi = s.state_vector()
+    assert np.max(np.abs(ex - observables.q_expectations(psi, n))) < 1e-11
+    if dtype != "enc2":
+        want = observables.q_expectations(sv.run_circuit(n, circ), n)
+        assert np.max(np.abs(ex - want)) < (1e-12 if dtype == "c128" else 1e-5)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64", "enc2"])
