@@ -292,7 +292,7 @@ def _timed(fn, steps, warmup, stream):
 
 def other_workload(args, juqcs, W, dev, stream):
     """Secondary configurations (not the headline line): many small circuits
-    in one persistent launch, the entangling-gate decomposition, and the
+    in one graph launch, the entangling-gate decomposition, and the
     largest single states in complex64 and two-byte form."""
     import numpy as np
     import torch
@@ -327,7 +327,7 @@ def other_workload(args, juqcs, W, dev, stream):
             "value": gates / (ms / 1e3), "ms_per_step": ms, "dtype": "f32",
             "config": {"workload": f"batch{len(inst)}: independent layered circuits, n ~ U{{12..24}}, "
                                    "depth ~ U{10..40} (Haar U(2) + random CZ pairs), complex64, "
-                                   "one persistent graph-captured launch",
+                                   "one graph launch (a persistent kernel per pass round)",
                        "circuits": len(inst), "gates": gates, "tile_tasks": st["tasks"],
                        "tile_passes": st["passes"],
                        "fusion_width_counts": {int(k): int((kin == k).sum()) for k in set(kin.tolist())},

@@ -256,7 +256,7 @@ juqcs_status juqcs_decode2(const void* d_codes, const void* d_scales,
                            juqcs_dtype dst, void* hip_stream);
 
 /* ------------------------------------------------------------------------
- * Batches of independent circuits (many small states, one persistent launch)
+ * Batches of independent circuits (many small states, one graph launch)
  * ---------------------------------------------------------------------- */
 
 typedef struct juqcs_batch juqcs_batch; /* opaque */
@@ -275,13 +275,15 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
                                 void* d_states, const uint64_t* state_offset,
                                 const juqcs_plan_opts* opts);
 
-/* Runs the whole batch in one persistent kernel launch on hip_stream
- * (asynchronous).  On a non-default stream the launch is captured once into
- * a HIP graph and replayed on later calls. */
+/* Runs the whole batch on hip_stream (asynchronous): one persistent kernel
+ * per pass round (round r applies pass r of every circuit that has one; the
+ * kernel boundary orders a circuit's passes, so workgroups never wait for
+ * each other).  On a non-default stream the launches are captured once into
+ * a HIP graph and replayed as one graph launch on later calls. */
 juqcs_status juqcs_batch_run(juqcs_batch* b, void* hip_stream);
 
-/* Synchronises the stream of the last run and reports a dependency wait
- * that hit its spin limit (JUQCS_ERR_HIP). */
+/* Synchronises the stream of the last run (JUQCS_ERR_HIP on a device
+ * error). */
 juqcs_status juqcs_batch_wait(juqcs_batch* b);
 
 /* Work-list statistics: tile tasks, gate records and tile passes. */
@@ -312,7 +314,7 @@ juqcs_status juqcs_batch_destroy(juqcs_batch* b);
  * bit k of b is 0, else -1, for the k-th crossing CZ in circuit order, and
  * applies diag(e^{i(x s_k - pi/4)}, e^{-i(x s_k - pi/4)}) to both of its
  * qubits at that position.  Every branch's two half-states are simulated in
- * C64 with batched persistent launches (group_size half-states resident at
+ * C64 as batches (group_size half-states resident at
  * a time, 0 = automatic), and the result
  * 2^-m sum_b A_b(z_A) B_b(z_B) is summed in FP64 on the device (Eq. (3)).
  * Only CZ may cross the cut (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.

@@ -237,16 +237,17 @@ juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, 
   if (kin > 4) return fail(JUQCS_ERR_ARG, "in-pass fusion width must be 1..4");
   if (pass_gates < -1) return fail(JUQCS_ERR_ARG, "pass_gates must be >= -1");
   const int cap = tile_mat_cap(st->dt, std::min(b, st->n));
+  const int mcap = tile_mma_cap(st->dt, std::min(b, st->n));
   const int l = std::min(L, st->n);
   TilePlan plan;
   if (pass_gates != 0 || st->dt == JUQCS_C128) {
-    plan_tiles(st->n, l, b, st->B, gates, &plan, kin, cap, std::max(pass_gates, 0));
+    plan_tiles(st->n, l, b, st->B, gates, &plan, kin, cap, std::max(pass_gates, 0), mcap);
   } else {
     double best = 0.0;
     for (int take : {0, 90, 60, 40}) {
       if (take > 0 && (int64_t)gates.size() <= take) continue;  // same as no cap
       TilePlan cand;
-      plan_tiles(st->n, l, b, st->B, gates, &cand, kin, cap, take);
+      plan_tiles(st->n, l, b, st->B, gates, &cand, kin, cap, take, mcap);
       const double ms = tile_plan_ms(cand, st->dt, st->n);
       if (plan.passes.empty() || ms < best) {
         best = ms;

@@ -22,7 +22,6 @@ namespace {
 
 using C = cplx<double>;
 constexpr int kChunkTiles = 8;
-constexpr uint32_t kSpinLimit = 1u << 25;  // bounded dependency wait
 
 juqcs_status fail(juqcs_status st, const std::string& msg) {
   set_error(msg);
@@ -75,7 +74,7 @@ void schedule_circuit(int n, const std::vector<Gate>& g, TileSchedule* sched) {
 void plan_circuit(int n, const std::vector<Gate>& g, int kin, TilePlan* plan) {
   TileSchedule sched;
   schedule_circuit(n, g, &sched);
-  emit_schedule(sched, g, kin, plan, batch_mat_cap());
+  emit_schedule(sched, g, kin, plan, 0, batch_mma_cap());
 }
 
 // Runs f(i) for i in [0, count) on the host's cores.
@@ -161,7 +160,6 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
       g.circuit = c;
       g.pass = first_pass[c] + i;
       g.chunk_tiles = chunk;
-      g.wait_target = (int32_t)(i * ntiles);
       g.init = i == 0 ? 1 : 0;
       groups.push_back(g);
     }
@@ -173,22 +171,35 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
   std::stable_sort(groups.begin(), groups.end(), [&](const BatchGroup& a, const BatchGroup& b) {
     return (a.pass - first_pass[a.circuit]) < (b.pass - first_pass[b.circuit]);
   });
+  // rounds: groups of the same pass index, contiguous after the sort
+  BatchDevice& d = B->dev;
+  d.round_group.clear();
+  d.round_chunk.clear();
   long long next = 0;
-  for (BatchGroup& g : groups) {
+  int round = -1;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    BatchGroup& g = groups[gi];
+    const int r = g.pass - first_pass[g.circuit];
+    while (round < r) {
+      d.round_group.push_back((int32_t)gi);
+      d.round_chunk.push_back(next);
+      ++round;
+    }
     g.first_chunk = next;
     const int b = passes[g.pass].g.b;
     const int64_t ntiles = int64_t(1) << (B->n[g.circuit] - b);
     next += ntiles / g.chunk_tiles;
   }
+  d.nrounds = round + 1;
+  d.round_group.push_back((int32_t)groups.size());
+  d.round_chunk.push_back(next);
   // one device buffer for everything
   const size_t o_groups = 0;
   const size_t o_passes = align256(o_groups + groups.size() * sizeof(BatchGroup));
   const size_t o_ops = align256(o_passes + passes.size() * sizeof(BatchPass));
   const size_t o_mats = align256(o_ops + std::max<size_t>(ops.size(), 1) * sizeof(TileOp));
-  const size_t o_done = align256(o_mats + std::max<size_t>(mats.size(), 1) * sizeof(cplx<float>));
-  const size_t o_ticket = align256(o_done + B->count * sizeof(uint32_t));
-  const size_t o_err = align256(o_ticket + sizeof(uint64_t));
-  const size_t o_soff = align256(o_err + sizeof(uint32_t));
+  const size_t o_tickets = align256(o_mats + std::max<size_t>(mats.size(), 1) * sizeof(cplx<float>));
+  const size_t o_soff = align256(o_tickets + std::max(d.nrounds, 1) * sizeof(uint64_t));
   const size_t o_nq = align256(o_soff + B->count * sizeof(uint64_t));
   const size_t total = align256(o_nq + B->count * sizeof(int32_t));
   std::vector<char> host(total, 0);
@@ -202,18 +213,14 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
   if (e != hipSuccess) return hip_fail(e, "batch hipMalloc");
   e = hipMemcpy(B->dbuf, host.data(), total, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "batch upload");
-  BatchDevice& d = B->dev;
   d.groups = (const BatchGroup*)(B->dbuf + o_groups);
   d.ngroups = (int)groups.size();
   d.passes = (const BatchPass*)(B->dbuf + o_passes);
   d.ops = (const TileOp*)(B->dbuf + o_ops);
   d.mats = (const cplx<float>*)(B->dbuf + o_mats);
-  d.done = (uint32_t*)(B->dbuf + o_done);
-  d.ticket = (uint64_t*)(B->dbuf + o_ticket);
-  d.err = (uint32_t*)(B->dbuf + o_err);
+  d.tickets = (uint64_t*)(B->dbuf + o_tickets);
   d.count = B->count;
   d.nchunks = next;
-  d.spin_limit = kSpinLimit;
   B->d_state_off = (uint64_t*)(B->dbuf + o_soff);
   B->d_nq = (int32_t*)(B->dbuf + o_nq);
   return JUQCS_OK;
@@ -300,14 +307,14 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
       TileSchedule sched;
       schedule_circuit(n[c], dec[c], &sched);
       if (fuse > 0) {
-        emit_schedule(sched, dec[c], fuse, &plans[c], batch_mat_cap());
+        emit_schedule(sched, dec[c], fuse, &plans[c], 0, batch_mma_cap());
         B->kin[c] = fuse;
         return;
       }
       double best = 1e300;
       for (int k = 2; k <= 4; ++k) {
         TilePlan p;
-        emit_schedule(sched, dec[c], k, &p, batch_mat_cap());
+        emit_schedule(sched, dec[c], k, &p, 0, batch_mma_cap());
         const double cst = plan_cost(p);
         if (cst < best) {
           best = cst;
@@ -381,10 +388,6 @@ juqcs_status juqcs_batch_wait(juqcs_batch* B) {
   if (!B) return fail(JUQCS_ERR_ARG, "null batch");
   hipError_t e = hipStreamSynchronize(B->last_stream);
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-  uint32_t flag = 0;
-  e = hipMemcpy(&flag, B->dev.err, sizeof(flag), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "error flag read");
-  if (flag) return fail(JUQCS_ERR_HIP, "a batch dependency wait exceeded its spin limit");
   return JUQCS_OK;
 }
 
@@ -610,10 +613,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     }
     if (rc == JUQCS_OK) {
       e = hipStreamSynchronize(s);
-      uint32_t flag = 0;
-      if (e == hipSuccess) e = hipMemcpy(&flag, B.dev.err, sizeof(flag), hipMemcpyDeviceToHost);
       if (e != hipSuccess) rc = hip_fail(e, "branch batch");
-      else if (flag) rc = fail(JUQCS_ERR_HIP, "a batch dependency wait exceeded its spin limit");
     }
     free_batch(&B);
   }

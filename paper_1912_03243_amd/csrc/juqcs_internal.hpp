@@ -91,6 +91,7 @@ struct TileGeom {
   int32_t block_bits;            // ENC2 only
   int32_t maxk;                  // widest op of the pass (1..4)
   int32_t mat_count;             // coefficients of the pass's ops, from ops[0].moff on
+  int32_t mma_count;             // 8x8 (TOP_DENSE3) ops of the pass
 };
 
 enum TileOpKind : int32_t {
@@ -152,9 +153,11 @@ size_t expect_partials_bytes();
 hipError_t launch_expect(juqcs_dtype dt, const void* amps, const void* scales, const TileGeom& g,
                          int jlo, double* partials, double* out3, hipStream_t s);
 
-// Coefficients a pass of 2^b-amplitude tiles may carry so that it runs on
-// the pipelined kernel (which stages them in LDS); 0 = no limit.
+// What a pass of 2^b-amplitude tiles may carry so that it runs on the
+// pipelined kernel: coefficients (staged in LDS by the two-byte kernels) and
+// 8x8 ops (whose tables the FP32 kernels build in LDS); 0 = no limit.
 int tile_mat_cap(juqcs_dtype dt, int b);
+int tile_mma_cap(juqcs_dtype dt, int b);
 
 hipError_t launch_fused(juqcs_dtype dt, void* amps, int n, int k,
                         const int* targets, const void* d_mat, juqcs_mma mode,
@@ -180,9 +183,7 @@ struct BatchGroup {  // every tile of one pass of one circuit
   int32_t circuit;
   int32_t pass;          // index into the BatchPass array
   int32_t chunk_tiles;   // tiles claimed per ticket
-  int32_t wait_target;   // finished tiles of the circuit required first
   int32_t init;          // 1: start from |0...0> instead of loading
-  int32_t pad;
 };
 
 struct BatchDevice {
@@ -191,16 +192,16 @@ struct BatchDevice {
   const BatchPass* passes;
   const TileOp* ops;
   const cplx<float>* mats;
-  uint32_t* done;
-  uint64_t* ticket;
-  uint32_t* err;
+  uint64_t* tickets;               // one counter per round (device)
+  int nrounds;                     // round r: pass r of every circuit that has one
+  std::vector<int32_t> round_group;    // host: first group of each round (+ end)
+  std::vector<int64_t> round_chunk;    // host: first chunk of each round (+ end)
   int count;
   long long nchunks;
-  uint32_t spin_limit;
 };
 
 int batch_max_bits();
-int batch_mat_cap();  // coefficients per pass staged in LDS by the batch kernel
+int batch_mma_cap();  // 8x8 ops per pass whose tables the batch kernel holds in LDS
 hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s);
 hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, const int32_t* nq,
                                int count, int m, const uint64_t* idx, double* out, hipStream_t s);
@@ -246,15 +247,16 @@ struct TileSchedule {
 void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
                   TileSchedule* sched, int max_take = 0);
 // Fuses every pass's gates into ops of at most kin qubits.  A pass whose
-// coefficients would exceed max_mats (> 0) is split into consecutive passes
-// of the same geometry.
+// coefficients would exceed max_mats (> 0), or whose 8x8 ops would exceed
+// max_mma (> 0), is split into consecutive passes of the same geometry.
 void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, int kin,
-                   TilePlan* plan, int max_mats = 0);
+                   TilePlan* plan, int max_mats = 0, int max_mma = 0);
 
 // Plans tile passes for gates (physical qubits).  L, b: low contiguous bits
 // and total tile bits; the low L bits are always tile bits.
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan, int kin = 2, int max_mats = 0, int max_take = 0);
+                TilePlan* plan, int kin = 2, int max_mats = 0, int max_take = 0,
+                int max_mma = 0);
 
 struct FusedBlock {
   std::vector<int> targets;           // physical

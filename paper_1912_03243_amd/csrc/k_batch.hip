@@ -1,16 +1,16 @@
-// One persistent launch for many independent circuits (and for the branch
-// simulations of the entangling-gate decomposition, Section 4, whose terms
-// are independent: the paper spreads them over MPI ranks and OpenMP threads,
-// here they are work items of one kernel).
+// Many independent circuits in one graph launch (and the branch simulations
+// of the entangling-gate decomposition, Section 4, whose terms are
+// independent: the paper spreads them over MPI ranks and OpenMP threads,
+// here they are work items of the same kernels).
 //
-// Work list: a "group" is one tile pass of one circuit (2^(n-b) tiles); its
-// tiles are claimed in chunks through a global ticket counter.  Groups are
-// ordered pass-major (every circuit's pass 0, then every pass 1, ...), so a
-// chunk of pass p only waits for pass p-1 of its own circuit, which was
-// claimed earlier by a running workgroup: the wait always ends.  A per-
-// circuit counter of finished tiles carries the dependency (agent-scope
-// release after the stores, acquire before the loads); the wait is bounded
-// and raises an error flag instead of spinning forever.
+// Work list: a "group" is one tile pass of one circuit (2^(n-b) tiles),
+// cut into chunks of tiles.  Groups are ordered pass-major: round r holds
+// pass r of every circuit that has one.  One persistent kernel per round
+// claims the round's chunks through a ticket counter; the tiles of one pass
+// are independent, and the kernel boundary between rounds orders pass r+1
+// of a circuit after its pass r.  No workgroup ever waits for another, and
+// no device-scope fence is needed inside a round (on this GPU such fences
+// write back or invalidate a whole L2 slice).
 #include "tile_ops.hpp"
 
 namespace juqcs {
@@ -19,13 +19,13 @@ namespace {
 
 using tileops::Fixed;
 using tileops::lds;
-using tileops::stage_mats;
 using tileops::Var;
 
 constexpr int kThreads = 256;       // helper kernels
 constexpr int kBatchThreads = 1024;  // the persistent batch kernel
 constexpr int kBatchMaxBits = 13;   // 64 KiB of C64 amplitudes per tile
-constexpr int kBatchMats = 8192;    // 64 KiB of C64 coefficients per pass
+constexpr int kBatchTabs = 44;      // 8x8-op tables per pass (about 83 KiB of LDS)
+using BatchTab = tileops::MmaTab<(1 << kBatchMaxBits) / 128>;  // the largest table
 
 __device__ inline uint64_t tile_base_hb(uint64_t tau, int L, int H, const int* hb) {
   uint64_t base = tau << L;
@@ -33,15 +33,12 @@ __device__ inline uint64_t tile_base_hb(uint64_t tau, int L, int H, const int* h
   return base;
 }
 
-__global__ __launch_bounds__(kThreads) void k_batch_reset(uint32_t* __restrict__ done, int count,
-                                                          unsigned long long* __restrict__ ticket,
-                                                          uint32_t* __restrict__ err) {
+// Clears the rounds' ticket counters (a fill kernel, so that graph replays
+// restart from zero).
+__global__ __launch_bounds__(kThreads) void k_batch_reset(unsigned long long* __restrict__ tickets,
+                                                          int nrounds) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i < count) done[i] = 0u;
-  if (i == 0) {
-    *ticket = 0ull;
-    *err = 0u;
-  }
+  if (i < nrounds) tickets[i] = 0ull;
 }
 
 // One chunk of tiles of a pass with a compile-time tile size: the next tile
@@ -50,7 +47,7 @@ template <int TB>
 __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64_t tau0, int ntile,
                                        bool init, int L, int H, const int* hb,
                                        const uint64_t* choff, const TileOp* ops, int nops,
-                                       const cplx<float>* mats, const cplx<float>* lmats) {
+                                       const cplx<float>* mats, const void* tabs) {
   constexpr int NA = 1 << TB, PER = NA / kBatchThreads;
   const int lmask = (1 << L) - 1;
   typedef float v2 __attribute__((ext_vector_type(2)));
@@ -87,7 +84,8 @@ __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64
         v[k] = gp[nb + choff[e >> L] + (e & lmask)];
       }
     }
-    Fixed<float, TB, kBatchThreads>::run(sh, ops, nops, mats, lmats);
+    using F = Fixed<float, TB, kBatchThreads>;
+    F::run_tab(sh, ops, nops, mats, reinterpret_cast<const typename F::Tab*>(tabs));
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = k * kBatchThreads + threadIdx.x;
@@ -119,25 +117,25 @@ __device__ inline void run_chunk_var(cplx<float>* sh, cplx<float>* psi, uint64_t
   }
 }
 
+// One round: chunks [c0, c1) of groups [g0, g1).
 __global__ __launch_bounds__(kBatchThreads) void k_batch(
-    char* __restrict__ states, const BatchGroup* __restrict__ groups, int ngroups,
+    char* __restrict__ states, const BatchGroup* __restrict__ groups, int g0, int g1,
     const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
-    const cplx<float>* __restrict__ mats, uint32_t* __restrict__ done,
-    unsigned long long* __restrict__ ticket, long long nchunks, uint32_t* __restrict__ err,
-    uint32_t spin_limit) {
+    const cplx<float>* __restrict__ mats, unsigned long long* __restrict__ ticket, long long c0,
+    long long c1) {
   __shared__ cplx<float> sh[1 << kBatchMaxBits];
   __shared__ uint64_t choff[1 << kMaxGather];
-  __shared__ cplx<float> smat[kBatchMats];  // the current pass's coefficients
+  __shared__ BatchTab tabs[kBatchTabs];  // the current pass's 8x8-op tables
   __shared__ int hb[kHbitsCap];
   __shared__ long long s_t;
   __shared__ int s_g;
   int cur_pass = -1;
   for (;;) {
     if (threadIdx.x == 0) {
-      const long long t = (long long)atomicAdd(ticket, 1ull);
+      const long long t = c0 + (long long)atomicAdd(ticket, 1ull);
       int g = -1;
-      if (t < nchunks) {  // last group whose first chunk is <= t
-        int lo = 0, hi = ngroups - 1;
+      if (t < c1) {  // last group of the round whose first chunk is <= t
+        int lo = g0, hi = g1 - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (groups[mid].first_chunk <= t) lo = mid;
@@ -151,24 +149,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     __syncthreads();
     const long long t = s_t;
     const int gi = s_g;
-    if (gi < 0) break;  // every workgroup leaves once the tickets run out
+    if (gi < 0) break;  // every workgroup leaves once the round's tickets run out
     const BatchGroup grp = groups[gi];
-    // wait for the circuit's previous pass (bounded)
-    if (grp.wait_target > 0) {
-      if (threadIdx.x == 0) {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(&done[grp.circuit], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-               (uint32_t)grp.wait_target) {
-          if (++spins > spin_limit) {
-            atomicOr(err, 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(4);
-        }
-      }
-      __syncthreads();
-      __threadfence();
-    }
     const BatchPass ps = passes[grp.pass];
     const int b = ps.g.b, L = ps.g.L, H = ps.g.H;
     if (grp.pass != cur_pass) {
@@ -182,9 +164,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
         for (int j = 0; j < H; ++j) o |= (uint64_t)((c >> j) & 1) << hb[j];
         choff[c] = o;
       }
-      if (ps.g.mat_count <= kBatchMats)
-        stage_mats<float, kBatchThreads>(smat, mats + (ps.op_count > 0 ? ops[ps.op_begin].moff : 0),
-                                         ps.g.mat_count);
+      if (ps.g.maxk <= 3 && ps.g.mma_count <= kBatchTabs) {
+        const TileOp* pops = ops + ps.op_begin;
+        if (b == 13) Fixed<float, 13, kBatchThreads>::build_tabs(
+            reinterpret_cast<Fixed<float, 13, kBatchThreads>::Tab*>(tabs), pops, ps.op_count, mats);
+        else if (b == 12) Fixed<float, 12, kBatchThreads>::build_tabs(
+            reinterpret_cast<Fixed<float, 12, kBatchThreads>::Tab*>(tabs), pops, ps.op_count, mats);
+        else if (b == 11) Fixed<float, 11, kBatchThreads>::build_tabs(
+            reinterpret_cast<Fixed<float, 11, kBatchThreads>::Tab*>(tabs), pops, ps.op_count, mats);
+      }
       __syncthreads();
       cur_pass = grp.pass;
     }
@@ -192,19 +180,14 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     const uint64_t tau0 = (uint64_t)(t - grp.first_chunk) * grp.chunk_tiles;
     const TileOp* pops = ops + ps.op_begin;
     const bool init = grp.init != 0;
-    // the fixed-size paths run ops of up to 3 qubits with the coefficients in LDS
-    switch (ps.g.maxk <= 3 && ps.g.mat_count <= kBatchMats ? b : 0) {
-      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, smat); break;
-      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, smat); break;
-      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, smat); break;
+    // the fixed-size paths run ops of up to 3 qubits, 8x8 ops from their tables
+    switch (ps.g.maxk <= 3 && ps.g.mma_count <= kBatchTabs ? b : 0) {
+      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, tabs); break;
+      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, tabs); break;
+      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, tabs); break;
       default: run_chunk_var(sh, psi, tau0, grp.chunk_tiles, init, b, L, H, hb, choff, pops, ps.op_count, mats); break;
     }
-    // publish the finished tiles (release at agent scope)
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0)
-      __hip_atomic_fetch_add(&done[grp.circuit], (uint32_t)grp.chunk_tiles, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -285,11 +268,11 @@ __global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __rest
 }  // namespace
 
 int batch_max_bits() { return kBatchMaxBits; }
-int batch_mat_cap() { return kBatchMats; }
+int batch_mma_cap() { return kBatchTabs; }
 
 hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_reset, dim3((d.count + kThreads - 1) / kThreads + 1), dim3(kThreads), 0,
-                     s, d.done, d.count, (unsigned long long*)d.ticket, d.err);
+  hipLaunchKernelGGL(k_batch_reset, dim3((d.nrounds + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     (unsigned long long*)d.tickets, d.nrounds);
   static uint64_t slots = 0;
   if (slots == 0) {
     int dev = 0, cus = 256, per = 1;
@@ -301,10 +284,14 @@ hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s) {
       per = 1;
     slots = (uint64_t)cus * per;
   }
-  const uint64_t grid = d.nchunks < (long long)slots ? (uint64_t)d.nchunks : slots;
-  hipLaunchKernelGGL(k_batch, dim3((unsigned)(grid ? grid : 1)), dim3(kBatchThreads), 0, s, states,
-                     d.groups, d.ngroups, d.passes, d.ops, d.mats, d.done,
-                     (unsigned long long*)d.ticket, d.nchunks, d.err, d.spin_limit);
+  for (int r = 0; r < d.nrounds; ++r) {
+    const long long c0 = d.round_chunk[r], c1 = d.round_chunk[r + 1];
+    if (c1 <= c0) continue;
+    const uint64_t grid = (uint64_t)(c1 - c0) < slots ? (uint64_t)(c1 - c0) : slots;
+    hipLaunchKernelGGL(k_batch, dim3((unsigned)grid), dim3(kBatchThreads), 0, s, states, d.groups,
+                       d.round_group[r], d.round_group[r + 1], d.passes, d.ops, d.mats,
+                       (unsigned long long*)d.tickets + r, c0, c1);
+  }
   return hipGetLastError();
 }
 

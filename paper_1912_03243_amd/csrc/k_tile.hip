@@ -55,14 +55,16 @@ struct GeomLds {
   uint64_t choff[1 << kMaxGather];
 };
 
-// LDS coefficient slots of the pipelined kernels (512-thread kernels run
-// two workgroups per CU); only the FP32 kernels stage coefficients.
+// LDS room of the pipelined FP32 kernels for the tables of their 8x8 ops
+// (512-thread kernels run two workgroups per CU).
 template <typename T, int TB, int NT>
-struct FixedMats {
-  static constexpr int kSlots =
-      Fixed<T, TB, NT>::kMma ? mat_slots((int)sizeof(cplx<T>) << TB, (int)sizeof(GeomLds),
-                                         (int)sizeof(cplx<T>), NT == 512 ? 2 : 1)
-                             : 0;
+struct FixedTabs {
+  using Tab = typename Fixed<T, TB, NT>::Tab;
+  static constexpr int kCap =
+      Fixed<T, TB, NT>::kMma
+          ? (163840 / (NT == 512 ? 2 : 1) - ((int)sizeof(cplx<T>) << TB) - (int)sizeof(GeomLds)) /
+                (int)sizeof(Tab)
+          : 0;
 };
 template <int TB>
 struct Enc2Mats {
@@ -147,9 +149,9 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
   constexpr int NA = 1 << TB, PER = NA / NT;
   __shared__ cplx<T> sh[NA];
   __shared__ GeomLds gs;
-  constexpr int kSlots = FixedMats<T, TB, NT>::kSlots;
-  __shared__ cplx<T> smat[kSlots > 0 ? kSlots : 1];
-  if (kSlots > 0) stage_mats<T, NT>(smat, mats + (nops > 0 ? ops[0].moff : 0), g.mat_count);
+  constexpr int kCap = FixedTabs<T, TB, NT>::kCap;
+  __shared__ typename Fixed<T, TB, NT>::Tab tabs[kCap > 0 ? kCap : 1];
+  if constexpr (kCap > 0) Fixed<T, TB, NT>::build_tabs(tabs, ops, nops, mats);
   load_geom<NT>(g, gs);  // synchronises
   const int H = g.H, L = g.L, lmask = (1 << L) - 1;
   const uint64_t ntiles = uint64_t(1) << (g.n - TB);
@@ -184,7 +186,8 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
         v[k] = ld_stream(&gp[nb + gs.choff[e >> L] + (e & lmask)]);
       }
     }
-    Fixed<T, TB, NT>::run(sh, ops, nops, mats, smat);
+    if constexpr (kCap > 0) Fixed<T, TB, NT>::run_tab(sh, ops, nops, mats, tabs);
+    else Fixed<T, TB, NT>::run(sh, ops, nops, mats, nullptr);
     const uint64_t base = tile_base(tau, L, H, gs.hb);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -497,12 +500,18 @@ int tile_max_bits(juqcs_dtype dt) {
   return dt == JUQCS_C128 ? TileCfg<double>::kMaxBits : TileCfg<float>::kMaxBits;
 }
 
-int tile_mat_cap(juqcs_dtype dt, int b) {
+int tile_mma_cap(juqcs_dtype dt, int b) {
   if (dt == JUQCS_C64) {
-    if (b == 13) return FixedMats<float, 13, 1024>::kSlots;
-    if (b == 12) return FixedMats<float, 12, 512>::kSlots;
-    if (b == 11) return FixedMats<float, 11, 512>::kSlots;
-  } else if (dt == JUQCS_ENC2) {
+    if (b == 14) return FixedTabs<float, 14, 1024>::kCap;
+    if (b == 13) return FixedTabs<float, 13, 1024>::kCap;
+    if (b == 12) return FixedTabs<float, 12, 512>::kCap;
+    if (b == 11) return FixedTabs<float, 11, 512>::kCap;
+  }
+  return 0;
+}
+
+int tile_mat_cap(juqcs_dtype dt, int b) {
+  if (dt == JUQCS_ENC2) {
     if (b == 13) return Enc2Mats<13>::kSlots;
     if (b == 12) return Enc2Mats<12>::kSlots;
   }
@@ -522,8 +531,9 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
   hipLaunchKernelGGL((k_tile_fixed<T, TB, NT>), pgrid((const void*)k_tile_fixed<T, TB, NT>, NT), \
                      dim3(NT), 0, s, (cplx<T>*)amps, g, d_ops, nops, (const cplx<T>*)d_mats)
   // the pipelined kernels run ops of up to 3 qubits, with the coefficients in LDS
-  const int cap = tile_mat_cap(dt, g.b);  // 0: coefficients stay in global memory
-  const bool fixed_ok = g.maxk <= 3 && (cap == 0 || g.mat_count <= cap);
+  const int cap = tile_mat_cap(dt, g.b), mcap = tile_mma_cap(dt, g.b);  // 0: no limit
+  const bool fixed_ok = g.maxk <= 3 && (cap == 0 || g.mat_count <= cap) &&
+                        (mcap == 0 || g.mma_count <= mcap);
   if (dt == JUQCS_C128) {
     auto* p = (cplx<double>*)amps;
     auto* m = (const cplx<double>*)d_mats;
@@ -535,7 +545,8 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
   } else if (dt == JUQCS_C64) {
     auto* p = (cplx<float>*)amps;
     auto* m = (const cplx<float>*)d_mats;
-    if (fixed_ok && g.b == 13) JUQCS_FIXED(float, 13, 1024);
+    if (fixed_ok && g.b == 14) JUQCS_FIXED(float, 14, 1024);
+    else if (fixed_ok && g.b == 13) JUQCS_FIXED(float, 13, 1024);
     else if (fixed_ok && g.b == 12) JUQCS_FIXED(float, 12, 512);
     else if (fixed_ok && g.b == 11) JUQCS_FIXED(float, 11, 512);
     else if (g.b <= 13) hipLaunchKernelGGL((k_tile<float, 13>), grid, block, 0, s, p, g, d_ops, nops, m);

@@ -389,6 +389,12 @@ void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& 
   }
 }
 
+// Whether emit_ops makes a cluster an 8x8 (TOP_DENSE3) op.
+bool cluster_mma(const Cluster& c) {
+  int sigma = 0;
+  return c.q.size() == 3 && !monomial(c.m.data(), 8, &sigma);
+}
+
 // Coefficients emit_ops stores for a cluster.
 int cluster_coefs(const Cluster& c) {
   const int k = (int)c.q.size();
@@ -399,7 +405,7 @@ int cluster_coefs(const Cluster& c) {
 }
 
 void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, int kin,
-                   TilePlan* plan, int max_mats) {
+                   TilePlan* plan, int max_mats, int max_mma) {
   plan->passes.clear();
   plan->ops.clear();
   plan->mats.clear();
@@ -409,15 +415,19 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
   for (size_t i = 0; i < sched.passes.size(); ++i) {
     std::vector<Cluster> cl;
     fuse(gates, sched.taken[i], kin, &cl);
-    // consecutive runs of clusters whose coefficients fit max_mats
+    // consecutive runs of clusters whose coefficients fit max_mats and whose
+    // 8x8 ops fit max_mma
     size_t c0 = 0;
     do {
       size_t c1 = c0;
-      int coefs = 0;
+      int coefs = 0, mma = 0;
       while (c1 < cl.size()) {
         const int w = cluster_coefs(cl[c1]);
-        if (max_mats > 0 && c1 > c0 && coefs + w > max_mats) break;
+        const int x = cluster_mma(cl[c1]) ? 1 : 0;
+        if (c1 > c0 && ((max_mats > 0 && coefs + w > max_mats) || (max_mma > 0 && mma + x > max_mma)))
+          break;
         coefs += w;
+        mma += x;
         ++c1;
       }
       const std::vector<Cluster> part(cl.begin() + c0, cl.begin() + c1);
@@ -427,6 +437,7 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
       emit_ops(part, pass.g, plan);
       pass.op_count = (int32_t)plan->ops.size() - pass.op_begin;
       pass.g.mat_count = (int32_t)((int64_t)plan->mats.size() - m0);
+      pass.g.mma_count = mma;
       pass.g.maxk = 1;
       for (const Cluster& c : part) pass.g.maxk = std::max(pass.g.maxk, (int32_t)c.q.size());
       plan->passes.push_back(pass);
@@ -436,10 +447,10 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
 }
 
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan, int kin, int max_mats, int max_take) {
+                TilePlan* plan, int kin, int max_mats, int max_take, int max_mma) {
   TileSchedule sched;
   select_tiles(n, L, b, block_bits, gates, &sched, max_take);
-  emit_schedule(sched, gates, kin, plan, max_mats);
+  emit_schedule(sched, gates, kin, plan, max_mats, max_mma);
 }
 
 void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan) {

@@ -184,6 +184,19 @@ struct Var {
   }
 };
 
+// Per-lane tables of one FP32 matrix-core 8x8 op on a tile of 16 NBLK groups:
+// what the op's lanes would otherwise recompute from the op's bits for every
+// tile (sorting, bit spreading, swizzling, operand selection).  Built once
+// per pass; all offsets are tile-local and fit 16 bits (tiles of at most
+// 2^14 amplitudes).
+template <int NBLK>
+struct alignas(16) MmaTab {
+  float a[64][4];      // A operand of lane l for the steps j = 0..3
+  uint16_t rd[64][4];  // real-part index 2 lds(e) + p of the lane's reads (block part excluded)
+  uint16_t wr[64][2];  // lds slots of the lane's two written amplitudes (block part excluded)
+  uint16_t ub[NBLK];   // lds slot of each 16-group block's first group
+};
+
 // ------------------------------------------------------- fixed tile size ---
 // Groups of an op are processed in register blocks of KB: all reads of a
 // block are issued before its writes (groups are disjoint, so blocks need no
@@ -282,7 +295,8 @@ struct Fixed {
   template <int K>
   __device__ static void perm(cplx<T>* sh, const int32_t* bits, int sigma,
                               const cplx<T>* __restrict__ m, int tid) {
-    constexpr int D = 1 << K, ITEMS = NA >> K, CNT = (ITEMS + NT - 1) / NT, KB = CNT < 2 ? CNT : 2;
+    constexpr int D = 1 << K, ITEMS = NA >> K, CNT = (ITEMS + NT - 1) / NT;
+    constexpr int KB = CNT < 2 || K == 3 ? 1 : 2;  // at most 8 amplitudes in flight
     constexpr int CB = (int)sizeof(cplx<T>);
     int bt[K], sorted[K];
     sort_bits<K>(bits, bt, sorted);
@@ -413,8 +427,103 @@ struct Fixed {
     }
   }
 
+  static constexpr int kBlocks = NA / 8 / 16;
+  using Tab = MmaTab<kBlocks>;
+
+  // Fills tabs[0..) with the tables of the pass's 8x8 ops in order (the
+  // caller guarantees room and synchronises afterwards).
+  __device__ static void build_tabs(Tab* tabs, const TileOp* __restrict__ ops, int nops,
+                                    const cplx<T>* __restrict__ mats) {
+    int k = 0;
+    for (int o = 0; o < nops; ++o) {
+      const TileOp op = ops[o];
+      if (op.kind != TOP_DENSE3) continue;
+      Tab& t = tabs[k++];
+      int bt[3], sorted[3];
+      sort_bits<3>(op.bits, bt, sorted);
+      const cplx<T>* m = mats + op.moff;
+      for (int i = threadIdx.x; i < 64 + kBlocks; i += NT) {
+        if (i < 64) {
+          const int c = i & 15, q = i >> 4, h = q >> 1, pp = q & 1, r = c >> 1, p = c & 1;
+          const int lc = spread<3>(c, sorted);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const cplx<T> z = m[8 * r + 2 * j + h];
+            t.a[i][j] = p == pp ? z.re : (p ? z.im : -z.im);
+            t.rd[i][j] = (uint16_t)(2 * lds<T>(lc | row_offset<3>(2 * j + h, bt)) + pp);
+          }
+          t.wr[i][0] = (uint16_t)lds<T>(lc | row_offset<3>(2 * q, bt));
+          t.wr[i][1] = (uint16_t)lds<T>(lc | row_offset<3>(2 * q + 1, bt));
+        } else {
+          t.ub[i - 64] = (uint16_t)lds<T>(spread<3>((i - 64) * 16, sorted));
+        }
+      }
+    }
+  }
+
+  // The 8x8 matrix-core op from its tables (same data layout as dense3_mma).
+  __device__ static void dense3_tab(cplx<T>* sh, const Tab& t, int tid) {
+    static_assert(sizeof(T) == 4, "FP32 matrix-core op");
+    constexpr int W = NT / 64, PER_W = kBlocks / W;
+    static_assert(kBlocks % W == 0, "whole 16-group blocks per wave");
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f a = *reinterpret_cast<const v4f*>(t.a[lane]);
+    int rd[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rd[j] = t.rd[lane][j];
+    const int w0 = t.wr[lane][0], w1 = t.wr[lane][1];
+    float* f = reinterpret_cast<float*>(sh);
+    constexpr int NB = PER_W >= 2 ? 2 : 1;
+#pragma unroll
+    for (int i0 = 0; i0 < PER_W; i0 += NB) {
+      int ub[NB];
+      float x[NB][4];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        ub[u] = t.ub[(i0 + u) * W + wave];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[u][j] = f[(2 * ub[u]) ^ rd[j]];
+      }
+      v4f acc[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) acc[u] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[u][j], acc[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        sh[ub[u] ^ w0] = cplx<T>{acc[u][0], acc[u][1]};
+        sh[ub[u] ^ w1] = cplx<T>{acc[u][2], acc[u][3]};
+      }
+    }
+  }
+
   // The matrix cores pay off for FP32 (twice the vector rate), not for FP64.
   static constexpr bool kMma = sizeof(T) == 4;
+
+  // As run() below, with the 8x8 ops taken from their tables (FP32).
+  __device__ static void run_tab(cplx<T>* sh, const TileOp* __restrict__ ops, int nops,
+                                 const cplx<T>* __restrict__ mats, const Tab* tabs) {
+    int k = 0;
+    for (int o = 0; o < nops; ++o) {
+      const TileOp op = ops[o];
+      const int tid = (int)threadIdx.x;
+      if (op.kind == TOP_DENSE2) dense2(sh, op.a, op.b, mats + op.moff, tid);
+      else if (op.kind == TOP_DENSE1) dense1(sh, op.a, mats + op.moff, tid);
+      else if (op.kind == TOP_DIAG2) diag2(sh, op.a, op.b, mats + op.moff, tid);
+      else if (op.kind == TOP_PERM) {
+        if (op.k == 1) perm<1>(sh, op.bits, op.a, mats + op.moff, tid);
+        else if (op.k == 2) perm<2>(sh, op.bits, op.a, mats + op.moff, tid);
+        else perm<3>(sh, op.bits, op.a, mats + op.moff, tid);
+      }
+      else dense3_tab(sh, tabs[k++], tid);  // callers route 4-qubit ops elsewhere
+      __syncthreads();
+    }
+  }
 
   // mats: every coefficient in global memory (op.moff); lmats (FP32 only):
   // the pass's coefficients staged in LDS from ops[0].moff on.  The vector

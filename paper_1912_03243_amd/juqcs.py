@@ -315,7 +315,7 @@ class State:
 
 # ---- Batch --------------------------------------------------------------------
 class Batch:
-    """Many independent C64 circuits executed by one persistent launch."""
+    """Many independent C64 circuits executed by one graph launch (one kernel per pass round)."""
 
     def __init__(self, circuits, device="cuda", states=None, fuse_k: int = 0,
                  autotune: bool = False):

@@ -1,4 +1,4 @@
-"""GPU parity of the batched persistent launch and of the Eq. (3) branch
+"""GPU parity of the batched graph launch and of the Eq. (3) branch
 driver against the oracle."""
 import math
 import os
