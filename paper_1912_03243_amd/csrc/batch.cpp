@@ -140,6 +140,7 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
     first_pass[c] = (int)passes.size();
     const int64_t op0 = (int64_t)ops.size(), m0 = (int64_t)mats.size();
     for (const TilePass& tp : p.passes) {
+      if (tp.g.H > batch_max_gather()) return fail(JUQCS_ERR_ARG, "batch tile with too many gathered bits");
       BatchPass bp;
       bp.g = tp.g;
       bp.op_begin = (int32_t)(op0 + tp.op_begin);

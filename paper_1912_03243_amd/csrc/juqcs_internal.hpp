@@ -83,6 +83,7 @@ __host__ __device__ inline uint64_t insert_zero(uint64_t x, int pos) {
 // L + i is physical bit hbits[i].  Ops act on local bits.
 // ---------------------------------------------------------------------------
 constexpr int kMaxGather = 10;  // gathered chunk bits of a tile pass
+constexpr int kPassOps = 48;    // most ops the planner puts in one pass
 constexpr int kHbitsCap = 12;   // fused blocks reuse the struct: 2k <= 12
 
 struct TileGeom {
@@ -202,6 +203,7 @@ struct BatchDevice {
 
 int batch_max_bits();
 int batch_mma_cap();  // 8x8 ops per pass whose tables the batch kernel holds in LDS
+int batch_max_gather();  // most gathered chunk bits of a batch pass
 hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s);
 hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, const int32_t* nq,
                                int count, int m, const uint64_t* idx, double* out, hipStream_t s);

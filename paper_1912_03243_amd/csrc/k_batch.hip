@@ -25,7 +25,15 @@ constexpr int kThreads = 256;       // helper kernels
 constexpr int kBatchThreads = 1024;  // the persistent batch kernel
 constexpr int kBatchMaxBits = 13;   // 64 KiB of C64 amplitudes per tile
 constexpr int kBatchTabs = 44;      // 8x8-op tables per pass (about 83 KiB of LDS)
+constexpr int kBatchGather = 6;     // gathered chunk bits (tiles keep min(7, b) low bits)
 using BatchTab = tileops::MmaTab<(1 << kBatchMaxBits) / 128>;  // the largest table
+
+// Passes the fixed-size paths take: ops of up to 3 qubits, every 8x8 op's
+// table and every op's parameters in LDS, chunk table in LDS.
+__device__ inline bool fixed_pass(const BatchPass& ps) {
+  return ps.g.maxk <= 3 && ps.g.mma_count <= kBatchTabs && ps.op_count <= kPassOps &&
+         ps.g.H <= kBatchGather;
+}
 
 __device__ inline uint64_t tile_base_hb(uint64_t tau, int L, int H, const int* hb) {
   uint64_t base = tau << L;
@@ -47,7 +55,8 @@ template <int TB>
 __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64_t tau0, int ntile,
                                        bool init, int L, int H, const int* hb,
                                        const uint64_t* choff, const TileOp* ops, int nops,
-                                       const cplx<float>* mats, const void* tabs) {
+                                       const cplx<float>* mats, const tileops::OpPre* pre,
+                                       const void* tabs) {
   constexpr int NA = 1 << TB, PER = NA / kBatchThreads;
   const int lmask = (1 << L) - 1;
   typedef float v2 __attribute__((ext_vector_type(2)));
@@ -85,7 +94,7 @@ __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64
       }
     }
     using F = Fixed<float, TB, kBatchThreads>;
-    F::run_tab(sh, ops, nops, mats, reinterpret_cast<const typename F::Tab*>(tabs));
+    F::template run<F::D3_TAB>(sh, ops, nops, mats, pre, tabs);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = k * kBatchThreads + threadIdx.x;
@@ -124,8 +133,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     const cplx<float>* __restrict__ mats, unsigned long long* __restrict__ ticket, long long c0,
     long long c1) {
   __shared__ cplx<float> sh[1 << kBatchMaxBits];
-  __shared__ uint64_t choff[1 << kMaxGather];
+  __shared__ uint64_t choff[1 << kBatchGather];
   __shared__ BatchTab tabs[kBatchTabs];  // the current pass's 8x8-op tables
+  __shared__ tileops::OpPre pre[kPassOps];  // the current pass's op parameters
   __shared__ int hb[kHbitsCap];
   __shared__ long long s_t;
   __shared__ int s_g;
@@ -164,14 +174,21 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
         for (int j = 0; j < H; ++j) o |= (uint64_t)((c >> j) & 1) << hb[j];
         choff[c] = o;
       }
-      if (ps.g.maxk <= 3 && ps.g.mma_count <= kBatchTabs) {
+      if (fixed_pass(ps)) {
         const TileOp* pops = ops + ps.op_begin;
-        if (b == 13) Fixed<float, 13, kBatchThreads>::build_tabs(
-            reinterpret_cast<Fixed<float, 13, kBatchThreads>::Tab*>(tabs), pops, ps.op_count, mats);
-        else if (b == 12) Fixed<float, 12, kBatchThreads>::build_tabs(
-            reinterpret_cast<Fixed<float, 12, kBatchThreads>::Tab*>(tabs), pops, ps.op_count, mats);
-        else if (b == 11) Fixed<float, 11, kBatchThreads>::build_tabs(
-            reinterpret_cast<Fixed<float, 11, kBatchThreads>::Tab*>(tabs), pops, ps.op_count, mats);
+        if (b == 13) {
+          using F = Fixed<float, 13, kBatchThreads>;
+          F::build_tabs(reinterpret_cast<F::Tab*>(tabs), pops, ps.op_count, mats);
+          F::build_pre(pre, pops, ps.op_count);
+        } else if (b == 12) {
+          using F = Fixed<float, 12, kBatchThreads>;
+          F::build_tabs(reinterpret_cast<F::Tab*>(tabs), pops, ps.op_count, mats);
+          F::build_pre(pre, pops, ps.op_count);
+        } else if (b == 11) {
+          using F = Fixed<float, 11, kBatchThreads>;
+          F::build_tabs(reinterpret_cast<F::Tab*>(tabs), pops, ps.op_count, mats);
+          F::build_pre(pre, pops, ps.op_count);
+        }
       }
       __syncthreads();
       cur_pass = grp.pass;
@@ -181,10 +198,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     const TileOp* pops = ops + ps.op_begin;
     const bool init = grp.init != 0;
     // the fixed-size paths run ops of up to 3 qubits, 8x8 ops from their tables
-    switch (ps.g.maxk <= 3 && ps.g.mma_count <= kBatchTabs ? b : 0) {
-      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, tabs); break;
-      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, tabs); break;
-      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, tabs); break;
+    switch (fixed_pass(ps) ? b : 0) {
+      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs); break;
+      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs); break;
+      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs); break;
       default: run_chunk_var(sh, psi, tau0, grp.chunk_tiles, init, b, L, H, hb, choff, pops, ps.op_count, mats); break;
     }
     __syncthreads();
@@ -269,6 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __rest
 
 int batch_max_bits() { return kBatchMaxBits; }
 int batch_mma_cap() { return kBatchTabs; }
+int batch_max_gather() { return kBatchGather; }
 
 hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3((d.nrounds + kThreads - 1) / kThreads), dim3(kThreads), 0, s,

@@ -27,6 +27,7 @@ namespace {
 
 using tileops::Fixed;
 using tileops::lds;
+using tileops::OpPre;
 using tileops::mat_slots;
 using tileops::stage_mats;
 using tileops::Var;
@@ -49,11 +50,18 @@ struct TileCfg<float> {
 };
 
 // Tile geometry copied to LDS once per workgroup (dynamic indexing of the
-// kernel-argument struct would go through scratch).
-struct GeomLds {
+// kernel-argument struct would go through scratch); room for 2^HMAX chunks.
+template <int HMAX>
+struct GeomLdsT {
   int hb[kHbitsCap];
-  uint64_t choff[1 << kMaxGather];
+  uint64_t choff[1 << HMAX];
 };
+using GeomLds = GeomLdsT<kMaxGather>;
+
+// The pipelined kernels keep every op's uniform parameters in LDS; passes
+// with more ops go to the generic kernels (the planner splits them).
+constexpr int kFixedOps = kPassOps;
+constexpr int kEnc2Gather = 6;  // two-byte tiles: chunks of at least 2^7 amplitudes
 
 // LDS room of the pipelined FP32 kernels for the tables of their 8x8 ops
 // (512-thread kernels run two workgroups per CU).
@@ -62,19 +70,21 @@ struct FixedTabs {
   using Tab = typename Fixed<T, TB, NT>::Tab;
   static constexpr int kCap =
       Fixed<T, TB, NT>::kMma
-          ? (163840 / (NT == 512 ? 2 : 1) - ((int)sizeof(cplx<T>) << TB) - (int)sizeof(GeomLds)) /
+          ? (163840 / (NT == 512 ? 2 : 1) - ((int)sizeof(cplx<T>) << TB) - (int)sizeof(GeomLds) -
+             kFixedOps * (int)sizeof(OpPre)) /
                 (int)sizeof(Tab)
           : 0;
 };
 template <int TB>
 struct Enc2Mats {
   static constexpr int kSlots = mat_slots((int)sizeof(cplx<float>) << TB,
-                                          (int)sizeof(GeomLds) + (4 << TB) / 8,
+                                          (int)sizeof(GeomLdsT<kEnc2Gather>) + (4 << TB) / 8 +
+                                              kFixedOps * (int)sizeof(OpPre),
                                           (int)sizeof(cplx<float>), 2);
 };
 
-template <int NT>
-__device__ inline void load_geom(const TileGeom& g, GeomLds& s) {
+template <int NT, int HMAX>
+__device__ inline void load_geom(const TileGeom& g, GeomLdsT<HMAX>& s) {
   if (threadIdx.x < kHbitsCap) s.hb[threadIdx.x] = (int)threadIdx.x < g.H ? g.hbits[threadIdx.x] : 0;
   __syncthreads();
   for (int c = threadIdx.x; c < (1 << g.H); c += NT) {
@@ -149,9 +159,12 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
   constexpr int NA = 1 << TB, PER = NA / NT;
   __shared__ cplx<T> sh[NA];
   __shared__ GeomLds gs;
+  __shared__ OpPre pre[kFixedOps];
+  using F = Fixed<T, TB, NT>;
   constexpr int kCap = FixedTabs<T, TB, NT>::kCap;
-  __shared__ typename Fixed<T, TB, NT>::Tab tabs[kCap > 0 ? kCap : 1];
-  if constexpr (kCap > 0) Fixed<T, TB, NT>::build_tabs(tabs, ops, nops, mats);
+  __shared__ typename F::Tab tabs[kCap > 0 ? kCap : 1];
+  F::build_pre(pre, ops, nops);
+  if constexpr (kCap > 0) F::build_tabs(tabs, ops, nops, mats);
   load_geom<NT>(g, gs);  // synchronises
   const int H = g.H, L = g.L, lmask = (1 << L) - 1;
   const uint64_t ntiles = uint64_t(1) << (g.n - TB);
@@ -186,8 +199,8 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
         v[k] = ld_stream(&gp[nb + gs.choff[e >> L] + (e & lmask)]);
       }
     }
-    if constexpr (kCap > 0) Fixed<T, TB, NT>::run_tab(sh, ops, nops, mats, tabs);
-    else Fixed<T, TB, NT>::run(sh, ops, nops, mats, nullptr);
+    if constexpr (kCap > 0) F::template run<F::D3_TAB>(sh, ops, nops, mats, pre, tabs);
+    else F::template run<F::D3_VALU>(sh, ops, nops, mats, pre, nullptr);
     const uint64_t base = tile_base(tau, L, H, gs.hb);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -294,10 +307,13 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
     const TileOp* __restrict__ ops, int nops, const cplx<float>* __restrict__ mats) {
   constexpr int NA = 1 << TB, NG = NA / 8, PER = (NG + kFixedThreads - 1) / kFixedThreads;
   __shared__ cplx<float> sh[NA];
-  __shared__ GeomLds gs;
+  __shared__ GeomLdsT<kEnc2Gather> gs;
   __shared__ uint32_t bmax[NA / 8];
+  __shared__ OpPre pre[kFixedOps];
   __shared__ cplx<float> smat[Enc2Mats<TB>::kSlots];
+  using F = Fixed<float, TB, kFixedThreads>;
   stage_mats<float, kFixedThreads>(smat, mats + (nops > 0 ? ops[0].moff : 0), g.mat_count);
+  F::build_pre(pre, ops, nops);
   load_geom<kFixedThreads>(g, gs);  // synchronises
   const int H = g.H, L = g.L, B = g.block_bits, lmask = (1 << L) - 1;
   const int nblk = NA >> B;
@@ -328,7 +344,7 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
     }
     __syncthreads();
     fetch(tau + 1 < tau_end ? tau + 1 : tau);
-    Fixed<float, TB, kFixedThreads>::run(sh, ops, nops, mats, smat);
+    F::template run<F::D3_STAGED>(sh, ops, nops, mats, pre, smat);
     store_enc2<kFixedThreads>(sh, bmax, NA, B, L, lmask, tile_base(tau, L, H, gs.hb), gs.choff,
                               codes, scales);
     __syncthreads();
@@ -532,8 +548,9 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
                      dim3(NT), 0, s, (cplx<T>*)amps, g, d_ops, nops, (const cplx<T>*)d_mats)
   // the pipelined kernels run ops of up to 3 qubits, with the coefficients in LDS
   const int cap = tile_mat_cap(dt, g.b), mcap = tile_mma_cap(dt, g.b);  // 0: no limit
-  const bool fixed_ok = g.maxk <= 3 && (cap == 0 || g.mat_count <= cap) &&
-                        (mcap == 0 || g.mma_count <= mcap);
+  const bool fixed_ok = g.maxk <= 3 && nops <= kFixedOps && (cap == 0 || g.mat_count <= cap) &&
+                        (mcap == 0 || g.mma_count <= mcap) &&
+                        (dt != JUQCS_ENC2 || g.H <= kEnc2Gather);
   if (dt == JUQCS_C128) {
     auto* p = (cplx<double>*)amps;
     auto* m = (const cplx<double>*)d_mats;

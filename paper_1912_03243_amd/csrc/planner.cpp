@@ -424,7 +424,8 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
       while (c1 < cl.size()) {
         const int w = cluster_coefs(cl[c1]);
         const int x = cluster_mma(cl[c1]) ? 1 : 0;
-        if (c1 > c0 && ((max_mats > 0 && coefs + w > max_mats) || (max_mma > 0 && mma + x > max_mma)))
+        if (c1 > c0 && ((max_mats > 0 && coefs + w > max_mats) || (max_mma > 0 && mma + x > max_mma) ||
+                        (int)(c1 - c0) >= kPassOps))
           break;
         coefs += w;
         mma += x;

@@ -197,6 +197,18 @@ struct alignas(16) MmaTab {
   uint16_t ub[NBLK];   // lds slot of each 16-group block's first group
 };
 
+// Uniform parameters of one in-tile op of a pass, built once per launch (the
+// fixed-size kernels would otherwise recompute them for every tile).  Byte
+// offsets within the tile; the group of item k NT + tid sits at
+// grp[k] ^ lds(spread(tid)) * sizeof(amplitude).
+struct alignas(16) OpPre {
+  int32_t row[8];   // offsets of the op's rows within a group (the rows written)
+  int32_t src[8];   // monomial ops: offsets of the rows read for each written row
+  int32_t grp[16];  // uniform part of the group offset of items k NT + tid
+  int32_t pos;      // group-bit positions, ascending, 4 bits each
+  int32_t pad[3];
+};
+
 // ------------------------------------------------------- fixed tile size ---
 // Groups of an op are processed in register blocks of KB: all reads of a
 // block are issued before its writes (groups are disjoint, so blocks need no
@@ -206,15 +218,67 @@ template <typename T, int TB, int NT>
 struct Fixed {
   static constexpr int NA = 1 << TB;
 
-  // Element addresses below are byte offsets into the tile, split as
-  // lds(spread(k NT + tid)) = lds(spread(k NT)) ^ lds(spread(tid)): the first
-  // part is uniform, the second fixed per thread for the op.
-  __device__ static void dense1(cplx<T>* sh, int a, const cplx<T>* __restrict__ m, int tid) {
+  static constexpr int CB = (int)sizeof(cplx<T>);
+
+  // Target positions of an op (ascending) packed 4 bits each.
+  template <int K>
+  __device__ static void unpack(int packed, int* pos) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) pos[j] = (packed >> (4 * j)) & 15;
+  }
+
+  // Fills pre[0..nops) (one op per thread, written straight to LDS; the
+  // caller synchronises).
+  __device__ static void build_pre(OpPre* pre, const TileOp* __restrict__ ops, int nops) {
+    for (int o = threadIdx.x; o < nops; o += NT) {
+      const TileOp op = ops[o];
+      OpPre& p = pre[o];
+      int b0 = 0, b1 = 0, b2 = 0, np = 0;  // target bits in matrix order
+      if (op.kind == TOP_DENSE1) {
+        b0 = op.a;
+        np = 1;
+      } else if (op.kind == TOP_DENSE2) {
+        b0 = op.a;
+        b1 = op.b;
+        np = 2;
+      } else if (op.kind == TOP_PERM || op.kind == TOP_DENSE3) {
+        np = op.kind == TOP_PERM ? op.k : 3;
+        b0 = op.bits[0];
+        b1 = np > 1 ? op.bits[1] : 0;
+        b2 = np > 2 ? op.bits[2] : 0;
+      }  // TOP_DIAG2: items are single elements (np = 0)
+      for (int r = 0; r < 8; ++r) {
+        const int sr = op.kind == TOP_PERM ? (op.a >> (3 * r)) & 7 : r;
+        const int ro = (np > 0 ? (r & 1) << b0 : 0) | (np > 1 ? ((r >> 1) & 1) << b1 : 0) |
+                       (np > 2 ? ((r >> 2) & 1) << b2 : 0);
+        const int rs = (np > 0 ? (sr & 1) << b0 : 0) | (np > 1 ? ((sr >> 1) & 1) << b1 : 0) |
+                       (np > 2 ? ((sr >> 2) & 1) << b2 : 0);
+        p.row[r] = r < (1 << np) ? lds<T>(ro) * CB : 0;
+        p.src[r] = r < (1 << np) ? lds<T>(rs) * CB : 0;
+      }
+      // ascending positions
+      int s0 = b0, s1 = b1, s2 = b2;
+      if (np > 1 && s0 > s1) { const int t = s0; s0 = s1; s1 = t; }
+      if (np > 2 && s1 > s2) { const int t = s1; s1 = s2; s2 = t; }
+      if (np > 1 && s0 > s1) { const int t = s0; s0 = s1; s1 = t; }
+      const int items = NA >> np;
+      for (int k = 0; k < 16; ++k) {
+        int g = k * NT < items ? k * NT : 0;
+        if (np > 0) g = ((g >> s0) << (s0 + 1)) | (g & ((1 << s0) - 1));
+        if (np > 1) g = ((g >> s1) << (s1 + 1)) | (g & ((1 << s1) - 1));
+        if (np > 2) g = ((g >> s2) << (s2 + 1)) | (g & ((1 << s2) - 1));
+        p.grp[k] = lds<T>(g) * CB;
+      }
+      p.pos = (np > 0 ? s0 : 0) | ((np > 1 ? s1 : 0) << 4) | ((np > 2 ? s2 : 0) << 8);
+    }
+  }
+
+  __device__ static void dense1(cplx<T>* sh, const OpPre& q, const cplx<T>* __restrict__ m, int tid) {
     constexpr int ITEMS = NA / 2, CNT = (ITEMS + NT - 1) / NT, KB = CNT < 4 ? CNT : 4;
-    constexpr int CB = (int)sizeof(cplx<T>);
     const cplx<T> u0 = m[0], u1 = m[1], u2 = m[2], u3 = m[3];
-    const int pos[1] = {a};
-    const int ob = lds<T>(1 << a) * CB;
+    int pos[1];
+    unpack<1>(q.pos, pos);
+    const int ob = q.row[1];
     const int lt = lds<T>(spread<1>(tid, pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
@@ -225,7 +289,7 @@ struct Fixed {
       for (int kk = 0; kk < KB; ++kk) {
         const int k = k0 + kk;
         const bool ok = ITEMS % NT == 0 || k * NT + tid < ITEMS;
-        o[kk] = ok ? (lds<T>(spread<1>(k * NT, pos)) * CB) ^ lt : 0;
+        o[kk] = ok ? q.grp[k] ^ lt : 0;
         x[kk] = *reinterpret_cast<const cplx<T>*>(base + o[kk]);
         y[kk] = *reinterpret_cast<const cplx<T>*>(base + (o[kk] ^ ob));
       }
@@ -239,12 +303,13 @@ struct Fixed {
     }
   }
 
-  __device__ static void dense2(cplx<T>* sh, int a, int c, const cplx<T>* __restrict__ m, int tid) {
+  __device__ static void dense2(cplx<T>* sh, const OpPre& q, const cplx<T>* __restrict__ m, int tid) {
     constexpr int ITEMS = NA / 4, CNT = (ITEMS + NT - 1) / NT, KB = CNT < 2 ? CNT : 2;
-    constexpr int CB = (int)sizeof(cplx<T>);
-    const int pos[2] = {a < c ? a : c, a < c ? c : a};
-    const int oa = lds<T>(1 << a) * CB, oc = lds<T>(1 << c) * CB;
-    const int off[4] = {0, oa, oc, oa ^ oc};
+    int pos[2];
+    unpack<2>(q.pos, pos);
+    int off[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) off[r] = q.row[r];
     const int lt = lds<T>(spread<2>(tid, pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
@@ -255,7 +320,7 @@ struct Fixed {
       for (int kk = 0; kk < KB; ++kk) {
         const int k = k0 + kk;
         const bool ok = ITEMS % NT == 0 || k * NT + tid < ITEMS;
-        o[kk] = ok ? (lds<T>(spread<2>(k * NT, pos)) * CB) ^ lt : 0;
+        o[kk] = ok ? q.grp[k] ^ lt : 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[kk][r] = *reinterpret_cast<const cplx<T>*>(base + (o[kk] ^ off[r]));
       }
@@ -275,8 +340,9 @@ struct Fixed {
     }
   }
 
-  __device__ static void diag2(cplx<T>* sh, int a, int c, const cplx<T>* __restrict__ m, int tid) {
-    constexpr int CNT = (NA + NT - 1) / NT, CB = (int)sizeof(cplx<T>);
+  __device__ static void diag2(cplx<T>* sh, const OpPre& q, int a, int c, const cplx<T>* __restrict__ m,
+                               int tid) {
+    constexpr int CNT = (NA + NT - 1) / NT;
     const cplx<T> d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
     const int lt = lds<T>(tid) * CB;
     char* base = reinterpret_cast<char*>(sh);
@@ -284,29 +350,21 @@ struct Fixed {
     for (int k = 0; k < CNT; ++k) {
       const int e = k * NT + tid;
       if (NA % NT == 0 || e < NA) {
-        cplx<T>* z = reinterpret_cast<cplx<T>*>(base + ((lds<T>(k * NT) * CB) ^ lt));
+        cplx<T>* z = reinterpret_cast<cplx<T>*>(base + (q.grp[k] ^ lt));
         *z = cmul(diag_pick(e, a, c, d0, d1, d2, d3), *z);
       }
     }
   }
 
   // monomial on K <= 3 local bits: out[r] = c[r] in[sigma(r)]; the reads go
-  // straight to the permuted rows (sigma is uniform), so no selects
+  // straight to the permuted rows, so no selects
   template <int K>
-  __device__ static void perm(cplx<T>* sh, const int32_t* bits, int sigma,
-                              const cplx<T>* __restrict__ m, int tid) {
+  __device__ static void perm(cplx<T>* sh, const OpPre& q, const cplx<T>* __restrict__ m, int tid) {
     constexpr int D = 1 << K, ITEMS = NA >> K, CNT = (ITEMS + NT - 1) / NT;
     constexpr int KB = CNT < 2 || K == 3 ? 1 : 2;  // at most 8 amplitudes in flight
-    constexpr int CB = (int)sizeof(cplx<T>);
-    int bt[K], sorted[K];
-    sort_bits<K>(bits, bt, sorted);
-    int dst[D], src[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-      dst[r] = lds<T>(row_offset<K>(r, bt)) * CB;
-      src[r] = lds<T>(row_offset<K>((sigma >> (3 * r)) & 7, bt)) * CB;
-    }
-    const int lt = lds<T>(spread<K>(tid, sorted)) * CB;
+    int pos[K];
+    unpack<K>(q.pos, pos);
+    const int lt = lds<T>(spread<K>(tid, pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k0 = 0; k0 < CNT; k0 += KB) {
@@ -316,16 +374,16 @@ struct Fixed {
       for (int kk = 0; kk < KB; ++kk) {
         const int k = k0 + kk;
         const bool ok = ITEMS % NT == 0 || k * NT + tid < ITEMS;
-        o[kk] = ok ? (lds<T>(spread<K>(k * NT, sorted)) * CB) ^ lt : 0;
+        o[kk] = ok ? q.grp[k] ^ lt : 0;
 #pragma unroll
-        for (int r = 0; r < D; ++r) v[kk][r] = *reinterpret_cast<const cplx<T>*>(base + (o[kk] ^ src[r]));
+        for (int r = 0; r < D; ++r) v[kk][r] = *reinterpret_cast<const cplx<T>*>(base + (o[kk] ^ q.src[r]));
       }
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
         if (ITEMS % NT == 0 || (k0 + kk) * NT + tid < ITEMS) {
 #pragma unroll
           for (int r = 0; r < D; ++r)
-            *reinterpret_cast<cplx<T>*>(base + (o[kk] ^ dst[r])) = cmul(m[r], v[kk][r]);
+            *reinterpret_cast<cplx<T>*>(base + (o[kk] ^ q.row[r])) = cmul(m[r], v[kk][r]);
         }
       }
     }
@@ -334,21 +392,19 @@ struct Fixed {
   // 8x8 on three local bits on the vector units (FP64: the matrix cores run
   // FP64 at the vector rate, and the uniform coefficients come through the
   // scalar cache); one group of 8 amplitudes in registers at a time.
-  __device__ static void dense3_valu(cplx<T>* sh, const int32_t* bits, const cplx<T>* __restrict__ m,
-                                     int tid) {
+  __device__ static void dense3_valu(cplx<T>* sh, const OpPre& q, const cplx<T>* __restrict__ m, int tid) {
     constexpr int ITEMS = NA / 8, CNT = (ITEMS + NT - 1) / NT;
-    int bt[3], sorted[3];
-    sort_bits<3>(bits, bt, sorted);
-    // byte offsets of the 8 rows (uniform), XORed onto each group's base
+    int pos[3];
+    unpack<3>(q.pos, pos);
     int off[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) off[r] = lds<T>(row_offset<3>(r, bt)) * (int)sizeof(cplx<T>);
+    for (int r = 0; r < 8; ++r) off[r] = q.row[r];
+    const int lt = lds<T>(spread<3>(tid, pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k = 0; k < CNT; ++k) {
-      const int p = k * NT + tid;
-      const bool ok = ITEMS % NT == 0 || p < ITEMS;
-      const int gb = lds<T>(spread<3>(ok ? p : 0, sorted)) * (int)sizeof(cplx<T>);
+      const bool ok = ITEMS % NT == 0 || k * NT + tid < ITEMS;
+      const int gb = ok ? q.grp[k] ^ lt : 0;
       cplx<T> v[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = *reinterpret_cast<const cplx<T>*>(base + (gb ^ off[r]));
@@ -505,46 +561,36 @@ struct Fixed {
   // The matrix cores pay off for FP32 (twice the vector rate), not for FP64.
   static constexpr bool kMma = sizeof(T) == 4;
 
-  // As run() below, with the 8x8 ops taken from their tables (FP32).
-  __device__ static void run_tab(cplx<T>* sh, const TileOp* __restrict__ ops, int nops,
-                                 const cplx<T>* __restrict__ mats, const Tab* tabs) {
-    int k = 0;
-    for (int o = 0; o < nops; ++o) {
-      const TileOp op = ops[o];
-      const int tid = (int)threadIdx.x;
-      if (op.kind == TOP_DENSE2) dense2(sh, op.a, op.b, mats + op.moff, tid);
-      else if (op.kind == TOP_DENSE1) dense1(sh, op.a, mats + op.moff, tid);
-      else if (op.kind == TOP_DIAG2) diag2(sh, op.a, op.b, mats + op.moff, tid);
-      else if (op.kind == TOP_PERM) {
-        if (op.k == 1) perm<1>(sh, op.bits, op.a, mats + op.moff, tid);
-        else if (op.k == 2) perm<2>(sh, op.bits, op.a, mats + op.moff, tid);
-        else perm<3>(sh, op.bits, op.a, mats + op.moff, tid);
-      }
-      else dense3_tab(sh, tabs[k++], tid);  // callers route 4-qubit ops elsewhere
-      __syncthreads();
-    }
-  }
+  // How a kernel applies 8x8 ops: on the vector units (FP64), on the matrix
+  // cores from per-pass tables (FP32), or on the matrix cores from
+  // coefficients staged in LDS (FP32 kernels without room for the tables).
+  enum { D3_VALU = 0, D3_TAB = 1, D3_STAGED = 2 };
 
-  // mats: every coefficient in global memory (op.moff); lmats (FP32 only):
-  // the pass's coefficients staged in LDS from ops[0].moff on.  The vector
-  // ops take their uniform coefficients through the scalar cache, the
-  // matrix-core op its per-lane operands from LDS.
+  // Applies the pass's ops to the tile in sh.  pre: the ops' uniform
+  // parameters (build_pre); aux: the 8x8 tables (D3_TAB) or the staged
+  // coefficients from ops[0].moff on (D3_STAGED).
+  template <int MODE>
   __device__ static void run(cplx<T>* sh, const TileOp* __restrict__ ops, int nops,
-                             const cplx<T>* __restrict__ mats, const cplx<T>* lmats) {
+                             const cplx<T>* __restrict__ mats, const OpPre* pre, const void* aux) {
     const int64_t mbase = nops > 0 ? ops[0].moff : 0;
+    int k3 = 0;
     for (int o = 0; o < nops; ++o) {
       const TileOp op = ops[o];
+      const OpPre& q = pre[o];
       const int tid = (int)threadIdx.x;
-      if (op.kind == TOP_DENSE2) dense2(sh, op.a, op.b, mats + op.moff, tid);
-      else if (op.kind == TOP_DENSE1) dense1(sh, op.a, mats + op.moff, tid);
-      else if (op.kind == TOP_DIAG2) diag2(sh, op.a, op.b, mats + op.moff, tid);
+      const cplx<T>* m = mats + op.moff;
+      if (op.kind == TOP_DENSE2) dense2(sh, q, m, tid);
+      else if (op.kind == TOP_DENSE1) dense1(sh, q, m, tid);
+      else if (op.kind == TOP_DIAG2) diag2(sh, q, op.a, op.b, m, tid);
       else if (op.kind == TOP_PERM) {
-        if (op.k == 1) perm<1>(sh, op.bits, op.a, mats + op.moff, tid);
-        else if (op.k == 2) perm<2>(sh, op.bits, op.a, mats + op.moff, tid);
-        else perm<3>(sh, op.bits, op.a, mats + op.moff, tid);
+        if (op.k == 1) perm<1>(sh, q, m, tid);
+        else if (op.k == 2) perm<2>(sh, q, m, tid);
+        else perm<3>(sh, q, m, tid);
+      } else {  // 8x8 (callers route passes with 4-qubit ops elsewhere)
+        if constexpr (MODE == D3_VALU) dense3_valu(sh, q, m, tid);
+        else if constexpr (MODE == D3_TAB) dense3_tab(sh, reinterpret_cast<const Tab*>(aux)[k3++], tid);
+        else dense3_mma(sh, op.bits, reinterpret_cast<const cplx<T>*>(aux) + (op.moff - mbase), tid);
       }
-      else if constexpr (kMma) dense3_mma(sh, op.bits, lmats + (op.moff - mbase), tid);
-      else dense3_valu(sh, op.bits, mats + op.moff, tid);  // callers route 4-qubit ops elsewhere
       __syncthreads();
     }
   }
