@@ -150,16 +150,38 @@ juqcs_status run_tile_plan(juqcs_state* st, const TilePlan& plan) {
   const size_t ops_bytes = plan.ops.size() * sizeof(TileOp);
   std::vector<char> buf;
   size_t mats_off = (ops_bytes + 255) & ~size_t(255);
+  std::vector<TileOp> ops = plan.ops;
   if (st->dt == JUQCS_C128) {
-    buf.resize(mats_off + plan.mats.size() * sizeof(C));
-    std::memcpy(buf.data() + mats_off, plan.mats.data(), plan.mats.size() * sizeof(C));
+    // 8x8 ops of pipelined passes in three-product form, appended
+    std::vector<C> mats = plan.mats;
+    for (const TilePass& p : plan.passes) {
+      if (!tile_pipelined(st->dt, p.g, p.op_count)) continue;
+      for (int o = p.op_begin; o < p.op_begin + p.op_count; ++o) {
+        TileOp& op = ops[o];
+        if (op.kind != TOP_DENSE3) continue;
+        const C* m = plan.mats.data() + op.moff;
+        std::vector<double> g(192);
+        for (int r = 0; r < 8; ++r)
+          for (int c = 0; c < 8; ++c) {
+            const C z = m[8 * r + c];
+            g[24 * r + c] = z.re;
+            g[24 * r + 8 + c] = z.re + z.im;
+            g[24 * r + 16 + c] = z.im - z.re;
+          }
+        op.kind = TOP_DENSE3G;
+        op.moff = (int64_t)mats.size();
+        for (int i = 0; i < 96; ++i) mats.push_back({g[2 * i], g[2 * i + 1]});
+      }
+    }
+    buf.resize(mats_off + mats.size() * sizeof(C));
+    std::memcpy(buf.data() + mats_off, mats.data(), mats.size() * sizeof(C));
   } else {
     std::vector<cplx<float>> m;
     convert(plan.mats, &m);
     buf.resize(mats_off + m.size() * sizeof(cplx<float>));
     std::memcpy(buf.data() + mats_off, m.data(), m.size() * sizeof(cplx<float>));
   }
-  std::memcpy(buf.data(), plan.ops.data(), ops_bytes);
+  std::memcpy(buf.data(), ops.data(), ops_bytes);
   char* dev = nullptr;
   juqcs_status rc = upload(st, buf.data(), buf.size(), &dev);
   if (rc != JUQCS_OK) return rc;

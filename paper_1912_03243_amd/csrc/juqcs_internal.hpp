@@ -103,6 +103,9 @@ enum TileOpKind : int32_t {
   TOP_DENSE4 = 4,  // 16x16 on local bits bits[0..4)
   TOP_PERM = 5,    // monomial on local bits bits[0..k), k <= 3: out[r] =
                    // c[r] in[sigma(r)], sigma(r) in bits 3r..3r+2 of a
+  TOP_DENSE3G = 6, // 8x8 on bits[0..3) in three-product form (FP64 pipelined
+                   // kernels only): per row r, 24 reals Re m_r., (Re + Im) m_r.,
+                   // (Im - Re) m_r.
 };
 
 struct TileOp {
@@ -145,6 +148,8 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales,
                        const TileGeom& g, const TileOp* d_ops, int nops,
                        const void* d_mats, hipStream_t s);
+// Whether launch_tile runs a pass on a pipelined (fixed tile size) kernel.
+bool tile_pipelined(juqcs_dtype dt, const TileGeom& g, int nops);
 int tile_max_bits(juqcs_dtype dt);
 // Expectation values of sigma^x,y,z for the tile bits jlo..b-1 of geometry
 // g (b <= expect_max_bits(), at most 16 bits per launch):

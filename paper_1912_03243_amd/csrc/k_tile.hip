@@ -516,6 +516,15 @@ int tile_max_bits(juqcs_dtype dt) {
   return dt == JUQCS_C128 ? TileCfg<double>::kMaxBits : TileCfg<float>::kMaxBits;
 }
 
+bool tile_pipelined(juqcs_dtype dt, const TileGeom& g, int nops) {
+  const int cap = tile_mat_cap(dt, g.b), mcap = tile_mma_cap(dt, g.b);  // 0: no limit
+  const bool sized = dt == JUQCS_C128   ? (g.b >= 11 && g.b <= 13)
+                     : dt == JUQCS_C64 ? (g.b >= 11 && g.b <= 14)
+                                       : (g.b == 12 || g.b == 13);
+  return sized && g.maxk <= 3 && nops <= kFixedOps && (cap == 0 || g.mat_count <= cap) &&
+         (mcap == 0 || g.mma_count <= mcap) && (dt != JUQCS_ENC2 || g.H <= kEnc2Gather);
+}
+
 int tile_mma_cap(juqcs_dtype dt, int b) {
   if (dt == JUQCS_C64) {
     if (b == 14) return FixedTabs<float, 14, 1024>::kCap;
@@ -547,10 +556,7 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
   hipLaunchKernelGGL((k_tile_fixed<T, TB, NT>), pgrid((const void*)k_tile_fixed<T, TB, NT>, NT), \
                      dim3(NT), 0, s, (cplx<T>*)amps, g, d_ops, nops, (const cplx<T>*)d_mats)
   // the pipelined kernels run ops of up to 3 qubits, with the coefficients in LDS
-  const int cap = tile_mat_cap(dt, g.b), mcap = tile_mma_cap(dt, g.b);  // 0: no limit
-  const bool fixed_ok = g.maxk <= 3 && nops <= kFixedOps && (cap == 0 || g.mat_count <= cap) &&
-                        (mcap == 0 || g.mma_count <= mcap) &&
-                        (dt != JUQCS_ENC2 || g.H <= kEnc2Gather);
+  const bool fixed_ok = tile_pipelined(dt, g, nops);
   if (dt == JUQCS_C128) {
     auto* p = (cplx<double>*)amps;
     auto* m = (const cplx<double>*)d_mats;
