@@ -16,6 +16,9 @@
 // panel in LDS with coalesced loads, each wave multiplies its 16 columns, the
 // results go back through LDS and are stored coalesced to the same places
 // (in place: every column belongs to exactly one workgroup).
+#include <map>
+#include <mutex>
+
 #include "juqcs_internal.hpp"
 
 namespace juqcs {
@@ -61,6 +64,9 @@ struct PrecTraits<P_BF16X3> {
 };
 
 // KD: K = 2^k amplitudes per column; R = padded real rows (multiple of 16).
+// Persistent: every workgroup loads the matrix once and then walks column
+// panels (gridDim.x apart), prefetching the next panel into registers while
+// the current one is multiplied.
 template <int P, int KD>
 __global__ __launch_bounds__(kThreads) void k_fused(
     cplx<typename PrecTraits<P>::T>* __restrict__ psi, uint64_t ncols, TileGeom tg,
@@ -69,9 +75,14 @@ __global__ __launch_bounds__(kThreads) void k_fused(
   constexpr int R0 = 2 * KD;
   constexpr int R = R0 < 16 ? 16 : R0;
   constexpr bool kALds = (R * R * sizeof(T)) <= 64 * 1024;
+  constexpr int PER = (KD * kCols + kThreads - 1) / kThreads;  // panel amplitudes per thread
+  // register prefetch only where it fits beside the accumulators
+  constexpr bool kPrefetch = PER * sizeof(cplx<T>) <= 8 * sizeof(cplx<double>);
+  constexpr int PV = kPrefetch ? PER : 1;
   __shared__ T sB[R * kCols];
   __shared__ T sA[kALds ? R * R : 1];
   __shared__ uint64_t off[KD];
+  __shared__ int hs[6];
 
   // tg.hbits[0..k) hold the targets in matrix order; tg.hbits[k..2k) sorted.
   const int k = tg.H;
@@ -80,6 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(
     for (int j = 0; j < k; ++j) o |= (uint64_t)((threadIdx.x >> j) & 1) << tg.hbits[j];
     off[threadIdx.x] = o;
   }
+  if (threadIdx.x < 6) hs[threadIdx.x] = (int)threadIdx.x < k ? tg.hbits[k + threadIdx.x] : 0;
   if (kALds) {
     for (int i = threadIdx.x; i < R * R; i += kThreads) sA[i] = At[i];
   }
@@ -93,21 +105,50 @@ __global__ __launch_bounds__(kThreads) void k_fused(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lhi = lane >> 4;
 
-  for (uint64_t cb = (uint64_t)blockIdx.x * kCols; cb < ncols; cb += (uint64_t)gridDim.x * kCols) {
-    // ---- load the 2K x 64 panel (coalesced over columns)
-    for (int e = threadIdx.x; e < KD * kCols; e += kThreads) {
+  // element e = r * kCols + col of a panel: amplitude r of column col
+  auto col_base = [&](uint64_t c) {
+    uint64_t base = c;
+    for (int j = 0; j < k; ++j) base = insert_zero(base, hs[j]);
+    return base;
+  };
+  cplx<T> v[PV];
+  auto fetch = [&](uint64_t cb) {
+#pragma unroll
+    for (int q = 0; q < PV; ++q) {
+      const int e = q * kThreads + threadIdx.x;
       const int col = e % kCols, r = e / kCols;
       const uint64_t c = cb + col;
-      cplx<T> v = {T(0), T(0)};
-      if (c < ncols) {
-        uint64_t base = c;
-        for (int j = 0; j < k; ++j) base = insert_zero(base, tg.hbits[k + j]);
-        v = ld_amp(&psi[base | off[r]]);
+      v[q] = cplx<T>{T(0), T(0)};
+      if (e < KD * kCols && c < ncols) v[q] = ld_amp(&psi[col_base(c) | off[r]]);
+    }
+  };
+  uint64_t cb = (uint64_t)blockIdx.x * kCols;
+  const uint64_t stride = (uint64_t)gridDim.x * kCols;
+  if (kPrefetch && cb < ncols) fetch(cb);
+  for (; cb < ncols; cb += stride) {
+    // ---- the 2K x 64 panel into LDS (prefetched, or loaded here)
+    if constexpr (kPrefetch) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = q * kThreads + threadIdx.x;
+        if (e < KD * kCols) {
+          const int col = e % kCols, r = e / kCols;
+          sB[(2 * r) * kCols + col] = v[q].re;
+          sB[(2 * r + 1) * kCols + col] = v[q].im;
+        }
       }
-      sB[(2 * r) * kCols + col] = v.re;
-      sB[(2 * r + 1) * kCols + col] = v.im;
+    } else {
+      for (int e = threadIdx.x; e < KD * kCols; e += kThreads) {
+        const int col = e % kCols, r = e / kCols;
+        const uint64_t c = cb + col;
+        cplx<T> w = {T(0), T(0)};
+        if (c < ncols) w = ld_amp(&psi[col_base(c) | off[r]]);
+        sB[(2 * r) * kCols + col] = w.re;
+        sB[(2 * r + 1) * kCols + col] = w.im;
+      }
     }
     __syncthreads();
+    if (kPrefetch && cb + stride < ncols) fetch(cb + stride);
 
     // ---- per wave: out(R x 16) = A(R x R) * B(R x 16)
     const int cw = wave * 16;
@@ -186,12 +227,10 @@ __global__ __launch_bounds__(kThreads) void k_fused(
       const int col = e % kCols, r = e / kCols;
       const uint64_t c = cb + col;
       if (c < ncols) {
-        uint64_t base = c;
-        for (int j = 0; j < k; ++j) base = insert_zero(base, tg.hbits[k + j]);
-        cplx<T> v;
-        v.re = sB[(2 * r) * kCols + col];
-        v.im = sB[(2 * r + 1) * kCols + col];
-        st_amp(&psi[base | off[r]], v);
+        cplx<T> w;
+        w.re = sB[(2 * r) * kCols + col];
+        w.im = sB[(2 * r + 1) * kCols + col];
+        st_amp(&psi[col_base(c) | off[r]], w);
       }
     }
     __syncthreads();
@@ -204,7 +243,32 @@ hipError_t dispatch_k(void* amps, int n, int k, const TileGeom& tg, const void* 
   using T = typename PrecTraits<P>::T;
   const uint64_t ncols = uint64_t(1) << (n - k);
   uint64_t g = (ncols + kCols - 1) / kCols;
-  if (g > (1u << 20)) g = 1u << 20;
+  // persistent grid: the resident workgroups of the kernel
+  static std::mutex mu;
+  static std::map<const void*, uint64_t> slots;
+  const void* kern = nullptr;
+  switch (k) {
+    case 1: kern = (const void*)k_fused<P, 2>; break;
+    case 2: kern = (const void*)k_fused<P, 4>; break;
+    case 3: kern = (const void*)k_fused<P, 8>; break;
+    case 4: kern = (const void*)k_fused<P, 16>; break;
+    case 5: kern = (const void*)k_fused<P, 32>; break;
+    case 6: kern = (const void*)k_fused<P, 64>; break;
+    default: return hipErrorInvalidValue;
+  }
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = slots.find(kern);
+    if (it == slots.end()) {
+      int dev = 0, cus = 256, per = 1;
+      if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, 0) != hipSuccess || per < 1)
+        per = 1;
+      it = slots.emplace(kern, (uint64_t)cus * per).first;
+    }
+    if (g > it->second) g = it->second;
+  }
   const dim3 grid((unsigned)g), block(kThreads);
   auto* p = (cplx<T>*)amps;
   const T* A = (const T*)d_mat;
