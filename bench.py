@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--low-bits", type=int, default=0, help="contiguous low tile bits (0 = default)")
     ap.add_argument("--pass-gates", type=int, default=0,
                     help="most gates per tile pass (0 = planner's cost model, -1 = no limit)")
+    ap.add_argument("--relabel", type=int, default=0,
+                    help="tile passes may move qubits onto the low bits (0 = planner's choice, -1 = off)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -159,7 +161,7 @@ def main():
         if mode == "tile":
             o = st.run(gates, mode=mode, profile=profile, fuse_k=args.tile_fuse,
                        tile_bits=args.tile_bits, low_bits=args.low_bits,
-                       pass_gates=args.pass_gates)
+                       pass_gates=args.pass_gates, relabel=args.relabel)
         else:
             o = st.run(gates, mode=mode, profile=profile, fuse_k=5)
         st.amplitudes_device(zd, outd)
@@ -226,7 +228,7 @@ def main():
                                "4096 amplitudes (seed 1002) and the norm per step",
                    "n": n, "gates": ngates, "bitstrings": int(z.size), "mode": args.mode,
                    "tile_fuse": args.tile_fuse, "tile_bits": args.tile_bits,
-                   "pass_gates": args.pass_gates,
+                   "pass_gates": args.pass_gates, "relabel": args.relabel,
                    "passes_per_step": passes // args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
@@ -410,7 +412,7 @@ def other_workload(args, juqcs, W, dev, stream):
             st.init(0)
             o = st.run(circ, mode="tile", profile=True, fuse_k=args.tile_fuse,
                        tile_bits=args.tile_bits, low_bits=args.low_bits,
-                       pass_gates=args.pass_gates)
+                       pass_gates=args.pass_gates, relabel=args.relabel)
             info["o"] = (o.passes, o.kernel_ms, o.bytes)
 
         ms = _timed(run, args.steps, args.warmup, stream)
@@ -420,7 +422,8 @@ def other_workload(args, juqcs, W, dev, stream):
         res.update({
             "value": len(circ) / (ms / 1e3), "ms_per_step": ms, "dtype": "f32",
             "config": {"workload": f"{args.workload}: n={n} {dtype}, 16 brick layers ({len(circ)} gates, "
-                                   "seed 3), tile passes", "n": n, "passes_per_step": passes},
+                                   "seed 3), tile passes", "n": n, "passes_per_step": passes,
+                       "relabel": args.relabel},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                          "bytes_per_launch": kb / passes, "avg_launch_ms": kms / passes},

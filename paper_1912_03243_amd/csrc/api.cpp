@@ -246,8 +246,11 @@ double tile_plan_ms(const TilePlan& p, juqcs_dtype dt, int n) {
 // pass_gates: > 0 caps the gates per pass, -1 lifts the cap, 0 is the
 // planner's choice: no cap for C128 (measured fastest: capped plans carry
 // more, less dense ops), for C64 and ENC2 the cap the cost model prefers.
+// relabel >= 0: C128 and C64 plans may move qubits onto the low physical
+// bits between passes (the layout st->phys follows); -1: the data stay
+// where they are (explicit layout moves rely on that).
 juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, int b,
-                        int64_t* passes, int kin = 0, int pass_gates = -1) {
+                        int64_t* passes, int kin = 0, int pass_gates = -1, int relabel = -1) {
   const int maxb = tile_max_bits(st->dt);
   if (b <= 0 || L <= 0) default_tile_bits(st->dt, st->B, &L, &b);
   if (b > maxb) return fail(JUQCS_ERR_ARG, "tile_bits above the LDS limit");
@@ -258,27 +261,35 @@ juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, 
   if (kin <= 0) kin = 3;
   if (kin > 4) return fail(JUQCS_ERR_ARG, "in-pass fusion width must be 1..4");
   if (pass_gates < -1) return fail(JUQCS_ERR_ARG, "pass_gates must be >= -1");
+  if (relabel < -1 || relabel > 1) return fail(JUQCS_ERR_ARG, "relabel must be -1, 0 or 1");
   const int cap = tile_mat_cap(st->dt, std::min(b, st->n));
   const int mcap = tile_mma_cap(st->dt, std::min(b, st->n));
   const int l = std::min(L, st->n);
+  const bool rl = relabel >= 0 && st->dt != JUQCS_ENC2;
   TilePlan plan;
+  std::vector<int> moved;  // moved[p]: physical bit that the qubit at bit p ends on
   if (pass_gates != 0 || st->dt == JUQCS_C128) {
-    plan_tiles(st->n, l, b, st->B, gates, &plan, kin, cap, std::max(pass_gates, 0), mcap);
+    plan_tiles(st->n, l, b, st->B, gates, &plan, kin, cap, std::max(pass_gates, 0), mcap, rl, &moved);
   } else {
     double best = 0.0;
     for (int take : {0, 90, 60, 40}) {
       if (take > 0 && (int64_t)gates.size() <= take) continue;  // same as no cap
       TilePlan cand;
-      plan_tiles(st->n, l, b, st->B, gates, &cand, kin, cap, take, mcap);
+      std::vector<int> mv;
+      plan_tiles(st->n, l, b, st->B, gates, &cand, kin, cap, take, mcap, rl, &mv);
       const double ms = tile_plan_ms(cand, st->dt, st->n);
       if (plan.passes.empty() || ms < best) {
         best = ms;
         plan = std::move(cand);
+        moved = std::move(mv);
       }
     }
   }
   if (passes) *passes = (int64_t)plan.passes.size();
-  return run_tile_plan(st, plan);
+  if (juqcs_status rc = run_tile_plan(st, plan)) return rc;
+  if (rl)
+    for (int q = 0; q < st->n; ++q) st->phys[q] = moved[st->phys[q]];
+  return JUQCS_OK;
 }
 
 // Gate on physical qubits.
@@ -653,7 +664,8 @@ juqcs_status run_planned(juqcs_state* st, const std::vector<Gate>& g, int mode,
   }
   if (mode == JUQCS_PLAN_TILE) {
     int64_t passes = 0;
-    juqcs_status rc = tile_gates(st, g, o->low_bits, o->tile_bits, &passes, o->fuse_k, o->pass_gates);
+    juqcs_status rc =
+        tile_gates(st, g, o->low_bits, o->tile_bits, &passes, o->fuse_k, o->pass_gates, o->relabel);
     o->passes = passes;
     return rc;
   }

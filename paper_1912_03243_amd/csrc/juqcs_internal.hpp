@@ -85,6 +85,7 @@ __host__ __device__ inline uint64_t insert_zero(uint64_t x, int pos) {
 constexpr int kMaxGather = 10;  // gathered chunk bits of a tile pass
 constexpr int kPassOps = 48;    // most ops the planner puts in one pass
 constexpr int kHbitsCap = 12;   // fused blocks reuse the struct: 2k <= 12
+constexpr int kSwapCap = 8;     // relabel swaps at the end of one pass
 
 struct TileGeom {
   int32_t n, L, H, b;
@@ -93,7 +94,28 @@ struct TileGeom {
   int32_t maxk;                  // widest op of the pass (1..4)
   int32_t mat_count;             // coefficients of the pass's ops, from ops[0].moff on
   int32_t mma_count;             // 8x8 (TOP_DENSE3) ops of the pass
+  // Relabeling (C128 / C64 only): after its ops the pass writes the tile
+  // back with local bits swap_a[i] and swap_b[i] exchanged (disjoint pairs),
+  // i.e. the qubits at those two physical positions trade places.
+  int32_t nswap;
+  int8_t swap_a[kSwapCap], swap_b[kSwapCap];
 };
+
+// Local index after the pass's relabel swaps (an involution: the swaps are
+// disjoint transpositions of bit positions).
+// The loop has a fixed trip count so that a kernel reads the pairs from its
+// argument block with constant offsets (no vector memory loads).
+__host__ __device__ inline int swap_local(int e, const TileGeom& g) {
+#pragma unroll
+  for (int i = 0; i < kSwapCap; ++i) {
+    if (i < g.nswap) {
+      const int a = g.swap_a[i], c = g.swap_b[i];
+      const int x = ((e >> a) ^ (e >> c)) & 1;
+      e ^= (x << a) | (x << c);
+    }
+  }
+  return e;
+}
 
 enum TileOpKind : int32_t {
   TOP_DENSE1 = 0,  // 2x2 on local bit a
@@ -248,22 +270,37 @@ struct TileSchedule {
   std::vector<TilePass> passes;
   std::vector<std::vector<int>> taken;
   int64_t gates = 0;
+  // Relabeling schedules only: the absorbed gates on the physical bits of
+  // their pass (taken indexes these), and final_pos[p] = where the qubit at
+  // physical bit p before the schedule sits after it.
+  std::vector<Gate> tgates;
+  std::vector<int> final_pos;
 };
 // max_take > 0 caps the gates one pass absorbs (later gates wait for the
 // next pass), which moves on-chip work from crowded passes to light ones.
 void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
                   TileSchedule* sched, int max_take = 0);
+// Same with relabeling: between passes, qubits of the finished tile may take
+// over the low L physical bits (swapped in by the finished pass's store), so
+// that the next tile is any b qubits of which at least L were in the
+// finished one.  Fills sched->tgates and sched->final_pos.
+void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
+                          TileSchedule* sched, int max_take = 0);
 // Fuses every pass's gates into ops of at most kin qubits.  A pass whose
 // coefficients would exceed max_mats (> 0), or whose 8x8 ops would exceed
-// max_mma (> 0), is split into consecutive passes of the same geometry.
+// max_mma (> 0), is split into consecutive passes of the same geometry (the
+// relabel swaps go with the last of them).  taken indexes sched.tgates when
+// that is non-empty, else gates; plan->op_gates index the same vector.
 void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, int kin,
                    TilePlan* plan, int max_mats = 0, int max_mma = 0);
 
 // Plans tile passes for gates (physical qubits).  L, b: low contiguous bits
 // and total tile bits; the low L bits are always tile bits.
+// relabel: plan with select_tiles_relabel; *final_pos (if given) receives
+// the schedule's final_pos (identity without relabeling).
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
                 TilePlan* plan, int kin = 2, int max_mats = 0, int max_take = 0,
-                int max_mma = 0);
+                int max_mma = 0, bool relabel = false, std::vector<int>* final_pos = nullptr);
 
 struct FusedBlock {
   std::vector<int> targets;           // physical

@@ -143,8 +143,11 @@ __global__ __launch_bounds__(kThreads) void k_tile(cplx<T>* __restrict__ psi, Ti
     }
     __syncthreads();
     Var<T, kThreads>::run(sh, b, ops, nops, mats);
+    // written back through the relabel swaps (see k_tile_fixed)
+    const int lt = lds<T>(swap_local((int)threadIdx.x, g));
     for (int e = threadIdx.x; e < tile_amps; e += kThreads)
-      st_stream(&gp[base + gs.choff[e >> L] + (e & lmask)], sp[lds<T>(e)]);
+      st_stream(&gp[base + gs.choff[e >> L] + (e & lmask)],
+                sp[lt ^ lds<T>(swap_local(e - (int)threadIdx.x, g))]);
     __syncthreads();
   }
 }
@@ -163,10 +166,19 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
   using F = Fixed<T, TB, NT>;
   constexpr int kCap = FixedTabs<T, TB, NT>::kCap;
   __shared__ typename F::Tab tabs[kCap > 0 ? kCap : 1];
+  // relabel swaps for the write-back: the pairs (a | c << 8) and, per k,
+  // the uniform part lds(swap(k NT)) of the LDS offsets
+  __shared__ int swp[kSwapCap];
+  __shared__ int swk[PER];
+  if (threadIdx.x < PER) swk[threadIdx.x] = lds<T>(swap_local((int)threadIdx.x * NT, g));
+  if (threadIdx.x < kSwapCap) {
+    const int i = threadIdx.x;
+    swp[i] = i < g.nswap ? (int)g.swap_a[i] | ((int)g.swap_b[i] << 8) : 0;
+  }
   F::build_pre(pre, ops, nops);
   if constexpr (kCap > 0) F::build_tabs(tabs, ops, nops, mats);
   load_geom<NT>(g, gs);  // synchronises
-  const int H = g.H, L = g.L, lmask = (1 << L) - 1;
+  const int H = g.H, L = g.L, lmask = (1 << L) - 1, nswap = g.nswap;
   const uint64_t ntiles = uint64_t(1) << (g.n - TB);
   // a native 2-vector keeps the prefetch buffer in registers (an array of
   // the cplx struct is demoted to scratch for FP64)
@@ -176,38 +188,62 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_tile_fixed(cplx<T>* _
   v2 v[PER];
   uint64_t tau, tau_end;
   tile_run(ntiles, &tau, &tau_end);
-  {
-    const uint64_t base = tile_base(tau, L, H, gs.hb);
+  // Loads of tile tau + 1 go out before the ops on tile tau and land in v;
+  // v is copied into LDS right after tile tau's stores have been issued, so
+  // those stores drain while the next tile is worked on.  (Copying at the
+  // top of the loop instead makes the compiler merge the first iteration's
+  // counters with the later ones and wait for every store in flight.)
+  // The thread's addresses are recomputed every tile from an opaque tid:
+  // hoisted out of the loop they would stay live across the ops and spill,
+  // and a spill reload also waits for every store in flight.
+  auto load = [&](uint64_t t, int tid) {
+    const uint64_t nb = tile_base(t, L, H, gs.hb);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int e = k * NT + threadIdx.x;
-      v[k] = ld_stream(&gp[base + gs.choff[e >> L] + (e & lmask)]);
+      const int e = k * NT + tid;
+      v[k] = ld_stream(&gp[nb + gs.choff[e >> L] + (e & lmask)]);
     }
+  };
+  auto fill = [&](int tid) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sp[lds<T>(k * NT + tid)] = v[k];
+  };
+  if (tau < tau_end) {
+    int tid = threadIdx.x;
+    load(tau, tid);
+    fill(tid);
+    __syncthreads();
+    // after the last tile the current one is read again (in bounds, unused)
+    load(tau + 1 < tau_end ? tau + 1 : tau, tid);
   }
   for (; tau < tau_end; ++tau) {
-#pragma unroll
-    for (int k = 0; k < PER; ++k) sp[lds<T>(k * NT + threadIdx.x)] = v[k];
-    __syncthreads();
-    // prefetch the next tile while this one is on chip; after the last tile
-    // the current one is read again (in bounds, values unused)
-    const uint64_t pf = tau + 1 < tau_end ? tau + 1 : tau;
-    {
-      const uint64_t nb = tile_base(pf, L, H, gs.hb);
-#pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int e = k * NT + threadIdx.x;
-        v[k] = ld_stream(&gp[nb + gs.choff[e >> L] + (e & lmask)]);
-      }
-    }
     if constexpr (kCap > 0) F::template run<F::D3_TAB>(sh, ops, nops, mats, pre, tabs);
     else F::template run<F::D3_VALU>(sh, ops, nops, mats, pre, nullptr);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const uint64_t base = tile_base(tau, L, H, gs.hb);
+    // The tile goes back to HBM through the pass's relabel swaps: destination
+    // local index e takes LDS element swap(e).  swap and lds are both linear
+    // over bit-XOR, so swap(k NT + t) splits into a per-thread part and the
+    // uniform per-k part swk[k], joined by one XOR (no swaps: the identity).
+    int t = tid;
+    for (int i = 0; i < nswap; ++i) {
+      const int pr = swp[i], a = pr & 255, c = pr >> 8;
+      const int x = ((t >> a) ^ (t >> c)) & 1;
+      t ^= (x << a) | (x << c);
+    }
+    const int lt = lds<T>(t);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int e = k * NT + threadIdx.x;
-      st_stream(&gp[base + gs.choff[e >> L] + (e & lmask)], sp[lds<T>(e)]);
+      const int e = k * NT + tid;
+      st_stream(&gp[base + gs.choff[e >> L] + (e & lmask)], sp[lt ^ swk[k]]);
     }
     __syncthreads();
+    if (tau + 1 < tau_end) {
+      fill(tid);
+      __syncthreads();
+      load(tau + 2 < tau_end ? tau + 2 : tau + 1, tid);
+    }
   }
 }
 
@@ -557,6 +593,9 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
                      dim3(NT), 0, s, (cplx<T>*)amps, g, d_ops, nops, (const cplx<T>*)d_mats)
   // the pipelined kernels run ops of up to 3 qubits, with the coefficients in LDS
   const bool fixed_ok = tile_pipelined(dt, g, nops);
+  if (g.nswap < 0 || g.nswap > kSwapCap || (g.nswap > 0 && dt == JUQCS_ENC2)) return hipErrorInvalidValue;
+  for (int i = 0; i < g.nswap; ++i)
+    if (g.swap_a[i] < 0 || g.swap_a[i] >= g.b || g.swap_b[i] < 0 || g.swap_b[i] >= g.b) return hipErrorInvalidValue;
   if (dt == JUQCS_C128) {
     auto* p = (cplx<double>*)amps;
     auto* m = (const cplx<double>*)d_mats;

@@ -389,6 +389,160 @@ void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& 
   }
 }
 
+namespace {
+
+// Greedy choice of a b-qubit tile for the front of rem.  Starts from the
+// qubits marked in `fixed` (kept), then adds the candidate that lets the
+// most gates through, one at a time; a qubit outside `near` may be added
+// only while fewer than `far_cap` such qubits were taken.
+std::vector<char> pick_tile(int n, int b, const std::vector<Gate>& gates, const std::vector<int>& rem,
+                            const std::vector<char>& fixed, const std::vector<char>& near, int far_cap) {
+  constexpr int kCandidates = 32;
+  std::vector<char> in_tile(fixed);
+  int count = 0, far = 0;
+  for (int q = 0; q < n; ++q) count += in_tile[q] ? 1 : 0;
+  std::vector<int> cand;
+  std::vector<char> seen(n, 0);
+  for (int gi : rem) {
+    const Gate& g = gates[gi];
+    for (int j = 0; j < g.nq; ++j) {
+      const int q = g.q[j];
+      if (!seen[q] && !in_tile[q]) {
+        seen[q] = 1;
+        cand.push_back(q);
+      }
+    }
+    if ((int)cand.size() >= kCandidates) break;
+  }
+  while (count < b) {
+    int best = -1, bc = -1;
+    for (int c : cand) {
+      if (in_tile[c] || (!near[c] && far >= far_cap)) continue;
+      in_tile[c] = 1;
+      const int v = absorb_count(gates, rem, in_tile, count + 1);
+      in_tile[c] = 0;
+      if (v > bc) {
+        bc = v;
+        best = c;
+      }
+    }
+    if (best < 0)  // candidates used up: any admissible qubit, nearby ones first
+      for (int round = 0; round < 2 && best < 0; ++round)
+        for (int q = n - 1; q >= 0; --q)
+          if (!in_tile[q] && (near[q] || (round == 1 && far < far_cap))) {
+            best = q;
+            break;
+          }
+    in_tile[best] = 1;
+    ++count;
+    if (!near[best]) ++far;
+  }
+  return in_tile;
+}
+
+}  // namespace
+
+void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
+                          TileSchedule* sched, int max_take) {
+  sched->final_pos.resize(n);
+  for (int q = 0; q < n; ++q) sched->final_pos[q] = q;
+  sched->tgates.clear();
+  if (n <= b) {
+    select_tiles(n, L, b, block_bits, gates, sched, max_take);
+    sched->tgates = gates;  // a single tile: nothing moves
+    return;
+  }
+  sched->passes.clear();
+  sched->taken.clear();
+  sched->gates = (int64_t)gates.size();
+  const int H = b - L;
+  // Qubits are named by their physical bit before the schedule ("wires");
+  // pos[w] is the wire's current physical bit, at[p] the wire at bit p.
+  std::vector<int> pos(n), at(n);
+  for (int q = 0; q < n; ++q) pos[q] = at[q] = q;
+  std::vector<int> rem(gates.size());
+  for (size_t i = 0; i < gates.size(); ++i) rem[i] = (int)i;
+  auto low_wires = [&]() {
+    std::vector<char> m(n, 0);
+    for (int p = 0; p < L; ++p) m[at[p]] = 1;
+    return m;
+  };
+  const std::vector<char> none(n, 0), all(n, 1);
+  std::vector<char> tile = pick_tile(n, b, gates, rem, low_wires(), all, n);
+  while (!rem.empty()) {
+    // absorb, in order, the gates whose qubits are all in the tile
+    std::vector<int> taken, keep;
+    std::vector<char> blocked(n, 0);
+    for (int gi : rem) {
+      const Gate& g = gates[gi];
+      bool ok = max_take <= 0 || (int)taken.size() < max_take;
+      for (int j = 0; j < g.nq; ++j)
+        if (!tile[g.q[j]] || blocked[g.q[j]]) ok = false;
+      if (ok) {
+        Gate t = g;
+        for (int j = 0; j < t.nq; ++j) t.q[j] = pos[t.q[j]];
+        taken.push_back((int)sched->tgates.size());
+        sched->tgates.push_back(t);
+      } else {
+        keep.push_back(gi);
+        for (int j = 0; j < g.nq; ++j) blocked[g.q[j]] = 1;
+      }
+    }
+    TilePass pass{};
+    pass.g.n = n;
+    pass.g.L = L;
+    pass.g.H = H;
+    pass.g.b = b;
+    pass.g.block_bits = block_bits;
+    pass.g.maxk = 1;
+    std::vector<int> hp;
+    for (int w = 0; w < n; ++w)
+      if (tile[w] && pos[w] >= L) hp.push_back(pos[w]);
+    std::sort(hp.begin(), hp.end());
+    for (int j = 0; j < H; ++j) pass.g.hbits[j] = hp[j];
+    rem.swap(keep);
+    if (!rem.empty()) {
+      // next tile: the low qubits kept, or any b qubits with at most H from
+      // outside this tile (its low L then come from this tile), whichever
+      // lets more gates through (ties keep the low qubits: no swaps)
+      std::vector<char> kept = pick_tile(n, b, gates, rem, low_wires(), all, n);
+      std::vector<char> moved = pick_tile(n, b, gates, rem, none, tile, H);
+      // new low wires if moving: those already low stay; the rest come from
+      // moved & tile
+      std::vector<char> nl(n, 0);
+      int cnt = 0;
+      for (int p = 0; p < L; ++p)
+        if (moved[at[p]]) nl[at[p]] = 1, ++cnt;
+      std::vector<int> in, out;
+      for (int w = 0; w < n && cnt < L; ++w)
+        if (moved[w] && tile[w] && !nl[w]) nl[w] = 1, ++cnt, in.push_back(w);
+      for (int p = 0; p < L; ++p)
+        if (!nl[at[p]]) out.push_back(at[p]);
+      if (cnt == L && in.size() == out.size() && (int)in.size() <= kSwapCap &&
+          absorb_count(gates, rem, moved, b) > absorb_count(gates, rem, kept, b)) {
+        // wire in[i] (gathered in this pass) trades places with out[i] (low)
+        for (size_t i = 0; i < in.size(); ++i) {
+          const int x = in[i], y = out[i], px = pos[x], py = pos[y];
+          const int lx = L + (int)(std::lower_bound(hp.begin(), hp.end(), px) - hp.begin());
+          pass.g.swap_a[pass.g.nswap] = (int8_t)py;
+          pass.g.swap_b[pass.g.nswap] = (int8_t)lx;
+          ++pass.g.nswap;
+          pos[x] = py;
+          pos[y] = px;
+          at[py] = x;
+          at[px] = y;
+        }
+        tile = moved;
+      } else {
+        tile = kept;
+      }
+    }
+    sched->passes.push_back(pass);
+    sched->taken.push_back(std::move(taken));
+  }
+  sched->final_pos = pos;
+}
+
 // Whether emit_ops makes a cluster an 8x8 (TOP_DENSE3) op.
 bool cluster_mma(const Cluster& c) {
   int sigma = 0;
@@ -412,9 +566,10 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
   plan->op_gates.clear();
   plan->gates = sched.gates;
   kin = std::max(1, std::min(kin, 4));  // on-chip fusion width
+  const std::vector<Gate>& src = sched.tgates.empty() ? gates : sched.tgates;
   for (size_t i = 0; i < sched.passes.size(); ++i) {
     std::vector<Cluster> cl;
-    fuse(gates, sched.taken[i], kin, &cl);
+    fuse(src, sched.taken[i], kin, &cl);
     // consecutive runs of clusters whose coefficients fit max_mats and whose
     // 8x8 ops fit max_mma
     size_t c0 = 0;
@@ -433,6 +588,7 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
       }
       const std::vector<Cluster> part(cl.begin() + c0, cl.begin() + c1);
       TilePass pass = sched.passes[i];
+      if (c1 < cl.size()) pass.g.nswap = 0;  // swaps after the pass's last ops
       pass.op_begin = (int32_t)plan->ops.size();
       const int64_t m0 = (int64_t)plan->mats.size();
       emit_ops(part, pass.g, plan);
@@ -448,10 +604,18 @@ void emit_schedule(const TileSchedule& sched, const std::vector<Gate>& gates, in
 }
 
 void plan_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
-                TilePlan* plan, int kin, int max_mats, int max_take, int max_mma) {
+                TilePlan* plan, int kin, int max_mats, int max_take, int max_mma, bool relabel,
+                std::vector<int>* final_pos) {
   TileSchedule sched;
-  select_tiles(n, L, b, block_bits, gates, &sched, max_take);
+  if (relabel) {
+    select_tiles_relabel(n, L, b, block_bits, gates, &sched, max_take);
+  } else {
+    select_tiles(n, L, b, block_bits, gates, &sched, max_take);
+    sched.final_pos.resize(n);
+    for (int q = 0; q < n; ++q) sched.final_pos[q] = q;
+  }
   emit_schedule(sched, gates, kin, plan, max_mats, max_mma);
+  if (final_pos) *final_pos = sched.final_pos;
 }
 
 void rebuild_mats(const std::vector<Gate>& gates, TilePlan* plan) {

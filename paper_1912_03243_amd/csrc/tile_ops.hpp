@@ -206,8 +206,25 @@ struct alignas(16) OpPre {
   int32_t src[8];   // monomial ops: offsets of the rows read for each written row
   int32_t grp[16];  // uniform part of the group offset of items k NT + tid
   int32_t pos;      // group-bit positions, ascending, 4 bits each
-  int32_t pad[3];
+  int32_t lsw;      // lane swaps (lane_swap): count in bits 0-2, then pairs of
+                    // thread-index bits (2 + 4 bits each) to exchange
+  int32_t pad[2];
 };
+
+// Thread index with the op's lane swaps applied.  An op's groups are handed
+// to threads through spread(lane_swap(tid)): the swaps move thread-index
+// bits so that the lanes of one LDS access phase (8 lanes for 16-byte, 16
+// for 8-byte amplitudes: 128 bytes) fall into distinct bank slots, which the
+// plain order misses when the op's targets sit among the low tile bits.
+__device__ __forceinline__ int lane_swap(int t, int lsw) {
+  const int n = lsw & 7;
+  for (int i = n - 1; i >= 0; --i) {  // last recorded swap first
+    const int a = (lsw >> (3 + 6 * i)) & 3, b = (lsw >> (5 + 6 * i)) & 15;
+    const int x = ((t >> a) ^ (t >> b)) & 1;
+    t ^= (x << a) | (x << b);
+  }
+  return t;
+}
 
 // ------------------------------------------------------- fixed tile size ---
 // Groups of an op are processed in register blocks of KB: all reads of a
@@ -270,7 +287,49 @@ struct Fixed {
         p.grp[k] = lds<T>(g) * CB;
       }
       p.pos = (np > 0 ? s0 : 0) | ((np > 1 ? s1 : 0) << 4) | ((np > 2 ? s2 : 0) << 8);
+      p.lsw = np > 0 ? lane_swaps(np, s0, s1, s2) : 0;
     }
+  }
+
+  // Lane swaps of an op with np targets at ascending positions s0 < s1 < s2:
+  // thread-index bit j goes to the j-th non-target tile position; for the W
+  // lane bits of an access phase, a bit whose bank slot (low W bits of its
+  // LDS slot) is spanned by the previous ones trades places with the first
+  // higher thread-index bit that adds a new slot direction.
+  __device__ static int lane_swaps(int np, int s0, int s1, int s2) {
+    constexpr int W = sizeof(T) == 8 ? 3 : 4;
+    constexpr int SLOTS = 1 << W;
+    int lt = 0;  // thread-index bits that index items
+    for (int items = (NA >> np) < NT ? (NA >> np) : NT; (1 << lt) < items;) ++lt;
+    // P: the non-target positions in order, 4 bits each (packed: no local
+    // array, which would go to scratch)
+    uint64_t P = 0;
+    int cnt = 0;
+    for (int b = 0; b < TB; ++b)
+      if (!(np > 0 && b == s0) && !(np > 1 && b == s1) && !(np > 2 && b == s2)) P |= (uint64_t)b << (4 * cnt++);
+    auto at = [&](int i) { return (int)((P >> (4 * i)) & 15); };
+    int span = 1;  // bit v set: slot direction v is in the span of the accepted lanes
+    int lsw = 0, n = 0;
+    for (int j = 0; j < W && j < lt; ++j) {
+      int pick = -1;
+      for (int jj = j; jj < lt && pick < 0; ++jj) {
+        const int v = lds<T>(1 << at(jj)) & (SLOTS - 1);
+        if (!((span >> v) & 1)) pick = jj;
+      }
+      if (pick < 0) continue;  // no independent direction left: a conflict stays
+      if (pick != j) {
+        const uint64_t x = (uint64_t)(at(j) ^ at(pick));
+        P ^= (x << (4 * j)) | (x << (4 * pick));
+        lsw |= (j | (pick << 2)) << (3 + 6 * n);
+        ++n;
+      }
+      const int v = lds<T>(1 << at(j)) & (SLOTS - 1);
+      int grown = span;
+      for (int u = 0; u < SLOTS; ++u)
+        if ((span >> u) & 1) grown |= 1 << (u ^ v);
+      span = grown;
+    }
+    return lsw | n;
   }
 
   __device__ static void dense1(cplx<T>* sh, const OpPre& q, const cplx<T>* __restrict__ m, int tid) {
@@ -279,7 +338,7 @@ struct Fixed {
     int pos[1];
     unpack<1>(q.pos, pos);
     const int ob = q.row[1];
-    const int lt = lds<T>(spread<1>(tid, pos)) * CB;
+    const int lt = lds<T>(spread<1>(lane_swap(tid, q.lsw), pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k0 = 0; k0 < CNT; k0 += KB) {
@@ -310,7 +369,7 @@ struct Fixed {
     int off[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) off[r] = q.row[r];
-    const int lt = lds<T>(spread<2>(tid, pos)) * CB;
+    const int lt = lds<T>(spread<2>(lane_swap(tid, q.lsw), pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k0 = 0; k0 < CNT; k0 += KB) {
@@ -364,7 +423,7 @@ struct Fixed {
     constexpr int KB = CNT < 2 || K == 3 ? 1 : 2;  // at most 8 amplitudes in flight
     int pos[K];
     unpack<K>(q.pos, pos);
-    const int lt = lds<T>(spread<K>(tid, pos)) * CB;
+    const int lt = lds<T>(spread<K>(lane_swap(tid, q.lsw), pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k0 = 0; k0 < CNT; k0 += KB) {
@@ -399,7 +458,7 @@ struct Fixed {
     int off[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) off[r] = q.row[r];
-    const int lt = lds<T>(spread<3>(tid, pos)) * CB;
+    const int lt = lds<T>(spread<3>(lane_swap(tid, q.lsw), pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k = 0; k < CNT; ++k) {
@@ -429,7 +488,7 @@ struct Fixed {
     int off[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) off[r] = q.row[r];
-    const int lt = lds<T>(spread<3>(tid, pos)) * CB;
+    const int lt = lds<T>(spread<3>(lane_swap(tid, q.lsw), pos)) * CB;
     char* base = reinterpret_cast<char*>(sh);
 #pragma unroll
     for (int k = 0; k < CNT; ++k) {

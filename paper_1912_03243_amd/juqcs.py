@@ -40,7 +40,8 @@ PLANS = {"plain": PLAN_PLAIN, "tile": PLAN_TILE, "fused": PLAN_FUSED, "auto": PL
 class PlanOpts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("fuse_k", ct.c_int32), ("mma", ct.c_int32),
                 ("tile_bits", ct.c_int32), ("low_bits", ct.c_int32), ("profile", ct.c_int32),
-                ("autotune", ct.c_int32), ("pass_gates", ct.c_int32), ("passes", ct.c_int64),
+                ("autotune", ct.c_int32), ("pass_gates", ct.c_int32), ("relabel", ct.c_int32),
+                ("passes", ct.c_int64),
                 ("gates", ct.c_int64),
                 ("kernel_ms", ct.c_double), ("bytes", ct.c_double)]
 
@@ -242,10 +243,11 @@ class State:
 
     def run(self, gates, mode: str = "auto", fuse_k: int = 0, mma: str = "auto",
             tile_bits: int = 0, low_bits: int = 0, profile: bool = False,
-            pass_gates: int = 0) -> PlanOpts:
+            pass_gates: int = 0, relabel: int = 0) -> PlanOpts:
         g = _gates(gates)
         o = PlanOpts(mode=PLANS[mode], fuse_k=fuse_k, mma=MMAS[mma], tile_bits=tile_bits,
-                     low_bits=low_bits, profile=int(profile), pass_gates=pass_gates)
+                     low_bits=low_bits, profile=int(profile), pass_gates=pass_gates,
+                     relabel=relabel)
         _check(_lib.juqcs_run_circuit(self.h, g.ctypes.data, g.size, ct.byref(o)),
                "juqcs_run_circuit")
         return o

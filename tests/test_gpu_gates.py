@@ -191,6 +191,85 @@ def test_tile_pass_gate_cap(J, dtype, pass_gates):
         assert_dtype(dtype, got, phi)
 
 
+# ---- relabeling: passes hand the low physical bits to other qubits ---------------
+RELABEL_CASES = [  # (n, tile_bits, low_bits, fuse_k): kernel exercised
+    (20, 0, 0, 0),    # default tile: pipelined 2^13 kernel
+    (18, 12, 5, 0),   # pipelined 2^12 kernel (two workgroups per CU)
+    (18, 11, 4, 0),   # pipelined 2^11 kernel
+    (16, 10, 3, 0),   # generic kernel (tile below the pipelined sizes)
+    (18, 12, 4, 4),   # generic kernel (16x16 ops)
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("case", RELABEL_CASES)
+def test_tile_relabel(J, dtype, case):
+    n, tb, lb, fk = case
+    circ = W.concat(W.layered_brick(n, 12, seed=60 + n), W.random_mixed(n, 80, seed=61 + n))
+    announce("tile-relabel", dtype, case)
+    z = np.arange(0, 1 << n, 997, dtype=np.uint64)
+    with J.State(n, dtype) as s:
+        s.init(3)
+        off = s.run(circ, mode="tile", tile_bits=tb, low_bits=lb, fuse_k=fk, relabel=-1)
+        assert s.layout() == list(range(n))
+        s.init(3)
+        on = s.run(circ, mode="tile", tile_bits=tb, low_bits=lb, fuse_k=fk, relabel=1)
+        layout = s.layout()
+        amps = s.amplitudes(z)            # read through the moved layout
+        ex = s.expectations()
+        got = s.state_vector()            # canonicalises
+        assert s.layout() == list(range(n))
+    phi = sv.run_circuit(n, circ, basis_index=3)
+    assert sorted(layout) == list(range(n))
+    assert layout != list(range(n)), "brick circuit on a partial tile: relabeling expected"
+    assert on.passes <= off.passes
+    assert_dtype(dtype, got, phi)
+    assert_dtype(dtype, amps, phi[z.astype(np.int64)])
+    tol = 1e-11 if dtype == "c128" else 2e-5
+    assert np.max(np.abs(ex - observables.q_expectations(phi, n))) < tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_tile_relabel_runs_chain(J, dtype):
+    # a run starts from the layout the previous one left, also after permute()
+    n = 19
+    a = W.layered_brick(n, 10, seed=71)
+    b = W.random_mixed(n, 150, seed=72)
+    c = W.layered_brick(n, 6, seed=73)
+    perm = np.random.default_rng(74).permutation(n)
+    announce("tile-relabel-chain", dtype)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        s.run(a, mode="tile", relabel=1)
+        s.run(b, mode="tile", relabel=1)
+        s.permute(perm)
+        s.run(c, mode="tile", relabel=1)
+        s.run(W.ghz(n)[:3], mode="plain")
+        got = s.state_vector()
+    phi = sv.run_circuit(n, W.concat(a, b, c, W.ghz(n)[:3]))
+    assert_dtype(dtype, got, phi)
+
+
+def test_tile_relabel_rejects_bad_value(J):
+    with J.State(8, "c128") as s:
+        with pytest.raises(J.JuqcsError) as e:
+            s.run(W.layered_brick(8, 2, seed=1), mode="tile", relabel=2)
+    assert e.value.status == J.ERR_ARG
+
+
+def test_tile_relabel_enc2_keeps_layout(J):
+    n = 16
+    circ = W.layered_brick(n, 8, seed=75)
+    announce("tile-relabel-enc2")
+    with J.State(n, "enc2") as s:
+        s.init(0)
+        o = s.run(circ, mode="tile", relabel=1)
+        assert s.layout() == list(range(n))
+        got = s.state_vector()
+    phi = sv.run_circuit(n, circ)
+    assert rel_l2(got, phi) < 0.02 * math.sqrt(o.passes + 1)
+
+
 def test_tile_pass_gate_cap_rejects_bad_value(J):
     with J.State(8, "c128") as s:
         with pytest.raises(J.JuqcsError) as e:
