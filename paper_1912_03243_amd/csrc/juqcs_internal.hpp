@@ -106,7 +106,6 @@ struct TileGeom {
 // The loop has a fixed trip count so that a kernel reads the pairs from its
 // argument block with constant offsets (no vector memory loads).
 __host__ __device__ inline int swap_local(int e, const TileGeom& g) {
-#pragma unroll
   for (int i = 0; i < kSwapCap; ++i) {
     if (i < g.nswap) {
       const int a = g.swap_a[i], c = g.swap_b[i];

@@ -21,44 +21,6 @@ inline C cadd(C a, C b) { return C{a.re + b.re, a.im + b.im}; }
 
 bool finite(C z) { return std::isfinite(z.re) && std::isfinite(z.im); }
 
-// Dense square matrix product out = a * b (dim x dim), row-major.
-void matmul(const C* a, const C* b, C* out, int dim) {
-  for (int i = 0; i < dim; ++i)
-    for (int j = 0; j < dim; ++j) {
-      C acc = cx(0, 0);
-      for (int k = 0; k < dim; ++k) acc = cmad(a[i * dim + k], b[k * dim + j], acc);
-      out[i * dim + j] = acc;
-    }
-}
-
-// Expand a gate given on qubits gq (size gk, matrix index sum_j b_{gq[j]} 2^j)
-// into the space of the qubit list space (size k): M[r][r'] =
-// G[sub(r)][sub(r')] if r and r' agree outside the gate's qubits.
-void expand(const C* g, const int* gq, int gk, const int* space, int k, C* out) {
-  int pos[6];
-  for (int j = 0; j < gk; ++j) {
-    pos[j] = -1;
-    for (int i = 0; i < k; ++i)
-      if (space[i] == gq[j]) pos[j] = i;
-  }
-  int gmask = 0;
-  for (int j = 0; j < gk; ++j) gmask |= 1 << pos[j];
-  const int dim = 1 << k, gd = 1 << gk;
-  for (int r = 0; r < dim; ++r)
-    for (int c = 0; c < dim; ++c) {
-      if ((r & ~gmask) != (c & ~gmask)) {
-        out[r * dim + c] = cx(0, 0);
-        continue;
-      }
-      int sr = 0, sc = 0;
-      for (int j = 0; j < gk; ++j) {
-        sr |= ((r >> pos[j]) & 1) << j;
-        sc |= ((c >> pos[j]) & 1) << j;
-      }
-      out[r * dim + c] = g[sr * gd + sc];
-    }
-}
-
 // One nonzero entry per row, in distinct columns: row r reads column
 // sigma(r), packed 3 bits per row (dim <= 8).
 bool monomial(const C* m, int dim, int* sigma) {
@@ -101,29 +63,58 @@ bool touches(const Cluster& c, const Gate& g) {
   return false;
 }
 
-// Union qubit list of a cluster and a gate, preserving the cluster's order.
-std::vector<int> union_q(const Cluster& c, const Gate& g) {
-  std::vector<int> u = c.q;
+// Qubits of a cluster and a gate together.
+int union_size(const Cluster& c, const Gate& g) {
+  int k = (int)c.q.size();
   for (int j = 0; j < g.nq; ++j)
-    if (std::find(u.begin(), u.end(), g.q[j]) == u.end()) u.push_back(g.q[j]);
-  return u;
+    if (std::find(c.q.begin(), c.q.end(), g.q[j]) == c.q.end()) ++k;
+  return k;
 }
 
-// Fold gate g into cluster c (g applied after c), re-expressed on the union.
+// Fold gate g into cluster c (g applied after c), re-expressed on the union
+// of their qubits (the cluster's order, then the gate's new qubits): the
+// cluster matrix is widened by identities on the new qubits, and g's rows
+// are combined over the index bits of its qubits, column by column.
 void merge_into(Cluster& c, const Gate& g) {
-  std::vector<int> u = union_q(c, g);
-  const int k = (int)u.size(), dim = 1 << k;
-  std::vector<C> old(dim * dim), gg(dim * dim), out(dim * dim);
-  if (c.q.empty()) {
-    for (int r = 0; r < dim; ++r)
-      for (int s = 0; s < dim; ++s) old[r * dim + s] = cx(r == s ? 1 : 0, 0);
-  } else {
-    expand(c.m.data(), c.q.data(), (int)c.q.size(), u.data(), k, old.data());
+  int u[8];
+  const int kold = (int)c.q.size();
+  int k = kold;
+  for (int i = 0; i < kold; ++i) u[i] = c.q[i];
+  for (int j = 0; j < g.nq; ++j)
+    if (std::find(u, u + k, g.q[j]) == u + k) u[k++] = g.q[j];
+  const int dim = 1 << k, dold = 1 << kold;
+  std::vector<C> a((size_t)dim * dim, cx(0, 0));
+  for (int r = 0; r < dim; ++r)
+    for (int cc = 0; cc < dim; ++cc)
+      if ((r >> kold) == (cc >> kold))
+        a[(size_t)r * dim + cc] = kold == 0 ? cx(r == cc ? 1 : 0, 0)
+                                            : c.m[(size_t)(r & (dold - 1)) * dold + (cc & (dold - 1))];
+  int pos[2] = {0, 0}, gmask = 0;
+  for (int j = 0; j < g.nq; ++j) {
+    pos[j] = (int)(std::find(u, u + k, g.q[j]) - u);
+    gmask |= 1 << pos[j];
   }
-  expand(g.m, g.q, g.nq, u.data(), k, gg.data());
-  matmul(gg.data(), old.data(), out.data(), dim);
-  c.q = u;
-  c.m = out;
+  const int gd = 1 << g.nq;
+  int off[4];
+  for (int t = 0; t < gd; ++t) {
+    off[t] = 0;
+    for (int j = 0; j < g.nq; ++j) off[t] |= ((t >> j) & 1) << pos[j];
+  }
+  std::vector<C> out(a);
+  for (int r0 = 0; r0 < dim; ++r0) {
+    if (r0 & gmask) continue;
+    for (int cc = 0; cc < dim; ++cc) {
+      C v[4];
+      for (int t = 0; t < gd; ++t) v[t] = a[(size_t)(r0 | off[t]) * dim + cc];
+      for (int t = 0; t < gd; ++t) {
+        C acc = cx(0, 0);
+        for (int t2 = 0; t2 < gd; ++t2) acc = cmad(g.m[t * gd + t2], v[t2], acc);
+        out[(size_t)(r0 | off[t]) * dim + cc] = acc;
+      }
+    }
+  }
+  c.q.assign(u, u + k);
+  c.m.swap(out);
 }
 
 // Greedy fusion: each gate joins the most recent cluster it may legally join
@@ -140,7 +131,7 @@ void fuse(const std::vector<Gate>& gates, const std::vector<int>& order, int kma
     int chosen = -1, fallback = -1;
     for (int i = (int)cl.size() - 1; i >= 0 && (int)cl.size() - 1 - i < kScan; --i) {
       const bool t = touches(cl[i], g);
-      const bool fits = (int)union_q(cl[i], g).size() <= kmax;
+      const bool fits = union_size(cl[i], g) <= kmax;
       if (t) {
         if (fits) chosen = i;
         break;
@@ -229,28 +220,40 @@ bool decode_gate(const juqcs_gate& g, int n, Gate* out, std::string* err) {
 // ---------------------------------------------------------------------------
 namespace {
 
-// Number of gates at the front of `rem` absorbable by the tile set.
-int absorb_count(const std::vector<Gate>& gates, const std::vector<int>& rem,
-                 const std::vector<char>& in_tile, int ntile) {
-  std::vector<char> blocked(in_tile.size(), 0);
-  int nblocked = 0, cnt = 0;
-  for (int gi : rem) {
-    const Gate& g = gates[gi];
-    bool ok = true;
-    for (int j = 0; j < g.nq; ++j)
-      if (!in_tile[g.q[j]] || blocked[g.q[j]]) ok = false;
-    if (ok) {
+// Qubit masks of the gates rem lists (n <= 40 qubits fit one word).
+std::vector<uint64_t> rem_masks(const std::vector<Gate>& gates, const std::vector<int>& rem) {
+  std::vector<uint64_t> m(rem.size());
+  for (size_t i = 0; i < rem.size(); ++i) {
+    const Gate& g = gates[rem[i]];
+    uint64_t x = 0;
+    for (int j = 0; j < g.nq; ++j) x |= uint64_t(1) << g.q[j];
+    m[i] = x;
+  }
+  return m;
+}
+
+// Number of gates at the front of the remaining list (as qubit masks)
+// absorbable by the tile: a gate is taken if its qubits are in the tile and
+// none of them is blocked by an earlier gate that was not taken.
+int absorb_count(const std::vector<uint64_t>& rm, uint64_t tile) {
+  uint64_t blocked = 0;
+  int cnt = 0;
+  for (uint64_t m : rm) {
+    if (!(m & ~tile) && !(m & blocked)) {
       ++cnt;
     } else {
-      for (int j = 0; j < g.nq; ++j)
-        if (!blocked[g.q[j]]) {
-          blocked[g.q[j]] = 1;
-          if (in_tile[g.q[j]]) ++nblocked;
-        }
-      if (nblocked >= ntile) break;
+      blocked |= m;
+      if (!(tile & ~blocked)) break;  // every tile qubit blocked
     }
   }
   return cnt;
+}
+
+uint64_t tile_mask(const std::vector<char>& in_tile) {
+  uint64_t t = 0;
+  for (size_t q = 0; q < in_tile.size(); ++q)
+    if (in_tile[q]) t |= uint64_t(1) << q;
+  return t;
 }
 
 void emit_ops(const std::vector<Cluster>& cl, const TileGeom& geom, TilePlan* plan) {
@@ -335,13 +338,13 @@ void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& 
         if ((int)cand.size() >= kCandidates) break;
       }
       // greedy: add the candidate that lets the most gates through
+      const std::vector<uint64_t> rm = rem_masks(gates, rem);
       for (int step = 0; step < H; ++step) {
         int best = -1, bc = -1;
+        const uint64_t base = tile_mask(in_tile);
         for (int c : cand) {
           if (in_tile[c]) continue;
-          in_tile[c] = 1;
-          const int v = absorb_count(gates, rem, in_tile, L + (int)chosen.size() + 1);
-          in_tile[c] = 0;
+          const int v = absorb_count(rm, base | (uint64_t(1) << c));
           if (v > bc) {
             bc = v;
             best = c;
@@ -414,13 +417,13 @@ std::vector<char> pick_tile(int n, int b, const std::vector<Gate>& gates, const 
     }
     if ((int)cand.size() >= kCandidates) break;
   }
+  const std::vector<uint64_t> rm = rem_masks(gates, rem);
   while (count < b) {
     int best = -1, bc = -1;
+    const uint64_t base = tile_mask(in_tile);
     for (int c : cand) {
       if (in_tile[c] || (!near[c] && far >= far_cap)) continue;
-      in_tile[c] = 1;
-      const int v = absorb_count(gates, rem, in_tile, count + 1);
-      in_tile[c] = 0;
+      const int v = absorb_count(rm, base | (uint64_t(1) << c));
       if (v > bc) {
         bc = v;
         best = c;
@@ -518,8 +521,9 @@ void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector
         if (moved[w] && tile[w] && !nl[w]) nl[w] = 1, ++cnt, in.push_back(w);
       for (int p = 0; p < L; ++p)
         if (!nl[at[p]]) out.push_back(at[p]);
+      const std::vector<uint64_t> rm = rem_masks(gates, rem);
       if (cnt == L && in.size() == out.size() && (int)in.size() <= kSwapCap &&
-          absorb_count(gates, rem, moved, b) > absorb_count(gates, rem, kept, b)) {
+          absorb_count(rm, tile_mask(moved)) > absorb_count(rm, tile_mask(kept))) {
         // wire in[i] (gathered in this pass) trades places with out[i] (low)
         for (size_t i = 0; i < in.size(); ++i) {
           const int x = in[i], y = out[i], px = pos[x], py = pos[y];
