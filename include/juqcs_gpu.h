@@ -179,7 +179,7 @@ typedef struct {
                           limit; 0 = the planner's choice (no limit for
                           C128; for C64 and ENC2 the limit its cost model
                           prefers, which spreads on-chip work over passes) */
-  int32_t relabel;     /* TILE, C128 and C64: 0 or 1 = a pass may hand the
+  int32_t relabel;     /* TILE: 0 or 1 = a pass may hand the
                           low (contiguous) physical bits to other qubits of
                           its tile as it writes the tile back (qubit
                           relabeling at no extra pass), so that the next
@@ -188,7 +188,7 @@ typedef struct {
                           by memory bandwidth).  The state is then left in
                           another physical layout: read-outs are in logical
                           terms, juqcs_get_layout shows it.  -1 = off
-                          (layout unchanged).  ENC2: ignored.             */
+                          (layout unchanged).                             */
   /* outputs */
   int64_t passes;      /* kernel passes over the state that were launched */
   int64_t gates;       /* gate records consumed                           */

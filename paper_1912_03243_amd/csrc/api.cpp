@@ -246,9 +246,9 @@ double tile_plan_ms(const TilePlan& p, juqcs_dtype dt, int n) {
 // pass_gates: > 0 caps the gates per pass, -1 lifts the cap, 0 is the
 // planner's choice: no cap for C128 (measured fastest: capped plans carry
 // more, less dense ops), for C64 and ENC2 the cap the cost model prefers.
-// relabel >= 0: C128 and C64 plans may move qubits onto the low physical
-// bits between passes (the layout st->phys follows); -1: the data stay
-// where they are (explicit layout moves rely on that).
+// relabel >= 0: plans may move qubits onto the low physical bits between
+// passes (the layout st->phys follows); -1: the data stay where they are
+// (explicit layout moves rely on that).
 juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, int b,
                         int64_t* passes, int kin = 0, int pass_gates = -1, int relabel = -1) {
   const int maxb = tile_max_bits(st->dt);
@@ -265,7 +265,7 @@ juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, 
   const int cap = tile_mat_cap(st->dt, std::min(b, st->n));
   const int mcap = tile_mma_cap(st->dt, std::min(b, st->n));
   const int l = std::min(L, st->n);
-  const bool rl = relabel >= 0 && st->dt != JUQCS_ENC2;
+  const bool rl = relabel >= 0;
   TilePlan plan;
   std::vector<int> moved;  // moved[p]: physical bit that the qubit at bit p ends on
   if (pass_gates != 0 || st->dt == JUQCS_C128) {

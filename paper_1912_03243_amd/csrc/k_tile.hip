@@ -261,11 +261,30 @@ __device__ inline void decode8(int4 raw, float d, cplx<float>* sh, int e) {
   }
 }
 
-__device__ inline int4 encode8(const cplx<float>* sh, int e, float r) {
+// Relabel swaps staged in LDS as pairs a | c << 8 (see k_tile_fixed).
+__device__ inline int swap_staged(int e, const int* swp, int nswap) {
+  for (int i = 0; i < nswap; ++i) {
+    const int pr = swp[i], a = pr & 255, c = pr >> 8;
+    const int x = ((e >> a) ^ (e >> c)) & 1;
+    e ^= (x << a) | (x << c);
+  }
+  return e;
+}
+
+// The 8 amplitudes of destination group e (e % 8 == 0) sit at LDS slots
+// lds(e + j) without relabeling, at ls ^ lsj[j] with it (ls = lds(swap(e)),
+// lsj[j] = lds(swap(j)): swap and lds are linear over bit-XOR).
+template <bool SW>
+__device__ inline int enc_slot(int e, int ls, const int* lsj, int j) {
+  return SW ? ls ^ lsj[j] : lds<float>(e + j);
+}
+
+template <bool SW>
+__device__ inline int4 encode8(const cplx<float>* sh, int e, int ls, const int* lsj, float r) {
   uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const cplx<float> v = sh[lds<float>(e + j)];
+    const cplx<float> v = sh[enc_slot<SW>(e, ls, lsj, j)];
     const float qr = fminf(fmaxf(rintf(v.re * r), -127.0f), 127.0f);
     const float qi = fminf(fmaxf(rintf(v.im * r), -127.0f), 127.0f);
     const uint32_t pr = ((uint32_t)(int)qr) & 0xffu, pi = ((uint32_t)(int)qi) & 0xffu;
@@ -274,36 +293,68 @@ __device__ inline int4 encode8(const cplx<float>* sh, int e, float r) {
   return make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
 }
 
-__device__ inline float max8(const cplx<float>* sh, int e) {
+template <bool SW>
+__device__ inline float max8(const cplx<float>* sh, int e, int ls, const int* lsj) {
   float mx = 0.0f;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const cplx<float> v = sh[lds<float>(e + j)];
+    const cplx<float> v = sh[enc_slot<SW>(e, ls, lsj, j)];
     mx = fmaxf(mx, fmaxf(fabsf(v.re), fabsf(v.im)));
   }
   return mx;
 }
 
 // Re-encode the tile: per-block maxima through LDS atomics (non-negative
-// floats order like their bit patterns), then codes and scales.
-template <int NT>
-__device__ inline void store_enc2(const cplx<float>* sh, uint32_t* bmax, int tile_amps, int B,
-                                  int L, int lmask, uint64_t base, const uint64_t* choff,
-                                  int8_t* codes, float* scales) {
+// floats order like their bit patterns), then codes and scales.  With
+// relabel swaps (SW), destination amplitude d is LDS element swap(d), and
+// the blocks are those of the destination order.
+template <int NT, bool SW>
+__device__ inline void store_enc2_t(const cplx<float>* sh, uint32_t* bmax, int tile_amps, int B,
+                                    int L, int lmask, uint64_t base, const uint64_t* choff,
+                                    int8_t* codes, float* scales, const int* swp, int nswap,
+                                    const int* lsj) {
   const int ngroups = tile_amps >> 3;
   for (int gq = threadIdx.x; gq < ngroups; gq += NT) {
     const int e = gq << 3;
-    atomicMax(&bmax[e >> B], __float_as_uint(max8(sh, e)));
+    const int ls = SW ? lds<float>(swap_staged(e, swp, nswap)) : 0;
+    atomicMax(&bmax[e >> B], __float_as_uint(max8<SW>(sh, e, ls, lsj)));
   }
   __syncthreads();
   for (int gq = threadIdx.x; gq < ngroups; gq += NT) {
     const int e = gq << 3;
+    const int ls = SW ? lds<float>(swap_staged(e, swp, nswap)) : 0;
     const uint64_t gi = base + choff[e >> L] + (e & lmask);
     const float s = __uint_as_float(bmax[e >> B]);
     const bool zero = !(s >= kTiny);
-    const int4 w = zero ? make_int4(0, 0, 0, 0) : encode8(sh, e, 127.0f / s);
+    const int4 w = zero ? make_int4(0, 0, 0, 0) : encode8<SW>(sh, e, ls, lsj, 127.0f / s);
     st_stream(reinterpret_cast<v4i*>(codes + 2 * gi), v4i{w.x, w.y, w.z, w.w});
     if ((e & ((1 << B) - 1)) == 0) st_stream(&scales[gi >> B], zero ? 0.0f : s);
+  }
+}
+
+template <int NT>
+__device__ inline void store_enc2(const cplx<float>* sh, uint32_t* bmax, int tile_amps, int B,
+                                  int L, int lmask, uint64_t base, const uint64_t* choff,
+                                  int8_t* codes, float* scales, const int* swp, int nswap,
+                                  const int* lsj) {
+  if (nswap > 0)
+    store_enc2_t<NT, true>(sh, bmax, tile_amps, B, L, lmask, base, choff, codes, scales, swp, nswap, lsj);
+  else
+    store_enc2_t<NT, false>(sh, bmax, tile_amps, B, L, lmask, base, choff, codes, scales, swp, nswap, lsj);
+}
+
+// Stages a pass's relabel swaps in LDS for the two-byte store: the pairs,
+// and lds(swap(j)) for the 8 amplitudes j of a group (the caller
+// synchronises).
+template <int NT>
+__device__ inline void stage_swaps(const TileGeom& g, int* swp, int* lsj) {
+  if (threadIdx.x < kSwapCap) {
+    const int i = threadIdx.x;
+    swp[i] = i < g.nswap ? (int)g.swap_a[i] | ((int)g.swap_b[i] << 8) : 0;
+  }
+  if (threadIdx.x >= 32 && threadIdx.x < 40) {
+    const int j = threadIdx.x - 32;
+    lsj[j] = lds<float>(swap_local(j, g));
   }
 }
 
@@ -315,7 +366,9 @@ __global__ __launch_bounds__(kThreads) void k_tile_enc2(int8_t* __restrict__ cod
   __shared__ cplx<float> sh[1 << MAXB];
   __shared__ GeomLds gs;
   __shared__ uint32_t bmax[1 << (MAXB - 3)];
-  load_geom<kThreads>(g, gs);
+  __shared__ int swp[kSwapCap], lsj[8];
+  stage_swaps<kThreads>(g, swp, lsj);
+  load_geom<kThreads>(g, gs);  // synchronises
   const int b = g.b, B = g.block_bits, L = g.L, lmask = (1 << L) - 1;
   const int tile_amps = 1 << b, ngroups = tile_amps >> 3, nblk = tile_amps >> B;
   const uint64_t ntiles = uint64_t(1) << (g.n - b);
@@ -330,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_enc2(int8_t* __restrict__ cod
     }
     __syncthreads();
     Var<float, kThreads>::run(sh, b, ops, nops, mats);
-    store_enc2<kThreads>(sh, bmax, tile_amps, B, L, lmask, base, gs.choff, codes, scales);
+    store_enc2<kThreads>(sh, bmax, tile_amps, B, L, lmask, base, gs.choff, codes, scales, swp, g.nswap, lsj);
     __syncthreads();
   }
 }
@@ -347,11 +400,13 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
   __shared__ uint32_t bmax[NA / 8];
   __shared__ OpPre pre[kFixedOps];
   __shared__ cplx<float> smat[Enc2Mats<TB>::kSlots];
+  __shared__ int swp[kSwapCap], lsj[8];
   using F = Fixed<float, TB, kFixedThreads>;
+  stage_swaps<kFixedThreads>(g, swp, lsj);
   stage_mats<float, kFixedThreads>(smat, mats + (nops > 0 ? ops[0].moff : 0), g.mat_count);
   F::build_pre(pre, ops, nops);
   load_geom<kFixedThreads>(g, gs);  // synchronises
-  const int H = g.H, L = g.L, B = g.block_bits, lmask = (1 << L) - 1;
+  const int H = g.H, L = g.L, B = g.block_bits, lmask = (1 << L) - 1, nswap = g.nswap;
   const int nblk = NA >> B;
   const uint64_t ntiles = uint64_t(1) << (g.n - TB);
   int4 raw[PER];
@@ -382,7 +437,7 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
     fetch(tau + 1 < tau_end ? tau + 1 : tau);
     F::template run<F::D3_STAGED>(sh, ops, nops, mats, pre, smat);
     store_enc2<kFixedThreads>(sh, bmax, NA, B, L, lmask, tile_base(tau, L, H, gs.hb), gs.choff,
-                              codes, scales);
+                              codes, scales, swp, nswap, lsj);
     __syncthreads();
   }
 }
@@ -593,7 +648,7 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
                      dim3(NT), 0, s, (cplx<T>*)amps, g, d_ops, nops, (const cplx<T>*)d_mats)
   // the pipelined kernels run ops of up to 3 qubits, with the coefficients in LDS
   const bool fixed_ok = tile_pipelined(dt, g, nops);
-  if (g.nswap < 0 || g.nswap > kSwapCap || (g.nswap > 0 && dt == JUQCS_ENC2)) return hipErrorInvalidValue;
+  if (g.nswap < 0 || g.nswap > kSwapCap) return hipErrorInvalidValue;
   for (int i = 0; i < g.nswap; ++i)
     if (g.swap_a[i] < 0 || g.swap_a[i] >= g.b || g.swap_b[i] < 0 || g.swap_b[i] >= g.b) return hipErrorInvalidValue;
   if (dt == JUQCS_C128) {

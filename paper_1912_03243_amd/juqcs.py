@@ -290,9 +290,12 @@ class State:
         return list(p)
 
     def state_vector(self) -> np.ndarray:
-        """Whole state in logical order as complex128 (host copy)."""
+        """Whole state in logical order as complex128 (host copy).  The data
+        are read where they are (a qubit layout left by relabeling or
+        permute() is undone on the host), so reading never changes the
+        state (moving two-byte data would re-encode it)."""
         import torch
-        self.canonicalize()
+        layout = self.layout()
         if self.dtype == C128:
             t = self.amps[: (1 << self.n) * 16].view(torch.float64)
         elif self.dtype == C64:
@@ -303,7 +306,15 @@ class State:
                           self.stream)
         torch.cuda.synchronize()
         a = t.cpu().numpy().astype(np.float64)
-        return a[0::2] + 1j * a[1::2]
+        phys = a[0::2] + 1j * a[1::2]
+        if layout == list(range(self.n)):
+            return phys
+        # logical index x sits at physical index sum_q bit_q(x) << layout[q]
+        x = np.arange(1 << self.n, dtype=np.int64)
+        p = np.zeros_like(x)
+        for q, pq in enumerate(layout):
+            p |= ((x >> q) & 1) << pq
+        return phys[p]
 
     def raw_codes(self):
         """(codes int8 (2^n, 2), scales float32) of an ENC2 state (host copies)."""

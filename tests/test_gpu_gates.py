@@ -217,9 +217,13 @@ def test_tile_relabel(J, dtype, case):
         layout = s.layout()
         amps = s.amplitudes(z)            # read through the moved layout
         ex = s.expectations()
-        got = s.state_vector()            # canonicalises
+        got = s.state_vector()            # read through the layout
+        assert s.layout() == layout
+        s.canonicalize()
         assert s.layout() == list(range(n))
+        got2 = s.state_vector()
     phi = sv.run_circuit(n, circ, basis_index=3)
+    assert_dtype(dtype, got2, phi)
     assert sorted(layout) == list(range(n))
     assert layout != list(range(n)), "brick circuit on a partial tile: relabeling expected"
     assert on.passes <= off.passes
@@ -257,17 +261,31 @@ def test_tile_relabel_rejects_bad_value(J):
     assert e.value.status == J.ERR_ARG
 
 
-def test_tile_relabel_enc2_keeps_layout(J):
-    n = 16
-    circ = W.layered_brick(n, 8, seed=75)
-    announce("tile-relabel-enc2")
+@pytest.mark.parametrize("case", [(20, 0, 0), (18, 12, 8)])
+def test_tile_relabel_enc2(J, case):
+    # two-byte tiles re-encode their blocks in the relabeled order
+    n, tb, lb = case
+    circ = W.concat(W.layered_brick(n, 10, seed=75 + n), W.random_mixed(n, 60, seed=76 + n))
+    announce("tile-relabel-enc2", case)
+    z = np.arange(0, 1 << n, 1001, dtype=np.uint64)
     with J.State(n, "enc2") as s:
         s.init(0)
-        o = s.run(circ, mode="tile", relabel=1)
+        off = s.run(circ, mode="tile", tile_bits=tb, low_bits=lb, relabel=-1)
         assert s.layout() == list(range(n))
+        ref = s.state_vector()
+        s.init(0)
+        on = s.run(circ, mode="tile", tile_bits=tb, low_bits=lb, relabel=1)
+        layout = s.layout()
+        amps = s.amplitudes(z)
+        ex = s.expectations()
         got = s.state_vector()
     phi = sv.run_circuit(n, circ)
-    assert rel_l2(got, phi) < 0.02 * math.sqrt(o.passes + 1)
+    assert layout != list(range(n))
+    assert on.passes <= off.passes
+    tol = 0.02 * math.sqrt(on.passes + 1)
+    assert rel_l2(got, phi) < tol and rel_l2(ref, phi) < 0.02 * math.sqrt(off.passes + 1)
+    assert rel_l2(amps, phi[z.astype(np.int64)]) < 3 * tol
+    assert np.max(np.abs(ex - observables.q_expectations(phi, n))) < 3 * tol
 
 
 def test_tile_pass_gate_cap_rejects_bad_value(J):
@@ -338,8 +356,14 @@ def test_permute_and_canonicalize(J, dtype):
         z = np.arange(0, 1 << n, 7, dtype=np.uint64)
         amps = s.amplitudes(z)
         got = s.state_vector()
+        s.canonicalize()
         assert s.layout() == list(range(n))
+        got2 = s.state_vector()
     phi = sv.run_circuit(n, W.concat(a, b))
+    if dtype == "enc2":
+        assert rel_l2(got2, phi) < 0.1
+    else:
+        assert_dtype(dtype, got2, phi)
     if dtype == "enc2":
         assert rel_l2(got, phi) < 0.1
     else:
