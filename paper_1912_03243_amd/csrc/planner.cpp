@@ -445,6 +445,30 @@ std::vector<char> pick_tile(int n, int b, const std::vector<Gate>& gates, const 
 
 }  // namespace
 
+namespace {
+
+// Rank of the bank-slot directions the first w lanes of the write-back of a
+// relabeling pass reach (local element swap(e) is read for destination e;
+// the kernels' LDS slot map folds bits s.. and 2s.. onto the low s bits:
+// s = 4 for 16-byte and 5 for 8-byte amplitudes; an access phase covers
+// 2^w lanes, w = 3 and 4).  Full rank: no bank conflicts.
+int writeback_slot_rank(const TileGeom& g, int s, int w) {
+  int span = 1, rank = 0;
+  for (int j = 0; j < w; ++j) {
+    const int e = swap_local(1 << j, g);
+    const int v = (e ^ (((e >> s) ^ (e >> (2 * s))) & ((1 << s) - 1))) & ((1 << w) - 1);
+    if ((span >> v) & 1) continue;
+    ++rank;
+    int grown = span;
+    for (int u = 0; u < (1 << w); ++u)
+      if ((span >> u) & 1) grown |= 1 << (u ^ v);
+    span = grown;
+  }
+  return rank;
+}
+
+}  // namespace
+
 void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector<Gate>& gates,
                           TileSchedule* sched, int max_take) {
   sched->final_pos.resize(n);
@@ -524,7 +548,31 @@ void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector
       const std::vector<uint64_t> rm = rem_masks(gates, rem);
       if (cnt == L && in.size() == out.size() && (int)in.size() <= kSwapCap &&
           absorb_count(rm, tile_mask(moved)) > absorb_count(rm, tile_mask(kept))) {
-        // wire in[i] (gathered in this pass) trades places with out[i] (low)
+        // wire in[i] (gathered in this pass) trades places with out[i] (low);
+        // the pairing is free, pick the one whose write-back keeps the LDS
+        // lanes of an access phase in distinct bank slots
+        std::vector<int> lin(in.size());
+        for (size_t i = 0; i < in.size(); ++i)
+          lin[i] = L + (int)(std::lower_bound(hp.begin(), hp.end(), pos[in[i]]) - hp.begin());
+        std::vector<int> perm(out.size()), best_perm;
+        for (size_t i = 0; i < out.size(); ++i) perm[i] = (int)i;
+        int best_score = -1;
+        do {
+          TileGeom t{};
+          t.nswap = (int)in.size();
+          for (size_t i = 0; i < in.size(); ++i) {
+            t.swap_a[i] = (int8_t)pos[out[perm[i]]];
+            t.swap_b[i] = (int8_t)lin[i];
+          }
+          const int score = 8 * writeback_slot_rank(t, 4, 3) + writeback_slot_rank(t, 5, 4);
+          if (score > best_score) {
+            best_score = score;
+            best_perm = perm;
+          }
+        } while (std::next_permutation(perm.begin(), perm.end()));
+        std::vector<int> out2(out.size());
+        for (size_t i = 0; i < out.size(); ++i) out2[i] = out[best_perm[i]];
+        out.swap(out2);
         for (size_t i = 0; i < in.size(); ++i) {
           const int x = in[i], y = out[i], px = pos[x], py = pos[y];
           const int lx = L + (int)(std::lower_bound(hp.begin(), hp.end(), px) - hp.begin());
