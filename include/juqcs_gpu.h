@@ -228,8 +228,11 @@ juqcs_status juqcs_norm(juqcs_state* st, double* out);
 juqcs_status juqcs_scale(juqcs_state* st, double factor);
 
 /* Single-qubit expectation values <Q_alpha(i)> = (1 - <sigma^alpha_i>)/2
- * for every qubit (Section 3), alpha = x, y, z: out[3*i + a], FP64, one
- * read pass.  Synchronises.  Errors: ARG, HIP. */
+ * for every qubit (Section 3), alpha = x, y, z: out[3*i + a], FP64 sums in
+ * a fixed order.  Read-only passes over the state: the pair sums of up to
+ * 13 bits come from one LDS-resident tile, so n qubits take
+ * 1 + ceil((n - 13) / 8) passes for C128 (one for n <= 13).  Synchronises.
+ * Errors: ARG, HIP. */
 juqcs_status juqcs_expectations(juqcs_state* st, double* out);
 
 /* ------------------------------------------------------------------------
