@@ -333,7 +333,7 @@ def other_workload(args, juqcs, W, dev, stream):
         t_gen = time.perf_counter() - t0
         s = torch.cuda.Stream(dev)
         t0 = time.perf_counter()
-        b = juqcs.Batch(inst, device=dev, autotune=bool(args.autotune))
+        b = juqcs.Batch(inst, device=dev, autotune=bool(args.autotune), relabel=args.relabel)
         t_plan = time.perf_counter() - t0
         st = b.stats()
         log(f"batch: {len(inst)} circuits, {st}, generation {t_gen:.1f}s, planning {t_plan:.1f}s")
@@ -359,7 +359,7 @@ def other_workload(args, juqcs, W, dev, stream):
                        "circuits": len(inst), "gates": gates, "tile_tasks": st["tasks"],
                        "tile_passes": st["passes"],
                        "fusion_width_counts": {int(k): int((kin == k).sum()) for k in set(kin.tolist())},
-                       "autotune": bool(args.autotune)},
+                       "autotune": bool(args.autotune), "relabel": args.relabel},
             "amp_updates_per_s": amp_updates / (ms / 1e3),
             "planning_s": t_plan,
             "check": {"max_abs_norm_minus_1": float(np.max(np.abs(norms - 1.0)))},

@@ -306,8 +306,16 @@ juqcs_status juqcs_batch_stats(const juqcs_batch* b, int64_t* tasks,
 /* Fusion width chosen for every circuit (count ints). */
 juqcs_status juqcs_batch_fusion(const juqcs_batch* b, int* kin);
 
+/* Physical bit of every qubit of circuit c after a run: phys[q] for q <
+ * n[c] (host array).  The tile passes relabel qubits as they write tiles
+ * back (opts->relabel of juqcs_batch_create: 0 or 1 on, -1 off); the state
+ * buffer holds amplitude z at index sum_q bit_q(z) << phys[q], and
+ * juqcs_batch_amplitudes maps through it.  Errors: ARG. */
+juqcs_status juqcs_batch_layout(const juqcs_batch* b, int c, int* phys);
+
 /* out[2*(c*m+k)], out[2*(c*m+k)+1] = amplitude idx[c*m+k] of circuit c
- * (host arrays, FP64 pairs; an index >= 2^n gives NaN).  Synchronises. */
+ * (logical index; host arrays, FP64 pairs; an index >= 2^n gives NaN).
+ * Synchronises. */
 juqcs_status juqcs_batch_amplitudes(juqcs_batch* b, const uint64_t* idx, int m,
                                     double* out, void* hip_stream);
 

@@ -56,9 +56,17 @@ double plan_cost(const TilePlan& p) {
   return c;
 }
 
-void schedule_circuit(int n, const std::vector<Gate>& g, TileSchedule* sched) {
+// Tile passes of one circuit; with relabel the passes may move qubits onto
+// the low bits (sched->final_pos: where each qubit ends).
+void schedule_circuit(int n, const std::vector<Gate>& g, TileSchedule* sched, bool relabel) {
   const int b = tile_bits_for(n);
-  select_tiles(n, low_bits_for(n), b, 0, g, sched);
+  if (relabel) {
+    select_tiles_relabel(n, low_bits_for(n), b, 0, g, sched);
+  } else {
+    select_tiles(n, low_bits_for(n), b, 0, g, sched);
+    sched->final_pos.resize(n);
+    for (int q = 0; q < n; ++q) sched->final_pos[q] = q;
+  }
   if (sched->passes.empty()) {  // no gates: one pass that writes |0...0>
     TilePass p{};
     p.g.n = n;
@@ -71,10 +79,12 @@ void schedule_circuit(int n, const std::vector<Gate>& g, TileSchedule* sched) {
   }
 }
 
-void plan_circuit(int n, const std::vector<Gate>& g, int kin, TilePlan* plan) {
+void plan_circuit(int n, const std::vector<Gate>& g, int kin, bool relabel, TilePlan* plan,
+                  TileSchedule* sched_out = nullptr) {
   TileSchedule sched;
-  schedule_circuit(n, g, &sched);
+  schedule_circuit(n, g, &sched, relabel);
   emit_schedule(sched, g, kin, plan, 0, batch_mma_cap());
+  if (sched_out) *sched_out = std::move(sched);
 }
 
 // Runs f(i) for i in [0, count) on the host's cores.
@@ -108,6 +118,8 @@ struct juqcs_batch {
   int32_t* d_nq = nullptr;
   int64_t tasks = 0, gate_apps = 0, passes = 0;
   std::vector<int> kin;  // chosen on-chip fusion width per circuit
+  std::vector<int8_t> pos;  // kMaxBatchQubits per circuit: physical bit of each qubit at the end
+  int8_t* d_pos = nullptr;
   hipStream_t last_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -126,6 +138,19 @@ void free_batch(juqcs_batch* b) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kMaxBatchQubits = 32;  // layout entries per circuit
+
+// Layout entries of circuit c from a schedule's final positions.
+void set_layout(juqcs_batch* B, int c, const std::vector<int>& final_pos) {
+  if (B->pos.size() != (size_t)B->count * kMaxBatchQubits) {
+    B->pos.assign((size_t)B->count * kMaxBatchQubits, 0);
+    for (int i = 0; i < B->count; ++i)
+      for (int q = 0; q < kMaxBatchQubits; ++q) B->pos[(size_t)i * kMaxBatchQubits + q] = (int8_t)q;
+  }
+  for (size_t q = 0; q < final_pos.size(); ++q)
+    B->pos[(size_t)c * kMaxBatchQubits + q] = (int8_t)final_pos[q];
+}
 
 // Lays the plans out as one device work list (pass-major groups).
 juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
@@ -202,7 +227,9 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
   const size_t o_tickets = align256(o_mats + std::max<size_t>(mats.size(), 1) * sizeof(cplx<float>));
   const size_t o_soff = align256(o_tickets + std::max(d.nrounds, 1) * sizeof(uint64_t));
   const size_t o_nq = align256(o_soff + B->count * sizeof(uint64_t));
-  const size_t total = align256(o_nq + B->count * sizeof(int32_t));
+  const size_t o_pos = align256(o_nq + B->count * sizeof(int32_t));
+  const size_t total = align256(o_pos + (size_t)B->count * kMaxBatchQubits);
+  if (B->pos.size() != (size_t)B->count * kMaxBatchQubits) set_layout(B, 0, {});
   std::vector<char> host(total, 0);
   std::memcpy(host.data() + o_groups, groups.data(), groups.size() * sizeof(BatchGroup));
   std::memcpy(host.data() + o_passes, passes.data(), passes.size() * sizeof(BatchPass));
@@ -210,6 +237,7 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
   std::memcpy(host.data() + o_mats, mats.data(), mats.size() * sizeof(cplx<float>));
   std::memcpy(host.data() + o_soff, B->state_off.data(), B->count * sizeof(uint64_t));
   std::memcpy(host.data() + o_nq, B->n.data(), B->count * sizeof(int32_t));
+  std::memcpy(host.data() + o_pos, B->pos.data(), B->pos.size());
   hipError_t e = hipMalloc((void**)&B->dbuf, total);
   if (e != hipSuccess) return hip_fail(e, "batch hipMalloc");
   e = hipMemcpy(B->dbuf, host.data(), total, hipMemcpyHostToDevice);
@@ -224,6 +252,7 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
   d.nchunks = next;
   B->d_state_off = (uint64_t*)(B->dbuf + o_soff);
   B->d_nq = (int32_t*)(B->dbuf + o_nq);
+  B->d_pos = (int8_t*)(B->dbuf + o_pos);
   return JUQCS_OK;
 }
 
@@ -282,6 +311,8 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
   if (offsets[count] > 0 && !gates) return fail(JUQCS_ERR_ARG, "null gate array");
   const int fuse = opts ? opts->fuse_k : 0;
   const bool autotune = opts && opts->autotune;
+  const bool relabel = !opts || opts->relabel >= 0;
+  if (opts && (opts->relabel < -1 || opts->relabel > 1)) return fail(JUQCS_ERR_ARG, "relabel must be -1, 0 or 1");
   if (fuse < 0 || fuse > 4) return fail(JUQCS_ERR_ARG, "batch fuse_k must be 0 (auto) or 1..4");
   auto* B = new juqcs_batch();
   B->count = count;
@@ -289,6 +320,7 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
   B->state_off.assign(state_offset, state_offset + count);
   B->states = (char*)d_states;
   B->kin.assign(count, 2);
+  set_layout(B, 0, {});
   std::vector<TilePlan> plans(count);
   std::vector<std::vector<Gate>> dec(count);
   std::string err;
@@ -306,7 +338,8 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
   if (!autotune) {
     parallel_for(count, [&](int c) {
       TileSchedule sched;
-      schedule_circuit(n[c], dec[c], &sched);
+      schedule_circuit(n[c], dec[c], &sched, relabel);
+      set_layout(B, c, sched.final_pos);
       if (fuse > 0) {
         emit_schedule(sched, dec[c], fuse, &plans[c], 0, batch_mma_cap());
         B->kin[c] = fuse;
@@ -334,7 +367,7 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
         int bk = 2;
         for (int k = 1; k <= 4; ++k) {
           TilePlan p;
-          plan_circuit(n[c], dec[c], k, &p);
+          plan_circuit(n[c], dec[c], k, relabel, &p);
           const double t = time_plan(B->states, B->state_off[c], n[c], p, nullptr);
           if (t < best) {
             best = t;
@@ -347,7 +380,11 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
     }
   }
   if (autotune)
-    parallel_for(count, [&](int c) { plan_circuit(n[c], dec[c], B->kin[c], &plans[c]); });
+    parallel_for(count, [&](int c) {
+      TileSchedule sched;
+      plan_circuit(n[c], dec[c], B->kin[c], relabel, &plans[c], &sched);
+      set_layout(B, c, sched.final_pos);
+    });
   juqcs_status rc = build_device(B, plans);
   if (rc != JUQCS_OK) {
     free_batch(B);
@@ -401,6 +438,13 @@ juqcs_status juqcs_batch_stats(const juqcs_batch* B, int64_t* tasks, int64_t* ga
   return JUQCS_OK;
 }
 
+juqcs_status juqcs_batch_layout(const juqcs_batch* B, int c, int* phys) {
+  if (!B || !phys) return fail(JUQCS_ERR_ARG, "null argument");
+  if (c < 0 || c >= B->count) return fail(JUQCS_ERR_ARG, "circuit index out of range");
+  for (int q = 0; q < B->n[c]; ++q) phys[q] = B->pos[(size_t)c * kMaxBatchQubits + q];
+  return JUQCS_OK;
+}
+
 juqcs_status juqcs_batch_fusion(const juqcs_batch* B, int* kin) {
   if (!B || !kin) return fail(JUQCS_ERR_ARG, "null argument");
   for (int c = 0; c < B->count; ++c) kin[c] = B->kin[c];
@@ -420,7 +464,7 @@ juqcs_status juqcs_batch_amplitudes(juqcs_batch* B, const uint64_t* idx, int m, 
   if (e == hipSuccess) e = hipMalloc((void**)&d_out, total * 2 * sizeof(double));
   if (e == hipSuccess) e = hipMemcpyAsync(d_idx, idx, total * sizeof(uint64_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = launch_batch_gather(B->states, B->d_state_off, B->d_nq, B->count, m, d_idx, d_out, s);
+    e = launch_batch_gather(B->states, B->d_state_off, B->d_nq, B->d_pos, B->count, m, d_idx, d_out, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, d_out, total * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -528,7 +572,8 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
   const long long nb = 1ll << m;
   // template plans, one per half; branches only change the diagonal values
   TilePlan tmpl[2];
-  for (int p = 0; p < 2; ++p) plan_circuit(nloc[p], half[p], 2, &tmpl[p]);
+  TileSchedule tsched[2];
+  for (int p = 0; p < 2; ++p) plan_circuit(nloc[p], half[p], 2, true, &tmpl[p], &tsched[p]);
   // bitstring halves
   std::vector<uint64_t> zh[2];
   for (int p = 0; p < 2; ++p) zh[p].resize(count);
@@ -575,8 +620,13 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
       for (int p = 0; p < 2; ++p) {
         std::vector<Gate> hg = half[p];
         for (auto& sl : slot[p]) branch_diag(((br >> sl.second) & 1) ? -1 : 1, hg[sl.first].m);
+        // the plan's ops refer to the schedule's relabeled gate copies
+        std::vector<Gate> tg = tsched[p].tgates.empty() ? hg : tsched[p].tgates;
+        if (!tsched[p].tgates.empty())
+          for (size_t j = 0; j < tg.size(); ++j)
+            std::memcpy(tg[j].m, hg[tsched[p].tsrc[j]].m, sizeof(tg[j].m));
         TilePlan pl = tmpl[p];
-        rebuild_mats(hg, &pl);
+        rebuild_mats(tg, &pl);
         // circuits [0, g): first part of each branch, [g, 2g): second part
         const int c = (int)(p * g + j);
         plans[c] = std::move(pl);
@@ -592,6 +642,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
       B.state_off[c] = off;
       off += align256(sbytes[p]);
     }
+    for (int c = 0; c < B.count; ++c) set_layout(&B, c, tsched[c < g ? 0 : 1].final_pos);
     B.states = states;
     rc = build_device(&B, plans);
     if (rc == JUQCS_OK) rc = run_device(&B, s);
@@ -601,7 +652,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
       double* tmp = nullptr;
       if (e == hipSuccess) e = hipMalloc((void**)&tmp, (size_t)B.count * count * 2 * sizeof(double));
       if (e == hipSuccess)
-        e = launch_batch_gather(B.states, B.d_state_off, B.d_nq, B.count, (int)count, dz, tmp, s);
+        e = launch_batch_gather(B.states, B.d_state_off, B.d_nq, B.d_pos, B.count, (int)count, dz, tmp, s);
       const size_t rows = (size_t)g * count * 2 * sizeof(double);
       if (e == hipSuccess)
         e = hipMemcpyAsync(dA + (size_t)b0 * count * 2, tmp, rows, hipMemcpyDeviceToDevice, s);

@@ -232,7 +232,8 @@ int batch_mma_cap();  // 8x8 ops per pass whose tables the batch kernel holds in
 int batch_max_gather();  // most gathered chunk bits of a batch pass
 hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s);
 hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, const int32_t* nq,
-                               int count, int m, const uint64_t* idx, double* out, hipStream_t s);
+                               const int8_t* pos, int count, int m, const uint64_t* idx, double* out,
+                               hipStream_t s);
 hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, const int32_t* nq,
                               int count, double* out, hipStream_t s);
 hipError_t launch_branch_reduce(const double* A, const double* B, long long nb, int m,
@@ -270,9 +271,11 @@ struct TileSchedule {
   std::vector<std::vector<int>> taken;
   int64_t gates = 0;
   // Relabeling schedules only: the absorbed gates on the physical bits of
-  // their pass (taken indexes these), and final_pos[p] = where the qubit at
-  // physical bit p before the schedule sits after it.
+  // their pass (taken indexes these), the index of each in the input gate
+  // list, and final_pos[p] = where the qubit at physical bit p before the
+  // schedule sits after it.
   std::vector<Gate> tgates;
+  std::vector<int> tsrc;
   std::vector<int> final_pos;
 };
 // max_take > 0 caps the gates one pass absorbs (later gates wait for the

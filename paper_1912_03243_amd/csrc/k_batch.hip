@@ -56,7 +56,7 @@ __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64
                                        bool init, int L, int H, const int* hb,
                                        const uint64_t* choff, const TileOp* ops, int nops,
                                        const cplx<float>* mats, const tileops::OpPre* pre,
-                                       const void* tabs) {
+                                       const void* tabs, const int* swp, int nswap, const int* swk) {
   constexpr int NA = 1 << TB, PER = NA / kBatchThreads;
   const int lmask = (1 << L) - 1;
   typedef float v2 __attribute__((ext_vector_type(2)));
@@ -95,10 +95,19 @@ __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64
     }
     using F = Fixed<float, TB, kBatchThreads>;
     F::template run<F::D3_TAB>(sh, ops, nops, mats, pre, tabs);
+    // write-back through the pass's relabel swaps (see k_tile_fixed):
+    // destination e takes LDS element lds(swap(t)) ^ swk[k]
+    int t = threadIdx.x;
+    for (int i = 0; i < nswap; ++i) {
+      const int pr = swp[i], a = pr & 255, c = pr >> 8;
+      const int x = ((t >> a) ^ (t >> c)) & 1;
+      t ^= (x << a) | (x << c);
+    }
+    const int lt = lds<float>(t);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = k * kBatchThreads + threadIdx.x;
-      gp[base + choff[e >> L] + (e & lmask)] = sp[lds<float>(e)];
+      gp[base + choff[e >> L] + (e & lmask)] = sp[lt ^ swk[k]];
     }
     __syncthreads();
   }
@@ -107,7 +116,7 @@ __device__ inline void run_chunk_fixed(cplx<float>* sh, cplx<float>* psi, uint64
 __device__ inline void run_chunk_var(cplx<float>* sh, cplx<float>* psi, uint64_t tau0, int ntile,
                                      bool init, int b, int L, int H, const int* hb,
                                      const uint64_t* choff, const TileOp* ops, int nops,
-                                     const cplx<float>* mats) {
+                                     const cplx<float>* mats, const int* swp, int nswap) {
   const int tile_amps = 1 << b, lmask = (1 << L) - 1;
   for (int j = 0; j < ntile; ++j) {
     const uint64_t base = tile_base_hb(tau0 + j, L, H, hb);
@@ -120,8 +129,15 @@ __device__ inline void run_chunk_var(cplx<float>* sh, cplx<float>* psi, uint64_t
     }
     __syncthreads();
     Var<float, kBatchThreads>::run(sh, b, ops, nops, mats);
-    for (int e = threadIdx.x; e < tile_amps; e += kBatchThreads)
-      psi[base + choff[e >> L] + (e & lmask)] = sh[lds<float>(e)];
+    for (int e = threadIdx.x; e < tile_amps; e += kBatchThreads) {
+      int t = e;  // relabel swaps of the write-back
+      for (int i = 0; i < nswap; ++i) {
+        const int pr = swp[i], a = pr & 255, c = pr >> 8;
+        const int x = ((t >> a) ^ (t >> c)) & 1;
+        t ^= (x << a) | (x << c);
+      }
+      psi[base + choff[e >> L] + (e & lmask)] = sh[lds<float>(t)];
+    }
     __syncthreads();
   }
 }
@@ -137,6 +153,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
   __shared__ BatchTab tabs[kBatchTabs];  // the current pass's 8x8-op tables
   __shared__ tileops::OpPre pre[kPassOps];  // the current pass's op parameters
   __shared__ int hb[kHbitsCap];
+  __shared__ int swp[kSwapCap];                // the current pass's relabel swaps
+  __shared__ int swk[(1 << kBatchMaxBits) / kBatchThreads];  // lds(swap(k NT))
   __shared__ long long s_t;
   __shared__ int s_g;
   int cur_pass = -1;
@@ -168,7 +186,21 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
       // would put it in scratch)
       if (threadIdx.x < kHbitsCap)
         hb[threadIdx.x] = (int)threadIdx.x < H ? passes[grp.pass].g.hbits[threadIdx.x] : 0;
+      if (threadIdx.x < kSwapCap) {
+        const int i = threadIdx.x;
+        const TileGeom& pg = passes[grp.pass].g;
+        swp[i] = i < ps.g.nswap ? (int)pg.swap_a[i] | ((int)pg.swap_b[i] << 8) : 0;
+      }
       __syncthreads();
+      if (threadIdx.x < (1 << kBatchMaxBits) / kBatchThreads) {
+        int t = threadIdx.x * kBatchThreads;
+        for (int i = 0; i < ps.g.nswap; ++i) {
+          const int pr = swp[i], a = pr & 255, c = pr >> 8;
+          const int x = ((t >> a) ^ (t >> c)) & 1;
+          t ^= (x << a) | (x << c);
+        }
+        swk[threadIdx.x] = lds<float>(t);
+      }
       for (int c = threadIdx.x; c < (1 << H); c += kBatchThreads) {
         uint64_t o = 0;
         for (int j = 0; j < H; ++j) o |= (uint64_t)((c >> j) & 1) << hb[j];
@@ -199,30 +231,35 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(
     const bool init = grp.init != 0;
     // the fixed-size paths run ops of up to 3 qubits, 8x8 ops from their tables
     switch (fixed_pass(ps) ? b : 0) {
-      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs); break;
-      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs); break;
-      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs); break;
-      default: run_chunk_var(sh, psi, tau0, grp.chunk_tiles, init, b, L, H, hb, choff, pops, ps.op_count, mats); break;
+      case 13: run_chunk_fixed<13>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs, swp, ps.g.nswap, swk); break;
+      case 12: run_chunk_fixed<12>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs, swp, ps.g.nswap, swk); break;
+      case 11: run_chunk_fixed<11>(sh, psi, tau0, grp.chunk_tiles, init, L, H, hb, choff, pops, ps.op_count, mats, pre, tabs, swp, ps.g.nswap, swk); break;
+      default: run_chunk_var(sh, psi, tau0, grp.chunk_tiles, init, b, L, H, hb, choff, pops, ps.op_count, mats, swp, ps.g.nswap); break;
     }
     __syncthreads();
   }
 }
 
-// out[c * m + k] = amplitude idx[c * m + k] of circuit c (FP64 pairs).
+// out[c * m + k] = amplitude idx[c * m + k] of circuit c (FP64 pairs);
+// logical bit q of the index sits at physical bit pos[c * 32 + q].
 __global__ __launch_bounds__(kThreads) void k_batch_gather(const char* __restrict__ states,
                                                            const uint64_t* __restrict__ state_off,
-                                                           const int32_t* __restrict__ nq, int count,
+                                                           const int32_t* __restrict__ nq,
+                                                           const int8_t* __restrict__ pos, int count,
                                                            int m, const uint64_t* __restrict__ idx,
                                                            double* __restrict__ out) {
   const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (k >= (long long)count * m) return;
   const int c = (int)(k / m);
   const uint64_t z = idx[k];
-  if ((z >> nq[c]) != 0) {
+  const int n = nq[c];
+  if ((z >> n) != 0) {
     out[2 * k] = out[2 * k + 1] = __builtin_nan("");
     return;
   }
-  const cplx<float> v = reinterpret_cast<const cplx<float>*>(states + state_off[c])[z];
+  uint64_t p = 0;
+  for (int q = 0; q < n; ++q) p |= ((z >> q) & 1) << pos[(size_t)c * 32 + q];
+  const cplx<float> v = reinterpret_cast<const cplx<float>*>(states + state_off[c])[p];
   out[2 * k] = (double)v.re;
   out[2 * k + 1] = (double)v.im;
 }
@@ -314,11 +351,12 @@ hipError_t launch_batch(char* states, const BatchDevice& d, hipStream_t s) {
 }
 
 hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, const int32_t* nq,
-                               int count, int m, const uint64_t* idx, double* out, hipStream_t s) {
+                               const int8_t* pos, int count, int m, const uint64_t* idx, double* out,
+                               hipStream_t s) {
   const long long total = (long long)count * m;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)((total + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, states, state_off, nq, count, m, idx, out);
+                     dim3(kThreads), 0, s, states, state_off, nq, pos, count, m, idx, out);
   return hipGetLastError();
 }
 

@@ -474,9 +474,12 @@ void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector
   sched->final_pos.resize(n);
   for (int q = 0; q < n; ++q) sched->final_pos[q] = q;
   sched->tgates.clear();
+  sched->tsrc.clear();
   if (n <= b) {
     select_tiles(n, L, b, block_bits, gates, sched, max_take);
     sched->tgates = gates;  // a single tile: nothing moves
+    sched->tsrc.resize(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) sched->tsrc[i] = (int)i;
     return;
   }
   sched->passes.clear();
@@ -510,6 +513,7 @@ void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector
         for (int j = 0; j < t.nq; ++j) t.q[j] = pos[t.q[j]];
         taken.push_back((int)sched->tgates.size());
         sched->tgates.push_back(t);
+        sched->tsrc.push_back(gi);
       } else {
         keep.push_back(gi);
         for (int j = 0; j < g.nq; ++j) blocked[g.q[j]] = 1;

@@ -85,6 +85,7 @@ _SIGS = {
     "juqcs_batch_run": [_P, _P],
     "juqcs_batch_wait": [_P],
     "juqcs_batch_fusion": [_P, ct.POINTER(_I)],
+    "juqcs_batch_layout": [_P, _I, ct.POINTER(_I)],
     "juqcs_batch_amplitudes": [_P, ct.POINTER(_U64), _I, _DP, _P],
     "juqcs_batch_norms": [_P, _DP, _P],
     "juqcs_batch_stats": [_P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
@@ -331,7 +332,7 @@ class Batch:
     """Many independent C64 circuits executed by one graph launch (one kernel per pass round)."""
 
     def __init__(self, circuits, device="cuda", states=None, fuse_k: int = 0,
-                 autotune: bool = False):
+                 autotune: bool = False, relabel: int = 0):
         import torch
         ns = np.array([n for n, _ in circuits], dtype=np.int32)
         offs = np.zeros(len(circuits) + 1, dtype=np.int64)
@@ -349,7 +350,7 @@ class Batch:
         self.state_offset = soff
         self.states = states if states is not None else torch.empty(max(run, 256), dtype=torch.uint8,
                                                                      device=device)
-        o = PlanOpts(mode=PLAN_TILE, fuse_k=fuse_k, autotune=int(autotune))
+        o = PlanOpts(mode=PLAN_TILE, fuse_k=fuse_k, autotune=int(autotune), relabel=relabel)
         h = _P()
         _check(_lib.juqcs_batch_create(ct.byref(h), len(circuits),
                                        ns.ctypes.data_as(ct.POINTER(_I)), allg.ctypes.data,
@@ -392,13 +393,28 @@ class Batch:
                "juqcs_batch_stats")
         return {"tasks": a.value, "gate_apps": b.value, "passes": c.value}
 
+    def layout(self, i: int):
+        p = (ct.c_int * int(self.n[i]))()
+        _check(_lib.juqcs_batch_layout(self.h, i, p), "juqcs_batch_layout")
+        return list(p)
+
     def state_vector(self, i: int) -> np.ndarray:
+        """State of circuit i in logical order (the relabeled layout is undone
+        on the host)."""
         import torch
         torch.cuda.synchronize()
         n = int(self.n[i])
         off = int(self.state_offset[i])
         a = self.states[off: off + (8 << n)].view(torch.float32).cpu().numpy().astype(np.float64)
-        return a[0::2] + 1j * a[1::2]
+        phys = a[0::2] + 1j * a[1::2]
+        layout = self.layout(i)
+        if layout == list(range(n)):
+            return phys
+        x = np.arange(1 << n, dtype=np.int64)
+        p = np.zeros_like(x)
+        for q, pq in enumerate(layout):
+            p |= ((x >> q) & 1) << pq
+        return phys[p]
 
     def close(self):
         if getattr(self, "h", None):

@@ -59,6 +59,31 @@ def test_batch_matches_oracle(J, fuse_k):
     b.close()
 
 
+@pytest.mark.parametrize("relabel", [-1, 0])
+def test_batch_relabel(J, relabel):
+    # deep circuits on 16-20 qubits need several passes; with relabeling the
+    # passes move qubits onto the low bits and the readouts map through the
+    # recorded layout
+    announce("batch-relabel", relabel)
+    circuits = [(n, W.layered_brick(n, 10, seed=300 + n)) for n in (16, 17, 18, 20)]
+    circuits.append((19, W.random_mixed(19, 150, seed=319)))
+    b = J.Batch(circuits, relabel=relabel)
+    b.run()
+    b.wait()
+    z = np.stack([np.arange(0, 1 << 16, 331, dtype=np.uint64)[:150]] * len(circuits))
+    amps = b.amplitudes(z)
+    moved = 0
+    for i, (n, circ) in enumerate(circuits):
+        phi = sv.run_circuit(n, circ)
+        assert_c64(b.state_vector(i), phi)
+        assert_c64(amps[i], phi[z[i].astype(np.int64)])
+        layout = b.layout(i)
+        assert sorted(layout) == list(range(n))
+        moved += layout != list(range(n))
+    assert moved > 0 if relabel == 0 else moved == 0
+    b.close()
+
+
 def test_batch_graph_replay_and_readout(J):
     import torch
     announce("batch-graph")
