@@ -447,13 +447,44 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
 // tile geometry: sums over the amplitude pairs that differ in bit j, of
 // (2 Re conj(a0) a1, 2 Im conj(a0) a1, |a0|^2 - |a1|^2), in FP64.  Both
 // members of every such pair lie in one tile, so one read pass covers b bits
-// (Section 3: the expectation values of all qubits).  With nb = b - jlo new
-// bits, wave w reduces bit jlo + w % nb over the share w / nb of the pairs
-// (a power-of-two number of shares, at most 16 / nb); every sum runs over a
-// fixed set of pairs in a fixed order.  The next tile is prefetched into registers while one is reduced.
+// (Section 3: the expectation values of all qubits).  The nb = b - jlo bits
+// form ng = ceil(nb / 3) groups of up to three consecutive bits; a wave
+// reads items of 2^gk amplitudes that span its group's gk bits (one LDS
+// read serves all pairs of the group: 12 pairs for three bits) and reduces
+// a share of the items (a power-of-two number of shares, at most 16 / ng).
+// Wave w takes group w % ng, share w / ng; every sum runs over a fixed set
+// of pairs in a fixed order.  The next tile is prefetched into registers
+// while one is reduced.
 constexpr int kExpectThreads = 1024;
 constexpr int kExpectBits = 13;
 constexpr int kExpectWaves = kExpectThreads / 64;
+constexpr int kExpectGroup = 3;  // bits per wave group
+
+__device__ __host__ inline int expect_groups(int nb) { return (nb + kExpectGroup - 1) / kExpectGroup; }
+__device__ __host__ inline int expect_shares(int ng) {
+  int shares = 1;
+  while (2 * shares * ng <= kExpectWaves) shares *= 2;
+  return shares;
+}
+
+// Pair sums of one item (2^GK amplitudes at LDS byte offsets u ^ row[r]).
+template <typename T, int GK>
+__device__ inline void expect_item(const char* base, int u, const int* row, double* sx, double* sy,
+                                   double* sz) {
+  cplx<T> a[1 << GK];
+#pragma unroll
+  for (int r = 0; r < (1 << GK); ++r) a[r] = *reinterpret_cast<const cplx<T>*>(base + (u ^ row[r]));
+#pragma unroll
+  for (int jj = 0; jj < GK; ++jj)
+#pragma unroll
+    for (int r = 0; r < (1 << GK); ++r) {
+      if ((r >> jj) & 1) continue;
+      const double ar = a[r].re, ai = a[r].im, br = a[r | (1 << jj)].re, bi = a[r | (1 << jj)].im;
+      sx[jj] = fma(ar, br, fma(ai, bi, sx[jj]));
+      sy[jj] = fma(ar, bi, fma(-ai, br, sy[jj]));
+      sz[jj] += fma(ar, ar, ai * ai) - fma(br, br, bi * bi);
+    }
+}
 
 template <typename S>  // storage: double (C128), float (C64), int8_t (ENC2)
 __global__ __launch_bounds__(kExpectThreads) void k_expect(const void* __restrict__ amps,
@@ -469,17 +500,22 @@ __global__ __launch_bounds__(kExpectThreads) void k_expect(const void* __restric
   const int b = g.b, L = g.L, lmask = (1 << L) - 1, tile_amps = 1 << b;
   const uint64_t ntiles = uint64_t(1) << (g.n - b);
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nb = b - jlo;
-  int shares = 1;  // a power of two (the pair index splits bitwise)
-  while (2 * shares * nb <= kExpectWaves) shares *= 2;
-  const int j = jlo + wave % nb, share = wave / nb;
+  const int nb = b - jlo, ng = expect_groups(nb), shares = expect_shares(ng);
+  const int grp = wave % ng, share = wave / ng;
   const bool active = share < shares;
-  // pair p = (it * shares + share) * 64 + lane: e0 = spread(p) splits into a
-  // uniform part and the lane's part; offsets in bytes
-  const int pos[1] = {j};
-  const int lane_off = tileops::lds<T>(tileops::spread<1>(lane, pos)) * CB;
-  const int partner = tileops::lds<T>(1 << j) * CB;
-  const int npairs = tile_amps >> 1;
+  const int j0 = jlo + kExpectGroup * grp;
+  const int gk = j0 + kExpectGroup <= b ? kExpectGroup : b - j0;  // bits of this wave's group
+  // item i = (it * shares + share) * 64 + lane: its base element spreads i
+  // over the positions around the group's bits j0..j0+gk-1 (a contiguous
+  // run, so the spread is one shift); byte offsets in LDS
+  const int nitems = tile_amps >> gk;
+  int row[1 << kExpectGroup];
+#pragma unroll
+  for (int r = 0; r < (1 << kExpectGroup); ++r) row[r] = tileops::lds<T>((r & ((1 << gk) - 1)) << j0) * CB;
+  auto item_off = [&](int i) {
+    const int e = ((i >> j0) << (j0 + gk)) | (i & ((1 << j0) - 1));
+    return tileops::lds<T>(e) * CB;
+  };
   const char* base = reinterpret_cast<const char*>(sh);
   // register prefetch: whole amplitudes (C128/C64) or 16-byte code groups
   constexpr int PER = sizeof(S) == 1 ? NA / 8 / kExpectThreads : NA / kExpectThreads;
@@ -487,11 +523,14 @@ __global__ __launch_bounds__(kExpectThreads) void k_expect(const void* __restric
   typedef typename std::conditional<sizeof(S) == 1, v4i, v2>::type Item;
   Item v[PER];
   float sc[PER];
-  auto fetch = [&](uint64_t tau) {
+  // the thread's addresses are recomputed every tile from an opaque tid:
+  // hoisted out of the loop they would stay live and spill, and a spill
+  // reload waits for the prefetch loads in flight
+  auto fetch = [&](uint64_t tau, int tid) {
     const uint64_t tb = tile_base(tau, L, g.H, gs.hb);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int q = k * kExpectThreads + threadIdx.x;
+      const int q = k * kExpectThreads + tid;
       if constexpr (sizeof(S) == 1) {
         const int e = (q << 3) < tile_amps ? q << 3 : 0;
         const uint64_t gi = tb + gs.choff[e >> L] + (e & lmask);
@@ -503,14 +542,17 @@ __global__ __launch_bounds__(kExpectThreads) void k_expect(const void* __restric
       }
     }
   };
-  double sx = 0.0, sy = 0.0, sz = 0.0;
+  double sx[kExpectGroup] = {0.0, 0.0, 0.0}, sy[kExpectGroup] = {0.0, 0.0, 0.0},
+         sz[kExpectGroup] = {0.0, 0.0, 0.0};
   uint64_t tau, tau_end;
   tile_run(ntiles, &tau, &tau_end);
-  fetch(tau);
+  fetch(tau, (int)threadIdx.x);
   for (; tau < tau_end; ++tau) {
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int q = k * kExpectThreads + threadIdx.x;
+      const int q = k * kExpectThreads + tid;
       if constexpr (sizeof(S) == 1) {
         if ((q << 3) < tile_amps) decode8(make_int4(v[k].x, v[k].y, v[k].z, v[k].w), sc[k] / 127.0f, sh, q << 3);
       } else {
@@ -518,65 +560,50 @@ __global__ __launch_bounds__(kExpectThreads) void k_expect(const void* __restric
       }
     }
     __syncthreads();
-    fetch(tau + 1 < tau_end ? tau + 1 : tau);
+    fetch(tau + 1 < tau_end ? tau + 1 : tau, tid);
     if (active) {
-      // rows of 64 pairs, wave-uniform; four rows' reads are issued together
-      const int step = 64 * shares;
-      auto pair = [&](const cplx<T>& x, const cplx<T>& y) {
-        const double ar = x.re, ai = x.im, br = y.re, bi = y.im;
-        sx = fma(ar, br, fma(ai, bi, sx));
-        sy = fma(ar, bi, fma(-ai, br, sy));
-        sz += fma(ar, ar, ai * ai) - fma(br, br, bi * bi);
-      };
-      int p0 = share * 64;
-      if (npairs >= 64) {
-        for (; p0 + 3 * step < npairs; p0 += 4 * step) {
-          cplx<T> x[4], y[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int u = (tileops::lds<T>(tileops::spread<1>(p0 + r * step, pos)) * CB) ^ lane_off;
-            x[r] = *reinterpret_cast<const cplx<T>*>(base + u);
-            y[r] = *reinterpret_cast<const cplx<T>*>(base + (u ^ partner));
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) pair(x[r], y[r]);
+      for (int p0 = share * 64; p0 < nitems; p0 += 64 * shares) {
+        const int i = p0 + lane;
+        if (i < nitems) {
+          const int u = item_off(i);
+          if (gk == 3) expect_item<T, 3>(base, u, row, sx, sy, sz);
+          else if (gk == 2) expect_item<T, 2>(base, u, row, sx, sy, sz);
+          else expect_item<T, 1>(base, u, row, sx, sy, sz);
         }
-        for (; p0 < npairs; p0 += step) {
-          const int u = (tileops::lds<T>(tileops::spread<1>(p0, pos)) * CB) ^ lane_off;
-          pair(*reinterpret_cast<const cplx<T>*>(base + u),
-               *reinterpret_cast<const cplx<T>*>(base + (u ^ partner)));
-        }
-      } else if (p0 == 0 && lane < npairs) {  // tiles of fewer than 128 amplitudes
-        pair(*reinterpret_cast<const cplx<T>*>(base + lane_off),
-             *reinterpret_cast<const cplx<T>*>(base + (lane_off ^ partner)));
       }
     }
     __syncthreads();
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    sx += __shfl_xor(sx, off, 64);
-    sy += __shfl_xor(sy, off, 64);
-    sz += __shfl_xor(sz, off, 64);
-  }
+#pragma unroll
+  for (int jj = 0; jj < kExpectGroup; ++jj)
+    for (int off = 32; off > 0; off >>= 1) {
+      sx[jj] += __shfl_xor(sx[jj], off, 64);
+      sy[jj] += __shfl_xor(sy[jj], off, 64);
+      sz[jj] += __shfl_xor(sz[jj], off, 64);
+    }
   if (lane == 0) {
-    double* o = partials + 3 * ((size_t)wave * gridDim.x + blockIdx.x);
-    o[0] = active ? 2.0 * sx : 0.0;
-    o[1] = active ? 2.0 * sy : 0.0;
-    o[2] = active ? sz : 0.0;
+#pragma unroll
+    for (int jj = 0; jj < kExpectGroup; ++jj) {
+      const bool used = active && jj < gk;
+      double* o = partials + 3 * (((size_t)wave * kExpectGroup + jj) * gridDim.x + blockIdx.x);
+      o[0] = used ? 2.0 * sx[jj] : 0.0;
+      o[1] = used ? 2.0 * sy[jj] : 0.0;
+      o[2] = used ? sz[jj] : 0.0;
+    }
   }
 }
 
-// out3[3 k + c]: bit jlo + k, summed over its waves (k, k + nb, ...) and
-// over blocks, in that order.
+// out3[3 k + c]: bit jlo + k, summed over the waves of its group (in wave
+// order) and over blocks, in that order.
 __global__ __launch_bounds__(64) void k_expect_final(const double* __restrict__ partials, int nblk,
                                                      int nbits, double* __restrict__ out3) {
   const int k = threadIdx.x / 3, c = threadIdx.x % 3;
   if (k >= nbits) return;
+  const int ng = expect_groups(nbits), shares = expect_shares(ng);
+  const int grp = k / kExpectGroup, jj = k % kExpectGroup;
   double s = 0.0;
-  int shares = 1;
-  while (2 * shares * nbits <= kExpectWaves) shares *= 2;
-  for (int w = k; w < shares * nbits; w += nbits)
-    for (int i = 0; i < nblk; ++i) s += partials[3 * ((size_t)w * nblk + i) + c];
+  for (int w = grp; w < shares * ng; w += ng)
+    for (int i = 0; i < nblk; ++i) s += partials[3 * (((size_t)w * kExpectGroup + jj) * nblk + i) + c];
   out3[3 * k + c] = s;
 }
 
@@ -688,7 +715,7 @@ hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales, const TileGeom&
 int expect_max_bits() { return kExpectBits; }
 
 size_t expect_partials_bytes() {
-  return sizeof(double) * 3 * kExpectWaves *
+  return sizeof(double) * 3 * kExpectWaves * kExpectGroup *
          (size_t)resident_blocks((const void*)k_expect<double>, kExpectThreads);
 }
 
