@@ -767,11 +767,16 @@ juqcs_status juqcs_expectations(juqcs_state* st, double* out) {
   if (e != hipSuccess) return hip_fail(e, "expectation launch");
   for (int covered = b; covered < n;) {
     const int H = std::min(b - L, n - covered);
+    // a last pass with fewer new bits keeps the full tile size: bits already
+    // covered (just below the new ones) fill the tile and are not reduced
+    // again (small tiles would make the pass launch-bound)
+    const int fill = std::min(b - L - H, covered - L);
     g.L = L;
-    g.H = H;
-    g.b = L + H;
-    for (int i = 0; i < H; ++i) g.hbits[i] = covered + i;
-    e = launch_expect(st->dt, st->amps, st->scales, g, L, partials, res + 3 * covered, st->stream);
+    g.H = fill + H;
+    g.b = L + fill + H;
+    for (int i = 0; i < fill; ++i) g.hbits[i] = covered - fill + i;
+    for (int i = 0; i < H; ++i) g.hbits[fill + i] = covered + i;
+    e = launch_expect(st->dt, st->amps, st->scales, g, L + fill, partials, res + 3 * covered, st->stream);
     if (e != hipSuccess) return hip_fail(e, "expectation launch");
     covered += H;
   }
