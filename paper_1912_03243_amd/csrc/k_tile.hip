@@ -451,7 +451,7 @@ __global__ __launch_bounds__(kFixedThreads, 4) void k_tile_enc2_fixed(
 // form ng = ceil(nb / 3) groups of up to three consecutive bits; a wave
 // reads items of 2^gk amplitudes that span its group's gk bits (one LDS
 // read serves all pairs of the group: 12 pairs for three bits) and reduces
-// a share of the items (a power-of-two number of shares, at most 16 / ng).
+// a share of the items (16 / ng shares, rounded down).
 // Wave w takes group w % ng, share w / ng; every sum runs over a fixed set
 // of pairs in a fixed order.  The next tile is prefetched into registers
 // while one is reduced.
@@ -461,11 +461,7 @@ constexpr int kExpectWaves = kExpectThreads / 64;
 constexpr int kExpectGroup = 3;  // bits per wave group
 
 __device__ __host__ inline int expect_groups(int nb) { return (nb + kExpectGroup - 1) / kExpectGroup; }
-__device__ __host__ inline int expect_shares(int ng) {
-  int shares = 1;
-  while (2 * shares * ng <= kExpectWaves) shares *= 2;
-  return shares;
-}
+__device__ __host__ inline int expect_shares(int ng) { return kExpectWaves / ng; }
 
 // Pair sums of one item (2^GK amplitudes at LDS byte offsets u ^ row[r]).
 template <typename T, int GK>
