@@ -329,18 +329,20 @@ juqcs_status juqcs_batch_destroy(juqcs_batch* b);
  * ---------------------------------------------------------------------- */
 
 /* <z|C|0> for count bitstrings z of an n-qubit circuit (n <= 62) whose
- * qubits are split in two parts by side[q] in {0,1} (each part at most 30
- * qubits).  Every CZ whose qubits lie in different parts is decomposed with
- * Eq. (2) (x = pi/4 - (i/2) asinh 1); branch b in [0, 2^m) uses s_k = +1 if
- * bit k of b is 0, else -1, for the k-th crossing CZ in circuit order, and
- * applies diag(e^{i(x s_k - pi/4)}, e^{-i(x s_k - pi/4)}) to both of its
- * qubits at that position.  Every branch's two half-states are simulated in
- * C64 as batches (group_size half-states resident at
- * a time, 0 = automatic), and the result
- * 2^-m sum_b A_b(z_A) B_b(z_B) is summed in FP64 on the device (Eq. (3)).
- * Only CZ may cross the cut (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.
- * out: 2*count doubles (host).  Synchronises hip_stream.  The library
- * allocates the device memory this needs and frees it before returning. */
+ * qubits are split in P parts by side[q] in {0, ..., P-1} (2 <= P <= 8,
+ * each part 1..30 qubits; Section 4's partition into mutually exclusive
+ * subsets).  Every CZ whose qubits lie in different parts is decomposed
+ * with Eq. (2) (x = pi/4 - (i/2) asinh 1); branch b in [0, 2^m) uses
+ * s_k = +1 if bit k of b is 0, else -1, for the k-th crossing CZ in circuit
+ * order, and applies diag(e^{i(x s_k - pi/4)}, e^{-i(x s_k - pi/4)}) to
+ * both of its qubits at that position.  Every branch's P part-states are
+ * simulated in C64 as batches (group_size branches resident at a time,
+ * 0 = automatic), and the result 2^-m sum_b prod_p A_{b,p}(z_p) is summed
+ * in FP64 on the device (Eq. (3)).  Only CZ may cross between parts
+ * (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.  out: 2*count doubles (host).
+ * Synchronises hip_stream.  The library allocates the device memory this
+ * needs (P * 2^m * count complex FP64 partial amplitudes among it) and
+ * frees it before returning. */
 juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates,
                                      size_t gate_count, const uint8_t* side,
                                      const uint64_t* z, size_t count,

@@ -140,6 +140,7 @@ void free_batch(juqcs_batch* b) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kMaxBatchQubits = 32;  // layout entries per circuit
+constexpr int kMaxParts = 8;         // parts of the Eq. (3) decomposition
 
 // Layout entries of circuit c from a schedule's final positions.
 void set_layout(juqcs_batch* B, int c, const std::vector<int>& final_pos) {
@@ -526,18 +527,21 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     return fail(JUQCS_ERR_ARG, "null argument");
   hipStream_t s = (hipStream_t)hip_stream;
   // parts and local qubit numbers (ascending order inside a part)
-  int local[64], nloc[2] = {0, 0};
+  int P = 0;
   for (int q = 0; q < n; ++q) {
-    if (side[q] > 1) return fail(JUQCS_ERR_ARG, "side[q] must be 0 or 1");
-    local[q] = nloc[side[q]]++;
+    if (side[q] >= kMaxParts) return fail(JUQCS_ERR_ARG, "side[q] must be < " + std::to_string(kMaxParts));
+    P = std::max(P, side[q] + 1);
   }
-  if (nloc[0] < 1 || nloc[1] < 1 || nloc[0] > 30 || nloc[1] > 30)
-    return fail(JUQCS_ERR_ARG, "each part needs 1..30 qubits");
+  int local[64], nloc[kMaxParts] = {};
+  for (int q = 0; q < n; ++q) local[q] = nloc[side[q]]++;
+  if (P < 2) return fail(JUQCS_ERR_ARG, "at least two parts");
+  for (int p = 0; p < P; ++p)
+    if (nloc[p] < 1 || nloc[p] > 30) return fail(JUQCS_ERR_ARG, "each part needs 1..30 qubits");
   for (size_t k = 0; k < count; ++k)
     if ((z[k] >> n) != 0) return fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
-  // half circuits with placeholder diagonals at every crossing CZ
-  std::vector<Gate> half[2];
-  std::vector<std::pair<int, int>> slot[2];  // (gate index in half, crossing number)
+  // part circuits with placeholder diagonals at every crossing CZ
+  std::vector<Gate> part[kMaxParts];
+  std::vector<std::pair<int, int>> slot[kMaxParts];  // (gate index in part, crossing number)
   int m = 0;
   std::string err;
   for (size_t i = 0; i < gate_count; ++i) {
@@ -549,7 +553,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     }
     if (g.nq == 2 && side[g.q[0]] != side[g.q[1]]) {
       if (gates[i].op != JUQCS_OP_CZ)
-        return fail(JUQCS_ERR_UNSUPPORTED, "only CZ gates may cross the cut");
+        return fail(JUQCS_ERR_UNSUPPORTED, "only CZ gates may cross between parts");
       for (int j = 0; j < 2; ++j) {
         const int q = g.q[j], p = side[q];
         Gate d{};
@@ -558,38 +562,33 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
         d.q[1] = -1;
         branch_diag(1, d.m);
         d.diag = true;
-        slot[p].push_back({(int)half[p].size(), m});
-        half[p].push_back(d);
+        slot[p].push_back({(int)part[p].size(), m});
+        part[p].push_back(d);
       }
       ++m;
       continue;
     }
     const int p = side[g.q[0]];
     for (int j = 0; j < g.nq; ++j) g.q[j] = local[g.q[j]];
-    half[p].push_back(g);
+    part[p].push_back(g);
   }
   if (m > 20) return fail(JUQCS_ERR_UNSUPPORTED, "at most 20 crossing CZ gates");
   const long long nb = 1ll << m;
-  // template plans, one per half; branches only change the diagonal values
-  TilePlan tmpl[2];
-  TileSchedule tsched[2];
-  for (int p = 0; p < 2; ++p) plan_circuit(nloc[p], half[p], 2, true, &tmpl[p], &tsched[p]);
-  // bitstring halves
-  std::vector<uint64_t> zh[2];
-  for (int p = 0; p < 2; ++p) zh[p].resize(count);
-  for (size_t k = 0; k < count; ++k) {
-    uint64_t a = 0, b = 0;
-    for (int q = 0; q < n; ++q) {
-      const uint64_t bit = (z[k] >> q) & 1;
-      if (side[q]) b |= bit << local[q];
-      else a |= bit << local[q];
-    }
-    zh[0][k] = a;
-    zh[1][k] = b;
+  // template plans, one per part; branches only change the diagonal values
+  TilePlan tmpl[kMaxParts];
+  TileSchedule tsched[kMaxParts];
+  for (int p = 0; p < P; ++p) plan_circuit(nloc[p], part[p], 2, true, &tmpl[p], &tsched[p]);
+  // bitstring parts
+  std::vector<uint64_t> zh[kMaxParts];
+  for (int p = 0; p < P; ++p) zh[p].assign(count, 0);
+  for (size_t k = 0; k < count; ++k)
+    for (int q = 0; q < n; ++q) zh[side[q]][k] |= ((z[k] >> q) & 1) << local[q];
+  // group size: branches resident at a time (P part-states each)
+  size_t sbytes[kMaxParts], per_branch = 0;
+  for (int p = 0; p < P; ++p) {
+    sbytes[p] = (size_t)8 << nloc[p];
+    per_branch += align256(sbytes[p]);
   }
-  // group size: half-states resident at a time (two per branch)
-  const size_t sbytes[2] = {(size_t)8 << nloc[0], (size_t)8 << nloc[1]};
-  size_t per_branch = align256(sbytes[0]) + align256(sbytes[1]);
   long long G = group_size > 0 ? group_size : 0;
   if (G == 0) {
     size_t freeb = 0, totalb = 0;
@@ -598,36 +597,37 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     G = std::max<long long>(1, (long long)(budget / per_branch));
   }
   G = std::min(G, nb);
+  // A[p][b][k]: amplitude zh[p][k] of part p in branch b (FP64 pairs)
+  const size_t cnt = std::max<size_t>(count, 1);
   char* states = nullptr;
-  double *dA = nullptr, *dB = nullptr, *dOut = nullptr;
+  double *dA = nullptr, *dOut = nullptr;
   uint64_t* dz = nullptr;
   hipError_t e = hipMalloc((void**)&states, per_branch * G);
-  if (e == hipSuccess) e = hipMalloc((void**)&dA, nb * std::max<size_t>(count, 1) * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&dB, nb * std::max<size_t>(count, 1) * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&dOut, std::max<size_t>(count, 1) * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&dz, 2 * G * std::max<size_t>(count, 1) * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&dA, (size_t)P * nb * cnt * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dOut, cnt * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dz, (size_t)P * G * cnt * sizeof(uint64_t));
   juqcs_status rc = JUQCS_OK;
   if (e != hipSuccess) rc = hip_fail(e, "branch hipMalloc");
   std::vector<uint64_t> zlist;
   for (long long b0 = 0; rc == JUQCS_OK && b0 < nb; b0 += G) {
     const long long g = std::min(G, nb - b0);
     juqcs_batch B;
-    B.count = (int)(2 * g);
+    B.count = (int)(P * g);
     std::vector<TilePlan> plans(B.count);
     zlist.assign((size_t)B.count * count, 0);
     for (long long j = 0; j < g; ++j) {
       const long long br = b0 + j;
-      for (int p = 0; p < 2; ++p) {
-        std::vector<Gate> hg = half[p];
+      for (int p = 0; p < P; ++p) {
+        std::vector<Gate> hg = part[p];
         for (auto& sl : slot[p]) branch_diag(((br >> sl.second) & 1) ? -1 : 1, hg[sl.first].m);
         // the plan's ops refer to the schedule's relabeled gate copies
         std::vector<Gate> tg = tsched[p].tgates.empty() ? hg : tsched[p].tgates;
         if (!tsched[p].tgates.empty())
-          for (size_t j = 0; j < tg.size(); ++j)
-            std::memcpy(tg[j].m, hg[tsched[p].tsrc[j]].m, sizeof(tg[j].m));
+          for (size_t t = 0; t < tg.size(); ++t)
+            std::memcpy(tg[t].m, hg[tsched[p].tsrc[t]].m, sizeof(tg[t].m));
         TilePlan pl = tmpl[p];
         rebuild_mats(tg, &pl);
-        // circuits [0, g): first part of each branch, [g, 2g): second part
+        // circuits [p g, (p + 1) g): part p of each branch of the group
         const int c = (int)(p * g + j);
         plans[c] = std::move(pl);
         std::memcpy(zlist.data() + (size_t)c * count, zh[p].data(), count * sizeof(uint64_t));
@@ -637,27 +637,25 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     B.state_off.assign(B.count, 0);
     uint64_t off = 0;
     for (int c = 0; c < B.count; ++c) {
-      const int p = c < g ? 0 : 1;
+      const int p = (int)(c / g);
       B.n[c] = nloc[p];
       B.state_off[c] = off;
       off += align256(sbytes[p]);
     }
-    for (int c = 0; c < B.count; ++c) set_layout(&B, c, tsched[c < g ? 0 : 1].final_pos);
+    for (int c = 0; c < B.count; ++c) set_layout(&B, c, tsched[c / g].final_pos);
     B.states = states;
     rc = build_device(&B, plans);
     if (rc == JUQCS_OK) rc = run_device(&B, s);
     if (rc == JUQCS_OK && count > 0) {
       e = hipMemcpyAsync(dz, zlist.data(), zlist.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-      // gather into a temporary, then scatter rows to A / B (branch-major)
+      // gather into a temporary, then copy each part's rows into A (branch-major)
       double* tmp = nullptr;
       if (e == hipSuccess) e = hipMalloc((void**)&tmp, (size_t)B.count * count * 2 * sizeof(double));
       if (e == hipSuccess)
         e = launch_batch_gather(B.states, B.d_state_off, B.d_nq, B.d_pos, B.count, (int)count, dz, tmp, s);
       const size_t rows = (size_t)g * count * 2 * sizeof(double);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(dA + (size_t)b0 * count * 2, tmp, rows, hipMemcpyDeviceToDevice, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(dB + (size_t)b0 * count * 2, tmp + (size_t)g * count * 2, rows,
+      for (int p = 0; p < P && e == hipSuccess; ++p)
+        e = hipMemcpyAsync(dA + ((size_t)p * nb + b0) * count * 2, tmp + (size_t)p * g * count * 2, rows,
                            hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (tmp) (void)hipFree(tmp);
@@ -670,7 +668,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     free_batch(&B);
   }
   if (rc == JUQCS_OK && count > 0) {
-    e = launch_branch_reduce(dA, dB, nb, (int)count, std::ldexp(1.0, -m), dOut, s);
+    e = launch_branch_reduce(dA, P, nb, (int)count, std::ldexp(1.0, -m), dOut, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(out, dOut, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -678,7 +676,6 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
   }
   (void)hipFree(states);
   (void)hipFree(dA);
-  (void)hipFree(dB);
   (void)hipFree(dOut);
   (void)hipFree(dz);
   return rc;

@@ -288,20 +288,26 @@ __global__ __launch_bounds__(kThreads) void k_batch_norms(const char* __restrict
   }
 }
 
-// Eq. (3) with two parts: out[k] = scale * sum_b A[b][k] * B[b][k] (complex,
-// FP64), one block per requested coefficient, fixed-order tree over b.
-__global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __restrict__ A,
-                                                            const double* __restrict__ B,
+// Eq. (3): out[k] = scale * sum_b prod_p A[p][b][k] (complex, FP64; the
+// parts multiplied in order p = 0..P-1), one block per requested
+// coefficient, fixed-order tree over b.
+__global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __restrict__ A, int P,
                                                             long long nb, int m, double scale,
                                                             double* __restrict__ out) {
   __shared__ double sre[kThreads], sim[kThreads];
   const int k = blockIdx.x;
   double re = 0.0, im = 0.0;
   for (long long b = threadIdx.x; b < nb; b += kThreads) {
-    const double ar = A[2 * (b * m + k)], ai = A[2 * (b * m + k) + 1];
-    const double br = B[2 * (b * m + k)], bi = B[2 * (b * m + k) + 1];
-    re += ar * br - ai * bi;
-    im += ar * bi + ai * br;
+    double pr = A[2 * (b * m + k)], pi = A[2 * (b * m + k) + 1];
+    for (int p = 1; p < P; ++p) {
+      const size_t o = 2 * (((size_t)p * nb + b) * m + k);
+      const double br = A[o], bi = A[o + 1];
+      const double t = pr * br - pi * bi;
+      pi = pr * bi + pi * br;
+      pr = t;
+    }
+    re += pr;
+    im += pi;
   }
   sre[threadIdx.x] = re;
   sim[threadIdx.x] = im;
@@ -367,10 +373,10 @@ hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, con
   return hipGetLastError();
 }
 
-hipError_t launch_branch_reduce(const double* A, const double* B, long long nb, int m, double scale,
+hipError_t launch_branch_reduce(const double* A, int P, long long nb, int m, double scale,
                                 double* out, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_branch_reduce, dim3(m), dim3(kThreads), 0, s, A, B, nb, m, scale, out);
+  hipLaunchKernelGGL(k_branch_reduce, dim3(m), dim3(kThreads), 0, s, A, P, nb, m, scale, out);
   return hipGetLastError();
 }
 

@@ -18,6 +18,22 @@ from make_golden import GRID_SETS, load, path_for  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
+
+def parts_circuit(nparts, seed):
+    """nparts parts of three qubits: Haar U(2) layers, a CZ inside every part
+    and 5 CZs between parts (32 branches)."""
+    rng = np.random.default_rng(seed)
+    n = 3 * nparts
+    side = np.arange(n) // 3
+    recs = []
+    cross = [(0, 3), (1, 4 if nparts > 2 else 5), (2, 6), (4, 7), (3, 3 * nparts - 1)]
+    for layer in range(3):
+        recs += [W.gate(W.OP_U, q, u=W.haar_u2(rng)) for q in range(n)]
+        recs += [W.gate(W.OP_CZ, 3 * p, 3 * p + 1 + layer % 2) for p in range(nparts)]
+        if layer < 2:
+            recs += [W.gate(W.OP_CZ, a, b) for a, b in cross[layer * 2: layer * 2 + 2 + layer]]
+    return n, side, W.concat(*recs)
+
 @pytest.fixture(scope="module")
 def J():
     import torch
@@ -163,6 +179,29 @@ def test_branch_amplitudes_small_grids(J, rows, cols, depth, seed, group):
         full = sv.run_circuit(n, circ)
         want = full[z.astype(np.int64)]
         assert np.max(np.abs(got - want)) / np.abs(full).max() < 1e-5
+
+
+@pytest.mark.parametrize("nparts, seed, group", [(3, 5, 0), (4, 6, 3), (3, 7, 1)])
+def test_branch_amplitudes_more_parts(J, nparts, seed, group):
+    # P > 2 parts (Section 4's general partition): against the oracle's
+    # branch sum and the full state vector
+    announce("branch-parts", nparts, seed, group)
+    n, side, circ = parts_circuit(nparts, seed)
+    side = side.astype(np.uint8)
+    z = np.random.default_rng(seed).integers(0, 1 << n, 40, dtype=np.uint64)
+    got = J.juqcs_branch_amplitudes(n, circ, side, z, group_size=group)
+    ob = odec.branch_amplitudes(n, circ, side, z[:8])
+    full = sv.run_circuit(n, circ)
+    scale = np.abs(full).max()
+    assert np.max(np.abs(got[:8] - ob)) / scale < 1e-5
+    assert np.max(np.abs(got - full[z.astype(np.int64)])) / scale < 1e-5
+
+
+def test_branch_rejects_too_many_parts(J):
+    side = np.arange(9, dtype=np.uint8)  # 9 parts
+    with pytest.raises(J.JuqcsError) as e:
+        J.juqcs_branch_amplitudes(9, W.concat(W.gate(W.OP_H, 0)), side, [0])
+    assert e.value.status == J.ERR_ARG
 
 
 def test_branch_ghz48_closed_form(J, golden):

@@ -18,6 +18,22 @@ R2 = 1.0 / math.sqrt(2.0)
 
 
 # ---- literal textbook actions (Section 2, Eq. (1); Section 4 for CZ) -------
+
+def parts_circuit(nparts, seed):
+    """nparts parts of three qubits: Haar U(2) layers, a CZ inside every part
+    and 5 CZs between parts (32 branches)."""
+    rng = np.random.default_rng(seed)
+    n = 3 * nparts
+    side = np.arange(n) // 3
+    recs = []
+    cross = [(0, 3), (1, 4 if nparts > 2 else 5), (2, 6), (4, 7), (3, 3 * nparts - 1)]
+    for layer in range(3):
+        recs += [W.gate(W.OP_U, q, u=W.haar_u2(rng)) for q in range(n)]
+        recs += [W.gate(W.OP_CZ, 3 * p, 3 * p + 1 + layer % 2) for p in range(nparts)]
+        if layer < 2:
+            recs += [W.gate(W.OP_CZ, a, b) for a, b in cross[layer * 2: layer * 2 + 2 + layer]]
+    return n, side, W.concat(*recs)
+
 @pytest.mark.parametrize(
     "rec, start, expect",
     [
@@ -185,6 +201,19 @@ def test_eq3_matches_full_state(rows, cols, depth, seed):
     zs = np.arange(1 << n) if n <= 8 else np.random.default_rng(seed).integers(0, 1 << n, 64)
     got = dec.branch_amplitudes(n, circ, side, zs)
     assert len(dec.crossing_czs(circ, side)) >= 1
+    assert np.max(np.abs(got - full[zs])) < 1e-12
+
+
+@pytest.mark.parametrize("nparts, seed", [(3, 5), (4, 6)])
+def test_eq3_more_parts_matches_full_state(nparts, seed):
+    # Section 4 allows any partition into mutually exclusive subsets: three
+    # or four parts of three qubits with 5 crossing CZs, against the full
+    # state vector
+    n, side, circ = parts_circuit(nparts, seed)
+    full = sv.run_circuit(n, circ)
+    zs = np.random.default_rng(seed).integers(0, 1 << n, 48)
+    got = dec.branch_amplitudes(n, circ, side, zs)
+    assert int(side.max()) + 1 == nparts
     assert np.max(np.abs(got - full[zs])) < 1e-12
 
 
