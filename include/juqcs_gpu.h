@@ -338,11 +338,12 @@ juqcs_status juqcs_batch_destroy(juqcs_batch* b);
  * both of its qubits at that position.  Every branch's P part-states are
  * simulated in C64 as batches (group_size branches resident at a time,
  * 0 = automatic), and the result 2^-m sum_b prod_p A_{b,p}(z_p) is summed
- * in FP64 on the device (Eq. (3)).  Only CZ may cross between parts
+ * in FP64 on the device (Eq. (3)), in branch order for every coefficient
+ * (the same result for any group size).  Only CZ may cross between parts
  * (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.  out: 2*count doubles (host).
  * Synchronises hip_stream.  The library allocates the device memory this
- * needs (P * 2^m * count complex FP64 partial amplitudes among it) and
- * frees it before returning. */
+ * needs (per group: the part-states and their count gathered amplitudes,
+ * so large counts shrink the group) and frees it before returning. */
 juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates,
                                      size_t gate_count, const uint8_t* side,
                                      const uint64_t* z, size_t count,

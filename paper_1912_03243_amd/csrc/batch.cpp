@@ -583,11 +583,13 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
   for (int p = 0; p < P; ++p) zh[p].assign(count, 0);
   for (size_t k = 0; k < count; ++k)
     for (int q = 0; q < n; ++q) zh[side[q]][k] |= ((z[k] >> q) & 1) << local[q];
-  // group size: branches resident at a time (P part-states each)
+  // group size: branches resident at a time (P part-states each, plus their
+  // gathered amplitudes and indices)
+  const size_t cnt = std::max<size_t>(count, 1);
   size_t sbytes[kMaxParts], per_branch = 0;
   for (int p = 0; p < P; ++p) {
     sbytes[p] = (size_t)8 << nloc[p];
-    per_branch += align256(sbytes[p]);
+    per_branch += align256(sbytes[p]) + cnt * (2 * sizeof(double) + sizeof(uint64_t));
   }
   long long G = group_size > 0 ? group_size : 0;
   if (G == 0) {
@@ -597,15 +599,16 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     G = std::max<long long>(1, (long long)(budget / per_branch));
   }
   G = std::min(G, nb);
-  // A[p][b][k]: amplitude zh[p][k] of part p in branch b (FP64 pairs)
-  const size_t cnt = std::max<size_t>(count, 1);
+  // gathered part amplitudes of one group: tmp[(p g + j) count + k]; the
+  // branch sum runs sequentially over b into acc (independent of G)
   char* states = nullptr;
-  double *dA = nullptr, *dOut = nullptr;
+  double *tmp = nullptr, *acc = nullptr;
   uint64_t* dz = nullptr;
   hipError_t e = hipMalloc((void**)&states, per_branch * G);
-  if (e == hipSuccess) e = hipMalloc((void**)&dA, (size_t)P * nb * cnt * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&dOut, cnt * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tmp, (size_t)P * G * cnt * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&acc, cnt * 2 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&dz, (size_t)P * G * cnt * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemsetAsync(acc, 0, cnt * 2 * sizeof(double), s);
   juqcs_status rc = JUQCS_OK;
   if (e != hipSuccess) rc = hip_fail(e, "branch hipMalloc");
   std::vector<uint64_t> zlist;
@@ -648,17 +651,10 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     if (rc == JUQCS_OK) rc = run_device(&B, s);
     if (rc == JUQCS_OK && count > 0) {
       e = hipMemcpyAsync(dz, zlist.data(), zlist.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-      // gather into a temporary, then copy each part's rows into A (branch-major)
-      double* tmp = nullptr;
-      if (e == hipSuccess) e = hipMalloc((void**)&tmp, (size_t)B.count * count * 2 * sizeof(double));
       if (e == hipSuccess)
         e = launch_batch_gather(B.states, B.d_state_off, B.d_nq, B.d_pos, B.count, (int)count, dz, tmp, s);
-      const size_t rows = (size_t)g * count * 2 * sizeof(double);
-      for (int p = 0; p < P && e == hipSuccess; ++p)
-        e = hipMemcpyAsync(dA + ((size_t)p * nb + b0) * count * 2, tmp + (size_t)p * g * count * 2, rows,
-                           hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = launch_branch_accum(tmp, P, g, (int)count, acc, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (tmp) (void)hipFree(tmp);
       if (e != hipSuccess) rc = hip_fail(e, "branch gather");
     }
     if (rc == JUQCS_OK) {
@@ -668,15 +664,15 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     free_batch(&B);
   }
   if (rc == JUQCS_OK && count > 0) {
-    e = launch_branch_reduce(dA, P, nb, (int)count, std::ldexp(1.0, -m), dOut, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(out, dOut, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(out, acc, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) rc = hip_fail(e, "branch reduce");
+    if (e != hipSuccess) rc = hip_fail(e, "branch result copy");
+    const double scale = std::ldexp(1.0, -m);
+    for (size_t i = 0; rc == JUQCS_OK && i < 2 * count; ++i) out[i] *= scale;
   }
   (void)hipFree(states);
-  (void)hipFree(dA);
-  (void)hipFree(dOut);
+  (void)hipFree(tmp);
+  (void)hipFree(acc);
   (void)hipFree(dz);
   return rc;
 }

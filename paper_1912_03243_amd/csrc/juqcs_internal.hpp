@@ -236,8 +236,8 @@ hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, co
                                hipStream_t s);
 hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, const int32_t* nq,
                               int count, double* out, hipStream_t s);
-hipError_t launch_branch_reduce(const double* A, int P, long long nb, int m, double scale,
-                                double* out, hipStream_t s);
+hipError_t launch_branch_accum(const double* A, int P, long long g, int m, double* acc,
+                               hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Host-side planning (planner.cpp)

@@ -288,19 +288,20 @@ __global__ __launch_bounds__(kThreads) void k_batch_norms(const char* __restrict
   }
 }
 
-// Eq. (3): out[k] = scale * sum_b prod_p A[p][b][k] (complex, FP64; the
-// parts multiplied in order p = 0..P-1), one block per requested
-// coefficient, fixed-order tree over b.
-__global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __restrict__ A, int P,
-                                                            long long nb, int m, double scale,
-                                                            double* __restrict__ out) {
-  __shared__ double sre[kThreads], sim[kThreads];
-  const int k = blockIdx.x;
-  double re = 0.0, im = 0.0;
-  for (long long b = threadIdx.x; b < nb; b += kThreads) {
-    double pr = A[2 * (b * m + k)], pi = A[2 * (b * m + k) + 1];
+// Eq. (3), one group of g branches: acc[k] += prod_p A[(p g + j) m + k] for
+// j = 0..g-1 in order (complex, FP64; parts multiplied in order p =
+// 0..P-1).  One thread per coefficient, so the sum over all branches runs
+// in branch order whatever the group size.
+__global__ __launch_bounds__(kThreads) void k_branch_accum(const double* __restrict__ A, int P,
+                                                           long long g, int m,
+                                                           double* __restrict__ acc) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m) return;
+  double re = acc[2 * k], im = acc[2 * k + 1];
+  for (long long j = 0; j < g; ++j) {
+    double pr = A[2 * (j * m + k)], pi = A[2 * (j * m + k) + 1];
     for (int p = 1; p < P; ++p) {
-      const size_t o = 2 * (((size_t)p * nb + b) * m + k);
+      const size_t o = 2 * (((size_t)p * g + j) * m + k);
       const double br = A[o], bi = A[o + 1];
       const double t = pr * br - pi * bi;
       pi = pr * bi + pi * br;
@@ -309,20 +310,8 @@ __global__ __launch_bounds__(kThreads) void k_branch_reduce(const double* __rest
     re += pr;
     im += pi;
   }
-  sre[threadIdx.x] = re;
-  sim[threadIdx.x] = im;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sre[threadIdx.x] += sre[threadIdx.x + s];
-      sim[threadIdx.x] += sim[threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[2 * k] = scale * sre[0];
-    out[2 * k + 1] = scale * sim[0];
-  }
+  acc[2 * k] = re;
+  acc[2 * k + 1] = im;
 }
 
 }  // namespace
@@ -373,10 +362,11 @@ hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, con
   return hipGetLastError();
 }
 
-hipError_t launch_branch_reduce(const double* A, int P, long long nb, int m, double scale,
-                                double* out, hipStream_t s) {
+hipError_t launch_branch_accum(const double* A, int P, long long g, int m, double* acc,
+                               hipStream_t s) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_branch_reduce, dim3(m), dim3(kThreads), 0, s, A, P, nb, m, scale, out);
+  hipLaunchKernelGGL(k_branch_accum, dim3((m + kThreads - 1) / kThreads), dim3(kThreads), 0, s, A, P, g,
+                     m, acc);
   return hipGetLastError();
 }
 

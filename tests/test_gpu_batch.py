@@ -197,6 +197,24 @@ def test_branch_amplitudes_more_parts(J, nparts, seed, group):
     assert np.max(np.abs(got - full[z.astype(np.int64)])) / scale < 1e-5
 
 
+@pytest.mark.parametrize("group", [0, 2])
+def test_branch_every_coefficient(J, group):
+    # all 2^16 coefficients of a 16-qubit grid at once (the gathered
+    # amplitudes of a branch group scale with their count), against the
+    # full state vector; the sum runs in branch order, so the group size
+    # changes nothing
+    announce("branch-all", group)
+    circ, side = W.grid_circuit(4, 4, 8, 11, max_cross=4)
+    n = 16
+    z = np.arange(1 << n, dtype=np.uint64)
+    got = J.juqcs_branch_amplitudes(n, circ, side, z, group_size=group)
+    full = sv.run_circuit(n, circ)
+    assert np.max(np.abs(got - full)) / np.abs(full).max() < 1e-5
+    if group:
+        ref = J.juqcs_branch_amplitudes(n, circ, side, z)
+        assert np.array_equal(got, ref)
+
+
 def test_branch_rejects_too_many_parts(J):
     side = np.arange(9, dtype=np.uint8)  # 9 parts
     with pytest.raises(J.JuqcsError) as e:
