@@ -10,12 +10,18 @@ different parts turns the circuit into a sum over branches s in {-1, 1}^S of
 tensor products of per-part subcircuits W_p(s), and Eq. (3) gives each
 requested coefficient as  <z|C|0> = sum_s prod_p <z_p| W_p(s) |0_p>.
 
+A CNOT whose qubits lie in different parts is the CZ between them with a
+Hadamard on its target before and after (H X H = Z), so it is decomposed as
+that CZ; the GHZ circuit of Sections 3 and 4 consists of such CNOTs.
+
 Readings taken where the paper is silent:
 * branch index b in [0, 2^S): bit k of b selects s_k for the k-th crossing
-  CZ in circuit order, bit value 0 -> s_k = +1, 1 -> s_k = -1;
+  gate (CZ or CNOT) in circuit order, bit value 0 -> s_k = +1, 1 -> s_k = -1;
 * the factor 1/2 of every decomposed CZ is applied once, as 2^-S, in the sum;
 * D(s_k) is applied to both qubits of the k-th crossing CZ at that CZ's
-  position in the circuit;
+  position in the circuit; for a crossing CNOT(c, t) the target's part
+  applies H, D(s_k), H on t at that position and the control's part D(s_k)
+  on c;
 * inside a part, qubits keep their relative order (local index = rank of the
   qubit among the part's qubits), and z_p collects z's bits in that order.
 """
@@ -46,17 +52,17 @@ def eq2_sum(x: complex = ROOT_X) -> np.ndarray:
     return 0.5 * total
 
 
-def crossing_czs(circuit, part) -> list:
-    """Positions of the decomposed CZs (qubits in different parts), in circuit
-    order.  Any other multi-qubit gate across parts is rejected."""
+def crossing_gates(circuit, part) -> list:
+    """Positions of the decomposed gates (CZ or CNOT with qubits in different
+    parts), in circuit order.  A controlled phase across parts is rejected."""
     pos = []
     for k, rec in enumerate(circuit):
         op = int(rec["op"])
         if op in (G.OP_CNOT, G.OP_CZ, G.OP_CP):
             a, b = int(rec["q0"]), int(rec["q1"])
             if part[a] != part[b]:
-                if op != G.OP_CZ:
-                    raise ValueError("only CZ gates may cross partitions")
+                if op == G.OP_CP:
+                    raise ValueError("only CZ and CNOT gates may cross partitions")
                 pos.append(k)
     return pos
 
@@ -85,9 +91,14 @@ def subcircuit_states(n: int, circuit, part, branch: int, x: complex = ROOT_X):
             if part[a] != part[b]:
                 s = 1 if ((branch >> k) & 1) == 0 else -1
                 d = branch_diag(s, x)
+                pb = part[b]
+                if op == G.OP_CNOT:  # target b: H before the CZ's factor
+                    sv.apply_1q(states[pb], len(qubits[pb]), local[b], G.H)
                 for q in (a, b):
                     p = part[q]
                     sv.apply_1q(states[p], len(qubits[p]), local[q], d)
+                if op == G.OP_CNOT:  # and after it
+                    sv.apply_1q(states[pb], len(qubits[pb]), local[b], G.H)
                 k += 1
                 continue
             p = part[a]
@@ -115,7 +126,7 @@ def branch_amplitudes(n: int, circuit, part, zs, x: complex = ROOT_X) -> np.ndar
     ``zs``, summed over all 2^S branches with math.fsum on real and imaginary
     parts separately."""
     zs = [int(z) for z in zs]
-    S = len(crossing_czs(circuit, part))
+    S = len(crossing_gates(circuit, part))
     terms = np.empty((1 << S, len(zs)), dtype=np.complex128)
     for b in range(1 << S):
         states, qubits = subcircuit_states(n, circuit, part, b, x)
@@ -130,14 +141,16 @@ def branch_amplitudes(n: int, circuit, part, zs, x: complex = ROOT_X) -> np.ndar
 
 
 def projector_amplitudes(n: int, circuit, part, zs) -> np.ndarray:
-    """Independent second branch sum: CZ_{i,j} = |0><0|_i (x) I_j + |1><1|_i (x) Z_j.
-    Branch bit 0 -> (|0><0| on i, I on j), bit 1 -> (|1><1| on i, Z on j).
-    No prefactor.  Must agree with ``branch_amplitudes``."""
+    """Independent second branch sum: CZ_{i,j} = |0><0|_i (x) I_j + |1><1|_i (x) Z_j
+    and CNOT_{c,t} = |0><0|_c (x) I_t + |1><1|_c (x) X_t (no Hadamards).
+    Branch bit 0 -> (|0><0| on the first qubit, I on the second), bit 1 ->
+    (|1><1| on the first, Z or X on the second).  No prefactor.  Must agree
+    with ``branch_amplitudes``."""
     part = np.asarray(part)
     nparts = int(part.max()) + 1
     qubits, local = _local_maps(part, nparts)
     zs = [int(z) for z in zs]
-    S = len(crossing_czs(circuit, part))
+    S = len(crossing_gates(circuit, part))
     p0 = np.diag([1.0, 0.0]).astype(np.complex128)
     p1 = np.diag([0.0, 1.0]).astype(np.complex128)
     terms = np.empty((1 << S, len(zs)), dtype=np.complex128)
@@ -154,7 +167,7 @@ def projector_amplitudes(n: int, circuit, part, zs) -> np.ndarray:
                 pa, pb = part[a], part[b]
                 sv.apply_1q(states[pa], len(qubits[pa]), local[a], p1 if bit else p0)
                 if bit:
-                    sv.apply_1q(states[pb], len(qubits[pb]), local[b], G.Z)
+                    sv.apply_1q(states[pb], len(qubits[pb]), local[b], G.X if op == G.OP_CNOT else G.Z)
                 k += 1
                 continue
             p = part[a]

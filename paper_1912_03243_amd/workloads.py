@@ -278,6 +278,53 @@ def bitstrings(n: int, count: int, seed: int) -> np.ndarray:
     return rng.integers(0, 1 << n, size=count, dtype=np.uint64)
 
 
+def bitstrings_wide(n: int, count: int, seed: int) -> np.ndarray:
+    """count uniform n-bit strings as (count, ceil(n/64)) little-endian uint64
+    words (qubit q is bit q % 64 of word q // 64)."""
+    words = (n + 63) // 64
+    rng = _rng(seed)
+    z = rng.integers(0, np.iinfo(np.uint64).max, size=(count, words), dtype=np.uint64,
+                     endpoint=True)
+    top = n - 64 * (words - 1)
+    if top < 64:
+        z[:, -1] &= np.uint64((1 << top) - 1)
+    return z
+
+
+def words_to_ints(z: np.ndarray) -> list:
+    """Rows of little-endian uint64 words as Python integers."""
+    z = np.atleast_2d(np.asarray(z, dtype=np.uint64))
+    return [sum(int(w) << (64 * i) for i, w in enumerate(row)) for row in z]
+
+
+def ints_to_words(zs, n: int) -> np.ndarray:
+    """Python integers (< 2^n) as rows of little-endian uint64 words."""
+    words = (n + 63) // 64
+    out = np.zeros((len(zs), words), dtype=np.uint64)
+    for k, z in enumerate(zs):
+        for i in range(words):
+            out[k, i] = (int(z) >> (64 * i)) & ((1 << 64) - 1)
+    return out
+
+
+def block_parts(n: int, nparts: int) -> np.ndarray:
+    """side[q] for nparts blocks of consecutive qubits (sizes differ by at
+    most one, lower parts larger)."""
+    base, extra = divmod(n, nparts)
+    sizes = [base + (1 if p < extra else 0) for p in range(nparts)]
+    return np.repeat(np.arange(nparts, dtype=np.uint8), sizes)
+
+
+def haar_layer(n: int, seed: int) -> np.ndarray:
+    """One Haar U(2) gate on every qubit (qubit order)."""
+    us = haar_u2_many(_rng(seed), n)
+    g = empty_circuit(n)
+    g["op"] = OP_U
+    g["q0"] = np.arange(n)
+    g["u"] = us
+    return g
+
+
 def inverse_circuit_records(gates: np.ndarray) -> np.ndarray:
     """Records of the reversed circuit with every gate replaced by its inverse.
     H, X, Y, Z, CNOT and CZ are self-inverse; S, T and U become OP_U with the

@@ -44,7 +44,7 @@ def make_grid(name):
     circ, side = W.grid_circuit(rows, cols, depth, cseed, max_cross=mcross)
     n = rows * cols
     z = W.bitstrings(n, count, seed=zseed)
-    S = len(decomposition.crossing_czs(circ, side))
+    S = len(decomposition.crossing_gates(circ, side))
     t0 = time.time()
     amps = decomposition.branch_amplitudes(n, circ, side, z)
     dt = time.time() - t0
@@ -66,7 +66,7 @@ def make(name):
     circ = W.layered_brick(n, layers, seed=cseed)
     z = W.bitstrings(n, count, seed=zseed)
     side = np.array([0] * (n // 2) + [1] * (n - n // 2), dtype=np.uint8)
-    S = len(decomposition.crossing_czs(circ, side))
+    S = len(decomposition.crossing_gates(circ, side))
     t0 = time.time()
     amps = decomposition.branch_amplitudes(n, circ, side, z)
     dt = time.time() - t0

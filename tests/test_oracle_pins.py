@@ -200,7 +200,7 @@ def test_eq3_matches_full_state(rows, cols, depth, seed):
     full = sv.run_circuit(n, circ)
     zs = np.arange(1 << n) if n <= 8 else np.random.default_rng(seed).integers(0, 1 << n, 64)
     got = dec.branch_amplitudes(n, circ, side, zs)
-    assert len(dec.crossing_czs(circ, side)) >= 1
+    assert len(dec.crossing_gates(circ, side)) >= 1
     assert np.max(np.abs(got - full[zs])) < 1e-12
 
 
@@ -243,6 +243,72 @@ def test_ghz_via_decomposition(golden):
     assert abs(got[0] - golden["ghz.amp_all_zero"]) < 1e-15
     assert abs(got[1] - golden["ghz.amp_all_one"]) < 1e-15
     assert abs(got[2]) < 1e-15
+
+
+def cnot_cut_circuit(seed: int):
+    """8 qubits cut 4|4, Haar layers with CNOTs across the cut in both
+    directions and one CZ: 5 crossing gates."""
+    n = 8
+    side = W.block_parts(n, 2)
+    recs = [W.haar_layer(n, seed)]
+    recs += [W.gate(W.OP_CNOT, 1, 5), W.gate(W.OP_CNOT, 6, 2), W.gate(W.OP_CNOT, 0, 1)]
+    recs += [W.haar_layer(n, seed + 1), W.gate(W.OP_CZ, 3, 4), W.gate(W.OP_CNOT, 7, 0)]
+    recs += [W.haar_layer(n, seed + 2), W.gate(W.OP_CNOT, 2, 7), W.gate(W.OP_CNOT, 4, 5)]
+    return n, side, W.concat(*recs)
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_eq3_crossing_cnots_match_full_state_and_projectors(seed):
+    # a crossing CNOT is its CZ between Hadamards on the target; the
+    # projector sum uses |1><1| (x) X directly, with no Hadamards
+    n, side, circ = cnot_cut_circuit(seed)
+    assert len(dec.crossing_gates(circ, side)) == 5
+    full = sv.run_circuit(n, circ)
+    zs = np.arange(1 << n)
+    a = dec.branch_amplitudes(n, circ, side, zs)
+    b = dec.projector_amplitudes(n, circ, side, zs)
+    assert np.max(np.abs(a - full)) < 1e-12
+    assert np.max(np.abs(b - full)) < 1e-12
+
+
+def test_ghz128_paper_values(golden):
+    # Section 4's scaling run: the GHZ circuit on 128 qubits, here in eight
+    # parts of 16 (7 crossing CNOTs); the coefficients of |0...0> and
+    # |1...1> are 1/sqrt(2).  Every other coefficient is zero: exactly when a
+    # part's bits are mixed (each part state lives on its all-0 and all-1
+    # strings), up to rounding when every part is uniform but the parts differ
+    # (the branch sum cancels).
+    n = 128
+    side = W.block_parts(n, 8)
+    ones = (1 << n) - 1
+    uniform_mixed = [sum(((1 << 16) - 1) << (16 * p) for p in range(8) if (m >> p) & 1)
+                     for m in (0b00000001, 0b10110010, 0b01111111)]
+    rand = W.words_to_ints(W.bitstrings_wide(n, 3, 7))
+    got = dec.branch_amplitudes(n, W.ghz(n), side, [0, ones] + uniform_mixed + rand)
+    assert abs(got[0] - golden["ghz.amp_all_zero"]) < 1e-14
+    assert abs(got[1] - golden["ghz.amp_all_one"]) < 1e-14
+    assert np.max(np.abs(got[2:5])) < 1e-14
+    assert np.all(got[5:] == 0)
+
+
+def test_ghz_then_haar_layer_closed_form():
+    # U_0 (x) ... (x) U_{n-1} applied to (|0...0> + |1...1>)/sqrt(2) has the
+    # coefficient (prod_q U_q[z_q, 0] + prod_q U_q[z_q, 1]) / sqrt(2) at z: a
+    # closed form for any z, here at n = 96 in six parts (5 crossing CNOTs)
+    n = 96
+    layer = W.haar_layer(n, 21)
+    circ = W.concat(W.ghz(n), layer)
+    side = W.block_parts(n, 6)
+    zs = W.words_to_ints(W.bitstrings_wide(n, 6, 22)) + [0, (1 << n) - 1]
+    got = dec.branch_amplitudes(n, circ, side, zs)
+    u = layer["u"].reshape(n, 2, 2, 2)
+    u = u[..., 0] + 1j * u[..., 1]
+    for k, z in enumerate(zs):
+        bits = [(z >> q) & 1 for q in range(n)]
+        a0 = np.prod([u[q, bits[q], 0] for q in range(n)])
+        a1 = np.prod([u[q, bits[q], 1] for q in range(n)])
+        want = (a0 + a1) / math.sqrt(2.0)
+        assert abs(got[k] - want) <= 1e-12 * abs(want)
 
 
 # ---- reference two-byte codec -------------------------------------------------------

@@ -29,10 +29,10 @@ def test_haar_matrices_are_unitary():
 
 def test_grid_cut_has_ten_crossing_czs():
     g, side = W.grid_circuit()
-    assert len(dec.crossing_czs(g, side)) == 10
+    assert len(dec.crossing_gates(g, side)) == 10
     assert side.tolist() == [0] * 24 + [1] * 24
     full, _ = W.grid_circuit(max_cross=None)
-    assert len(dec.crossing_czs(full, side)) == 12
+    assert len(dec.crossing_gates(full, side)) == 12
     assert len(full) - len(g) == 2
 
 
