@@ -119,10 +119,12 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only the reference copy kernel (counter calibration)")
     ap.add_argument("--workload", default="brick30",
-                    choices=["brick30", "batch4096", "grid48", "large34", "large36", "ghz33", "ghz36"],
+                    choices=["brick30", "batch4096", "grid48", "ghz128", "large34", "large36", "ghz33",
+                             "ghz36"],
                     help="brick30 is the headline configuration; the others are the batched, "
                          "decomposition and large-state configurations")
     ap.add_argument("--count", type=int, default=4096, help="batch4096: number of circuits")
+    ap.add_argument("--coeffs", type=int, default=27, help="ghz128: log2 of the extracted coefficients")
     ap.add_argument("--autotune", type=int, default=0, help="batch4096: timed-trial autotuner")
     ap.add_argument("--tile-fuse", type=int, default=0, help="in-pass fusion width (0 = default)")
     ap.add_argument("--tile-bits", type=int, default=0, help="tile bits (0 = default)")
@@ -384,6 +386,40 @@ def other_workload(args, juqcs, W, dev, stream):
                                    "branches in FP64 (value counts half-circuit gates of every branch)",
                        "gates": int(len(circ)), "branches": 1 << m, "bitstrings": int(z.size)},
             "check": {"sum_abs2_of_1024_amps": float(np.sum(np.abs(out["a"]) ** 2))},
+        })
+    elif args.workload == "ghz128":
+        # Section 4's scaling run at its largest size: the GHZ circuit on 128
+        # qubits by the Eq. (3) decomposition, M = 2^27 coefficients; the
+        # paper reports the elapsed time per gate
+        n, nparts = 128, 8
+        circ = W.ghz(n)
+        side = W.block_parts(n, nparts)
+        M = 1 << args.coeffs
+        ones = (1 << n) - 1
+        z = W.bitstrings_wide(n, M, seed=1006)
+        z[:2] = W.ints_to_words([0, ones], n)
+        out = {}
+
+        def run():
+            out["a"] = juqcs.juqcs_branch_amplitudes(n, circ, side, z, stream=stream)
+
+        ms = _timed(run, args.steps, args.warmup, stream)
+        m = nparts - 1
+        part_gates = len(circ) - m + 4 * m   # a crossing CNOT: H, diagonal, H on the target, diagonal on the control
+        a = out["a"]
+        res.update({
+            "value": (1 << m) * part_gates / (ms / 1e3), "ms_per_step": ms, "dtype": "f32",
+            "config": {"workload": f"ghz128: GHZ circuit (H(0) + 127 CNOT(i,i+1)) on 128 qubits in "
+                                   f"{nparts} parts of 16, the {m} crossing CNOTs decomposed -> "
+                                   f"{1 << m} branches of {nparts} complex64 part-states; 2^{args.coeffs} "
+                                   "coefficients (|0...0>, |1...1> and seeded random strings) summed "
+                                   "over branches in FP64; host bitstrings in, host coefficients out "
+                                   "(value counts part-circuit gates of every branch)",
+                       "gates": int(len(circ)), "branches": 1 << m, "bitstrings": M},
+            "ms_per_gate": ms / len(circ),
+            "coefficients_per_s": M / (ms / 1e3),
+            "check": {"amp_all_zero": float(a[0].real), "amp_all_one": float(a[1].real),
+                      "nonzero_random": int(np.count_nonzero(a[2:]))},
         })
     elif args.workload in ("ghz33", "ghz36"):
         # the paper's benchmark circuit (Section 3): H on qubit 0, CNOT(i, i+1)

@@ -332,23 +332,38 @@ juqcs_status juqcs_batch_destroy(juqcs_batch* b);
  * qubits are split in P parts by side[q] in {0, ..., P-1} (2 <= P <= 8,
  * each part 1..30 qubits; Section 4's partition into mutually exclusive
  * subsets).  Every CZ whose qubits lie in different parts is decomposed
- * with Eq. (2) (x = pi/4 - (i/2) asinh 1); branch b in [0, 2^m) uses
- * s_k = +1 if bit k of b is 0, else -1, for the k-th crossing CZ in circuit
- * order, and applies diag(e^{i(x s_k - pi/4)}, e^{-i(x s_k - pi/4)}) to
- * both of its qubits at that position.  Every branch's P part-states are
- * simulated in C64 as batches (group_size branches resident at a time,
- * 0 = automatic), and the result 2^-m sum_b prod_p A_{b,p}(z_p) is summed
- * in FP64 on the device (Eq. (3)), in branch order for every coefficient
- * (the same result for any group size).  Only CZ may cross between parts
- * (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.  out: 2*count doubles (host).
- * Synchronises hip_stream.  The library allocates the device memory this
- * needs (per group: the part-states and their count gathered amplitudes,
- * so large counts shrink the group) and frees it before returning. */
+ * with Eq. (2) (x = pi/4 - (i/2) asinh 1), and so is every such CNOT, as
+ * its CZ between Hadamards on the target (H X H = Z).  Branch b in
+ * [0, 2^m) uses s_k = +1 if bit k of b is 0, else -1, for the k-th
+ * crossing gate in circuit order, and applies
+ * diag(e^{i(x s_k - pi/4)}, e^{-i(x s_k - pi/4)}) to both of its qubits at
+ * that position.  Every branch's P part-states are simulated in C64 as
+ * batches (group_size branches resident at a time, 0 = automatic), and the
+ * result 2^-m sum_b prod_p A_{b,p}(z_p) is summed in FP64 on the device
+ * (Eq. (3)), in branch order for every coefficient (the same result for any
+ * group size).  Only CZ and CNOT may cross between parts
+ * (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.  z: count uint64 (host);
+ * out: 2*count doubles (host).  Synchronises hip_stream.  The library
+ * allocates the device memory this needs (the part-states of a group, the
+ * per-part indices and the running sum: 4 P + 16 bytes per bitstring) and
+ * frees it before returning. */
 juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates,
                                      size_t gate_count, const uint8_t* side,
                                      const uint64_t* z, size_t count,
                                      int group_size, double* out,
                                      void* hip_stream);
+
+/* The same for circuits of up to 240 qubits (eight parts of 30), such as
+ * Section 4's GHZ circuit on 128 qubits: bitstring k is the words uint64
+ * z[k*words .. k*words + words) (little-endian: qubit q is bit q % 64 of
+ * word q / 64), ceil(n/64) <= words <= 4, bits at n and above zero
+ * (JUQCS_ERR_ARG otherwise); count <= 2^31.  Other arguments, results and
+ * errors as for juqcs_branch_amplitudes. */
+juqcs_status juqcs_branch_amplitudes_wide(int n, const juqcs_gate* gates,
+                                          size_t gate_count, const uint8_t* side,
+                                          const uint64_t* z, int words, size_t count,
+                                          int group_size, double* out,
+                                          void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Utilities

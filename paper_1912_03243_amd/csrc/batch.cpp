@@ -140,7 +140,6 @@ void free_batch(juqcs_batch* b) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kMaxBatchQubits = 32;  // layout entries per circuit
-constexpr int kMaxParts = 8;         // parts of the Eq. (3) decomposition
 
 // Layout entries of circuit c from a schedule's final positions.
 void set_layout(juqcs_batch* B, int c, const std::vector<int>& final_pos) {
@@ -516,34 +515,43 @@ void branch_diag(int s, C* d) {
   d[3] = {e1.real(), e1.imag()};
 }
 
-}  // namespace
-
-extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count,
-                                                const uint8_t* side, const uint64_t* z,
-                                                size_t count, int group_size, double* out,
-                                                void* hip_stream) {
-  if (n < 2 || n > 62) return fail(JUQCS_ERR_ARG, "n must be in [2, 62]");
+// Eq. (3) for count bitstrings of words 64-bit words each (see
+// juqcs_branch_amplitudes_wide).
+juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count, const uint8_t* side,
+                               const uint64_t* z, int words, size_t count, int group_size, double* out,
+                               hipStream_t s) {
+  if (n < 2 || n > kBranchMaxQubits) return fail(JUQCS_ERR_ARG, "n must be in [2, 240]");
+  if (words < (n + 63) / 64 || words > kBranchMaxWords)
+    return fail(JUQCS_ERR_ARG, "words must be in [ceil(n / 64), 4]");
   if (!side || (count > 0 && (!z || !out)) || (gate_count > 0 && !gates))
     return fail(JUQCS_ERR_ARG, "null argument");
-  hipStream_t s = (hipStream_t)hip_stream;
+  if (count > (size_t)1 << 31) return fail(JUQCS_ERR_SIZE, "at most 2^31 bitstrings");
   // parts and local qubit numbers (ascending order inside a part)
   int P = 0;
   for (int q = 0; q < n; ++q) {
-    if (side[q] >= kMaxParts) return fail(JUQCS_ERR_ARG, "side[q] must be < " + std::to_string(kMaxParts));
+    if (side[q] >= kBranchMaxParts)
+      return fail(JUQCS_ERR_ARG, "side[q] must be < " + std::to_string(kBranchMaxParts));
     P = std::max(P, side[q] + 1);
   }
-  int local[64], nloc[kMaxParts] = {};
+  int local[kBranchMaxQubits], nloc[kBranchMaxParts] = {};
   for (int q = 0; q < n; ++q) local[q] = nloc[side[q]]++;
   if (P < 2) return fail(JUQCS_ERR_ARG, "at least two parts");
   for (int p = 0; p < P; ++p)
     if (nloc[p] < 1 || nloc[p] > 30) return fail(JUQCS_ERR_ARG, "each part needs 1..30 qubits");
-  for (size_t k = 0; k < count; ++k)
-    if ((z[k] >> n) != 0) return fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
-  // part circuits with placeholder diagonals at every crossing CZ
-  std::vector<Gate> part[kMaxParts];
-  std::vector<std::pair<int, int>> slot[kMaxParts];  // (gate index in part, crossing number)
+  // bits at or above n must be clear (only the words that can hold them)
+  for (int w = n / 64; w < words; ++w) {
+    const int lo = std::max(0, n - 64 * w);
+    const uint64_t bad = lo >= 64 ? 0 : ~0ull << lo;
+    for (size_t k = 0; k < count; ++k)
+      if (z[k * words + w] & bad) return fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
+  }
+  // part circuits with placeholder diagonals at every crossing gate; a
+  // crossing CNOT is its CZ between Hadamards on the target (H X H = Z)
+  std::vector<Gate> part[kBranchMaxParts];
+  std::vector<std::pair<int, int>> slot[kBranchMaxParts];  // (gate index in part, crossing number)
   int m = 0;
   std::string err;
+  const double s2 = 1.0 / std::sqrt(2.0);
   for (size_t i = 0; i < gate_count; ++i) {
     Gate g;
     if (!decode_gate(gates[i], n, &g, &err)) {
@@ -552,8 +560,20 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
                   "gate " + std::to_string(i) + ": " + err);
     }
     if (g.nq == 2 && side[g.q[0]] != side[g.q[1]]) {
-      if (gates[i].op != JUQCS_OP_CZ)
-        return fail(JUQCS_ERR_UNSUPPORTED, "only CZ gates may cross between parts");
+      const int op = gates[i].op;
+      if (op != JUQCS_OP_CZ && op != JUQCS_OP_CNOT)
+        return fail(JUQCS_ERR_UNSUPPORTED, "only CZ and CNOT gates may cross between parts");
+      if (m == 20) return fail(JUQCS_ERR_UNSUPPORTED, "at most 20 crossing gates");
+      const int t = g.q[1], pt = side[t];  // CNOT: q1 is the target
+      Gate h{};
+      h.nq = 1;
+      h.q[0] = local[t];
+      h.q[1] = -1;
+      h.m[0] = {s2, 0};
+      h.m[1] = {s2, 0};
+      h.m[2] = {s2, 0};
+      h.m[3] = {-s2, 0};
+      if (op == JUQCS_OP_CNOT) part[pt].push_back(h);
       for (int j = 0; j < 2; ++j) {
         const int q = g.q[j], p = side[q];
         Gate d{};
@@ -565,6 +585,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
         slot[p].push_back({(int)part[p].size(), m});
         part[p].push_back(d);
       }
+      if (op == JUQCS_OP_CNOT) part[pt].push_back(h);
       ++m;
       continue;
     }
@@ -572,25 +593,59 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     for (int j = 0; j < g.nq; ++j) g.q[j] = local[g.q[j]];
     part[p].push_back(g);
   }
-  if (m > 20) return fail(JUQCS_ERR_UNSUPPORTED, "at most 20 crossing CZ gates");
+  if (count == 0) return JUQCS_OK;
   const long long nb = 1ll << m;
   // template plans, one per part; branches only change the diagonal values
-  TilePlan tmpl[kMaxParts];
-  TileSchedule tsched[kMaxParts];
+  TilePlan tmpl[kBranchMaxParts];
+  TileSchedule tsched[kBranchMaxParts];
   for (int p = 0; p < P; ++p) plan_circuit(nloc[p], part[p], 2, true, &tmpl[p], &tsched[p]);
-  // bitstring parts
-  std::vector<uint64_t> zh[kMaxParts];
-  for (int p = 0; p < P; ++p) zh[p].assign(count, 0);
-  for (size_t k = 0; k < count; ++k)
-    for (int q = 0; q < n; ++q) zh[side[q]][k] |= ((z[k] >> q) & 1) << local[q];
-  // group size: branches resident at a time (P part-states each, plus their
-  // gathered amplitudes and indices)
-  const size_t cnt = std::max<size_t>(count, 1);
-  size_t sbytes[kMaxParts], per_branch = 0;
+  // split table: each part's qubits and their physical bits in the final layout
+  std::vector<int32_t> tab(kBranchTabInts, 0);
+  {
+    int32_t* first = tab.data();
+    int32_t* qs = first + kBranchMaxParts + 1;
+    int32_t* phys = qs + kBranchMaxQubits;
+    int o = 0;
+    for (int p = 0; p < P; ++p) {
+      first[p] = o;
+      for (int q = 0; q < n; ++q) {
+        if (side[q] != p) continue;
+        const int r = local[q];
+        qs[o] = q;
+        phys[o] = r < (int)tsched[p].final_pos.size() ? tsched[p].final_pos[r] : r;
+        ++o;
+      }
+    }
+    first[P] = o;
+  }
+  size_t sbytes[kBranchMaxParts], per_branch = 0;
   for (int p = 0; p < P; ++p) {
     sbytes[p] = (size_t)8 << nloc[p];
-    per_branch += align256(sbytes[p]) + cnt * (2 * sizeof(double) + sizeof(uint64_t));
+    per_branch += align256(sbytes[p]);
   }
+  // bitstrings -> per-part indices on the device; acc holds the running sum
+  uint64_t* dz = nullptr;
+  uint32_t* zp = nullptr;
+  int32_t* dtab = nullptr;
+  double* acc = nullptr;
+  char* states = nullptr;
+  hipError_t e = hipSuccess;
+  {
+    e = hipMalloc((void**)&dz, count * words * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&zp, (size_t)P * count * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&dtab, tab.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&acc, count * 2 * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dz, z, count * words * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_branch_split(dz, words, (long long)count, P, dtab, zp, s);
+    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, count * 2 * sizeof(double), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dz);
+    dz = nullptr;
+  }
+  // group size: branches whose P part-states are resident at a time
   long long G = group_size > 0 ? group_size : 0;
   if (G == 0) {
     size_t freeb = 0, totalb = 0;
@@ -599,25 +654,14 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     G = std::max<long long>(1, (long long)(budget / per_branch));
   }
   G = std::min(G, nb);
-  // gathered part amplitudes of one group: tmp[(p g + j) count + k]; the
-  // branch sum runs sequentially over b into acc (independent of G)
-  char* states = nullptr;
-  double *tmp = nullptr, *acc = nullptr;
-  uint64_t* dz = nullptr;
-  hipError_t e = hipMalloc((void**)&states, per_branch * G);
-  if (e == hipSuccess) e = hipMalloc((void**)&tmp, (size_t)P * G * cnt * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&acc, cnt * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&dz, (size_t)P * G * cnt * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMemsetAsync(acc, 0, cnt * 2 * sizeof(double), s);
+  if (e == hipSuccess) e = hipMalloc((void**)&states, per_branch * G);
   juqcs_status rc = JUQCS_OK;
-  if (e != hipSuccess) rc = hip_fail(e, "branch hipMalloc");
-  std::vector<uint64_t> zlist;
+  if (e != hipSuccess) rc = hip_fail(e, "branch set-up");
   for (long long b0 = 0; rc == JUQCS_OK && b0 < nb; b0 += G) {
     const long long g = std::min(G, nb - b0);
     juqcs_batch B;
     B.count = (int)(P * g);
     std::vector<TilePlan> plans(B.count);
-    zlist.assign((size_t)B.count * count, 0);
     for (long long j = 0; j < g; ++j) {
       const long long br = b0 + j;
       for (int p = 0; p < P; ++p) {
@@ -631,9 +675,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
         TilePlan pl = tmpl[p];
         rebuild_mats(tg, &pl);
         // circuits [p g, (p + 1) g): part p of each branch of the group
-        const int c = (int)(p * g + j);
-        plans[c] = std::move(pl);
-        std::memcpy(zlist.data() + (size_t)c * count, zh[p].data(), count * sizeof(uint64_t));
+        plans[(size_t)(p * g + j)] = std::move(pl);
       }
     }
     B.n.assign(B.count, 0);
@@ -649,30 +691,42 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
     B.states = states;
     rc = build_device(&B, plans);
     if (rc == JUQCS_OK) rc = run_device(&B, s);
-    if (rc == JUQCS_OK && count > 0) {
-      e = hipMemcpyAsync(dz, zlist.data(), zlist.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-      if (e == hipSuccess)
-        e = launch_batch_gather(B.states, B.d_state_off, B.d_nq, B.d_pos, B.count, (int)count, dz, tmp, s);
-      if (e == hipSuccess) e = launch_branch_accum(tmp, P, g, (int)count, acc, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) rc = hip_fail(e, "branch gather");
-    }
     if (rc == JUQCS_OK) {
-      e = hipStreamSynchronize(s);
-      if (e != hipSuccess) rc = hip_fail(e, "branch batch");
+      const bool last = b0 + g >= nb;
+      e = launch_branch_gather_accum(B.states, B.d_state_off, P, g, zp, (long long)count, acc, last,
+                                     std::ldexp(1.0, -m), s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = hip_fail(e, "branch sum");
     }
     free_batch(&B);
   }
-  if (rc == JUQCS_OK && count > 0) {
+  if (rc == JUQCS_OK) {
     e = hipMemcpyAsync(out, acc, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "branch result copy");
-    const double scale = std::ldexp(1.0, -m);
-    for (size_t i = 0; rc == JUQCS_OK && i < 2 * count; ++i) out[i] *= scale;
   }
   (void)hipFree(states);
-  (void)hipFree(tmp);
+  (void)hipFree(zp);
+  (void)hipFree(dtab);
   (void)hipFree(acc);
-  (void)hipFree(dz);
   return rc;
+}
+
+}  // namespace
+
+extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count,
+                                                const uint8_t* side, const uint64_t* z,
+                                                size_t count, int group_size, double* out,
+                                                void* hip_stream) {
+  if (n < 2 || n > 62) return fail(JUQCS_ERR_ARG, "n must be in [2, 62]");
+  return branch_amplitudes(n, gates, gate_count, side, z, 1, count, group_size, out,
+                           (hipStream_t)hip_stream);
+}
+
+extern "C" juqcs_status juqcs_branch_amplitudes_wide(int n, const juqcs_gate* gates, size_t gate_count,
+                                                     const uint8_t* side, const uint64_t* z, int words,
+                                                     size_t count, int group_size, double* out,
+                                                     void* hip_stream) {
+  return branch_amplitudes(n, gates, gate_count, side, z, words, count, group_size, out,
+                           (hipStream_t)hip_stream);
 }

@@ -236,8 +236,22 @@ hipError_t launch_batch_gather(const char* states, const uint64_t* state_off, co
                                hipStream_t s);
 hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, const int32_t* nq,
                               int count, double* out, hipStream_t s);
-hipError_t launch_branch_accum(const double* A, int P, long long g, int m, double* acc,
-                               hipStream_t s);
+
+// Entangling-gate decomposition (Eq. (3)) on the device.
+constexpr int kBranchMaxParts = 8;    // parts of a decomposition
+constexpr int kBranchMaxQubits = 240; // kBranchMaxParts parts of at most 30 qubits
+constexpr int kBranchMaxWords = 4;    // 64-bit words per bitstring
+// Bitstring split table (int32 entries): [0, P] part starts into the qubit
+// lists, then kBranchMaxQubits qubit numbers (part by part, ascending), then
+// the physical bit of each in its part state.
+constexpr int kBranchTabInts = kBranchMaxParts + 1 + 2 * kBranchMaxQubits;
+hipError_t launch_branch_split(const uint64_t* z, int words, long long count, int P,
+                               const int32_t* tab, uint32_t* zp, hipStream_t s);
+// acc[k] += sum over the group's g branches (in order) of prod_p
+// psi_{p g + j}[zp[p count + k]] (FP64); the last group multiplies by scale.
+hipError_t launch_branch_gather_accum(const char* states, const uint64_t* state_off, int P,
+                                      long long g, const uint32_t* zp, long long count,
+                                      double* acc, bool last, double scale, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Host-side planning (planner.cpp)

@@ -292,23 +292,62 @@ __global__ __launch_bounds__(kThreads) void k_batch_norms(const char* __restrict
 // j = 0..g-1 in order (complex, FP64; parts multiplied in order p =
 // 0..P-1).  One thread per coefficient, so the sum over all branches runs
 // in branch order whatever the group size.
-__global__ __launch_bounds__(kThreads) void k_branch_accum(const double* __restrict__ A, int P,
-                                                           long long g, int m,
-                                                           double* __restrict__ acc) {
-  const int k = blockIdx.x * kThreads + threadIdx.x;
-  if (k >= m) return;
+// Per-part bitstrings z_p of Eq. (3), each mapped through its part state's
+// layout: zp[p count + k] (one thread per bitstring).
+__global__ __launch_bounds__(kThreads) void k_branch_split(const uint64_t* __restrict__ z, int words,
+                                                           long long count, int P,
+                                                           const int32_t* __restrict__ tab,
+                                                           uint32_t* __restrict__ zp) {
+  const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= count) return;
+  const uint64_t* row = z + k * words;
+  uint64_t w[kBranchMaxWords];
+#pragma unroll
+  for (int i = 0; i < kBranchMaxWords; ++i) w[i] = i < words ? row[i] : 0;
+  const int32_t* qs = tab + kBranchMaxParts + 1;
+  const int32_t* phys = qs + kBranchMaxQubits;
+  for (int p = 0; p < P; ++p) {
+    uint32_t v = 0;
+    for (int i = tab[p]; i < tab[p + 1]; ++i) {
+      const int q = qs[i], wi = q >> 6;  // wave-uniform
+      const uint64_t x = wi == 0 ? w[0] : wi == 1 ? w[1] : wi == 2 ? w[2] : w[3];
+      v |= (uint32_t)((x >> (q & 63)) & 1) << phys[i];
+    }
+    zp[(size_t)p * count + k] = v;
+  }
+}
+
+// Eq. (3) over one group of g branches, one thread per bitstring: the
+// product over parts in FP64, added to acc in branch order.
+__global__ __launch_bounds__(kThreads) void k_branch_gather_accum(
+    const char* __restrict__ states, const uint64_t* __restrict__ state_off, int P, long long g,
+    const uint32_t* __restrict__ zp, long long count, double* __restrict__ acc, int last,
+    double scale) {
+  const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= count) return;
+  uint32_t zi[kBranchMaxParts];
+#pragma unroll
+  for (int p = 0; p < kBranchMaxParts; ++p) zi[p] = p < P ? zp[(size_t)p * count + k] : 0u;
   double re = acc[2 * k], im = acc[2 * k + 1];
   for (long long j = 0; j < g; ++j) {
-    double pr = A[2 * (j * m + k)], pi = A[2 * (j * m + k) + 1];
-    for (int p = 1; p < P; ++p) {
-      const size_t o = 2 * (((size_t)p * g + j) * m + k);
-      const double br = A[o], bi = A[o + 1];
-      const double t = pr * br - pi * bi;
-      pi = pr * bi + pi * br;
-      pr = t;
+    const cplx<float> a = reinterpret_cast<const cplx<float>*>(states + state_off[j])[zi[0]];
+    double pr = a.re, pi = a.im;
+#pragma unroll
+    for (int p = 1; p < kBranchMaxParts; ++p) {
+      if (p < P) {
+        const cplx<float> b = reinterpret_cast<const cplx<float>*>(states + state_off[p * g + j])[zi[p]];
+        const double br = b.re, bi = b.im;
+        const double t = pr * br - pi * bi;
+        pi = pr * bi + pi * br;
+        pr = t;
+      }
     }
     re += pr;
     im += pi;
+  }
+  if (last) {
+    re *= scale;
+    im *= scale;
   }
   acc[2 * k] = re;
   acc[2 * k + 1] = im;
@@ -362,11 +401,22 @@ hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, con
   return hipGetLastError();
 }
 
-hipError_t launch_branch_accum(const double* A, int P, long long g, int m, double* acc,
-                               hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_branch_accum, dim3((m + kThreads - 1) / kThreads), dim3(kThreads), 0, s, A, P, g,
-                     m, acc);
+hipError_t launch_branch_split(const uint64_t* z, int words, long long count, int P,
+                               const int32_t* tab, uint32_t* zp, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (words < 1 || words > kBranchMaxWords || P < 1 || P > kBranchMaxParts) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_branch_split, dim3((unsigned)((count + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     s, z, words, count, P, tab, zp);
+  return hipGetLastError();
+}
+
+hipError_t launch_branch_gather_accum(const char* states, const uint64_t* state_off, int P,
+                                      long long g, const uint32_t* zp, long long count,
+                                      double* acc, bool last, double scale, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (P < 1 || P > kBranchMaxParts || g < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_branch_gather_accum, dim3((unsigned)((count + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, states, state_off, P, g, zp, count, acc, last ? 1 : 0, scale);
   return hipGetLastError();
 }
 

@@ -93,6 +93,8 @@ _SIGS = {
     "juqcs_batch_destroy": [_P],
     "juqcs_branch_amplitudes": [_I, _P, _S, ct.POINTER(ct.c_uint8), ct.POINTER(_U64), _S, _I,
                                 _DP, _P],
+    "juqcs_branch_amplitudes_wide": [_I, _P, _S, ct.POINTER(ct.c_uint8), ct.POINTER(_U64), _I, _S,
+                                     _I, _DP, _P],
     "juqcs_copy": [_P, _P, _S, _P],
 }
 EXPORTED = sorted(list(_SIGS) + ["juqcs_last_error", "juqcs_version"])
@@ -167,16 +169,25 @@ def juqcs_copy(dst, src, nbytes: int, stream=None):
 
 
 def juqcs_branch_amplitudes(n: int, gates, side, z, group_size: int = 0, stream=None) -> np.ndarray:
+    """<z|C|0> by the Eq. (3) decomposition.  z: a 1-D uint64 array of
+    bitstrings (n <= 62), or a (count, words) array of little-endian uint64
+    words (n <= 240, juqcs_branch_amplitudes_wide)."""
     g = _gates(gates)
     side = np.ascontiguousarray(side, dtype=np.uint8)
     z = np.ascontiguousarray(z, dtype=np.uint64)
-    out = np.empty(2 * z.size, dtype=np.float64)
-    _check(_lib.juqcs_branch_amplitudes(n, g.ctypes.data, g.size,
-                                        side.ctypes.data_as(ct.POINTER(ct.c_uint8)),
-                                        z.ctypes.data_as(ct.POINTER(_U64)), z.size, group_size,
-                                        _dptr(out), _stream_handle(stream)),
-           "juqcs_branch_amplitudes")
-    return out[0::2] + 1j * out[1::2]
+    count = z.shape[0] if z.ndim == 2 else z.size
+    out = np.empty(2 * count, dtype=np.float64)
+    sp = side.ctypes.data_as(ct.POINTER(ct.c_uint8))
+    zp = z.ctypes.data_as(ct.POINTER(_U64))
+    if z.ndim == 2:
+        _check(_lib.juqcs_branch_amplitudes_wide(n, g.ctypes.data, g.size, sp, zp, z.shape[1], count,
+                                                 group_size, _dptr(out), _stream_handle(stream)),
+               "juqcs_branch_amplitudes_wide")
+    else:
+        _check(_lib.juqcs_branch_amplitudes(n, g.ctypes.data, g.size, sp, zp, count, group_size,
+                                            _dptr(out), _stream_handle(stream)),
+               "juqcs_branch_amplitudes")
+    return out.view(np.complex128)  # (re, im) pairs
 
 
 # ---- State --------------------------------------------------------------------

@@ -278,6 +278,18 @@ def bitstrings(n: int, count: int, seed: int) -> np.ndarray:
     return rng.integers(0, 1 << n, size=count, dtype=np.uint64)
 
 
+def cnot_cut_circuit(seed: int):
+    """(n, side, gates): 8 qubits cut 4|4, three Haar layers with CNOTs
+    across the cut in both directions and one CZ (5 crossing gates)."""
+    n = 8
+    side = block_parts(n, 2)
+    recs = [haar_layer(n, seed)]
+    recs += [gate(OP_CNOT, 1, 5), gate(OP_CNOT, 6, 2), gate(OP_CNOT, 0, 1)]
+    recs += [haar_layer(n, seed + 1), gate(OP_CZ, 3, 4), gate(OP_CNOT, 7, 0)]
+    recs += [haar_layer(n, seed + 2), gate(OP_CNOT, 2, 7), gate(OP_CNOT, 4, 5)]
+    return n, side, concat(*recs)
+
+
 def bitstrings_wide(n: int, count: int, seed: int) -> np.ndarray:
     """count uniform n-bit strings as (count, ceil(n/64)) little-endian uint64
     words (qubit q is bit q % 64 of word q // 64)."""

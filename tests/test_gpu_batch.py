@@ -251,8 +251,117 @@ def test_branch_grid48_against_stored_oracle_values(J):
     assert rel_l2(got, want) < 1e-5
 
 
-def test_branch_rejects_non_cz_crossing(J):
+def test_branch_rejects_other_crossings(J):
+    # only CZ and CNOT are decomposed: a controlled phase across the cut is not
     side = np.array([0, 0, 1, 1], dtype=np.uint8)
     with pytest.raises(J.JuqcsError) as e:
-        J.juqcs_branch_amplitudes(4, W.concat(W.gate(W.OP_CNOT, 1, 2)), side, [0])
+        J.juqcs_branch_amplitudes(4, W.concat(W.gate(W.OP_CP, 1, 2, theta=0.3)), side, [0])
     assert e.value.status == J.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("seed, group", [(11, 0), (12, 2)])
+def test_branch_crossing_cnots(J, seed, group):
+    # CNOTs across the cut in both directions (each its CZ between Hadamards
+    # on the target) and a CZ: all 256 coefficients against the full state
+    # vector and the oracle's branch sum
+    announce("branch-cnot", seed, group)
+    n, side, circ = W.cnot_cut_circuit(seed)
+    z = np.arange(1 << n, dtype=np.uint64)
+    got = J.juqcs_branch_amplitudes(n, circ, side, z, group_size=group)
+    full = sv.run_circuit(n, circ)
+    assert_c64(got, full)
+    ob = odec.branch_amplitudes(n, circ, side, z[:16])
+    assert np.max(np.abs(got[:16] - ob)) / np.abs(full).max() < 1e-5
+
+
+def test_branch_ghz128_paper_values(J, golden):
+    # Section 4's scaling circuit at its largest size: GHZ on 128 qubits in
+    # eight parts of 16 (7 crossing CNOTs, 128 branches).  |0...0> and
+    # |1...1> have 1/sqrt(2); strings with uniform parts that differ cancel
+    # in the branch sum; every other string is exactly zero.
+    n = 128
+    announce("branch-ghz128")
+    side = W.block_parts(n, 8)
+    ones = (1 << n) - 1
+    mixed = [sum(((1 << 16) - 1) << (16 * p) for p in range(8) if (m >> p) & 1)
+             for m in (0b00000001, 0b10110010, 0b01111111, 0b10000000)]
+    head = W.ints_to_words([0, ones] + mixed, n)
+    z = np.concatenate([head, W.bitstrings_wide(n, 1 << 16, 5)])
+    got = J.juqcs_branch_amplitudes(n, W.ghz(n), side, z)
+    assert abs(got[0] - golden["ghz.amp_all_zero"]) < 1e-6
+    assert abs(got[1] - golden["ghz.amp_all_one"]) < 1e-6
+    assert np.max(np.abs(got[2:6])) < 1e-6
+    assert np.all(got[6:] == 0)
+
+
+def ghz_blocks(n, blocks):
+    """H on the first qubit of every block [a, b) of consecutive qubits, then
+    the CNOT chain a -> a+1 -> ... -> b-1: a product of GHZ states."""
+    recs = []
+    for a, b in blocks:
+        recs.append(W.gate(W.OP_H, a))
+        recs += [W.gate(W.OP_CNOT, i, i + 1) for i in range(a, b - 1)]
+    return W.concat(*recs)
+
+
+def ghz_haar_closed_form(layer, zs, n, blocks):
+    """prod over blocks of (prod_q U_q[z_q, 0] + prod_q U_q[z_q, 1]) / sqrt(2):
+    the coefficient at z of U_0 (x) ... (x) U_{n-1} applied to the product of
+    the blocks' GHZ states."""
+    u = layer["u"].reshape(n, 2, 2, 2)
+    u = u[..., 0] + 1j * u[..., 1]
+    out = []
+    for z in zs:
+        amp = 1.0 + 0.0j
+        for a, b in blocks:
+            a0 = np.prod([u[q, (z >> q) & 1, 0] for q in range(a, b)])
+            a1 = np.prod([u[q, (z >> q) & 1, 1] for q in range(a, b)])
+            amp *= (a0 + a1) / math.sqrt(2.0)
+        out.append(amp)
+    return np.array(out)
+
+
+# n = 100 puts a part across the 64-bit word boundary; n = 240 is eight parts
+# of 30 qubits (8 GiB part states) with two crossing CNOTs
+WIDE_CASES = [(96, 6, 0, [(0, 96)]), (100, 5, 3, [(0, 100)]), (128, 8, 0, [(0, 128)]),
+              (240, 8, 0, [(0, 30), (30, 65), (65, 90), (90, 120), (120, 150), (150, 185),
+                           (185, 210), (210, 240)])]
+
+
+@pytest.mark.parametrize("n, nparts, group, blocks", WIDE_CASES)
+def test_branch_wide_ghz_haar_closed_form(J, n, nparts, group, blocks):
+    # GHZ states followed by a Haar U(2) on every qubit have a closed form
+    # at any z
+    announce("branch-wide", n, nparts, group)
+    layer = W.haar_layer(n, 21)
+    circ = W.concat(ghz_blocks(n, blocks), layer)
+    side = W.block_parts(n, nparts)
+    zs = W.words_to_ints(W.bitstrings_wide(n, 62, 22)) + [0, (1 << n) - 1]
+    got = J.juqcs_branch_amplitudes(n, circ, side, W.ints_to_words(zs, n), group_size=group)
+    assert_c64(got, ghz_haar_closed_form(layer, zs, n, blocks))
+    if n == 96:  # and the oracle's branch sum
+        ob = odec.branch_amplitudes(n, circ, side, zs[:3])
+        assert_c64(got[:3], ob)
+
+
+def test_branch_wide_matches_narrow(J):
+    # the same bitstrings as one word each: identical results
+    announce("branch-wide-narrow")
+    n, side, circ = parts_circuit(3, 5)
+    side = side.astype(np.uint8)
+    z = np.random.default_rng(5).integers(0, 1 << n, 64, dtype=np.uint64)
+    a = J.juqcs_branch_amplitudes(n, circ, side, z)
+    b = J.juqcs_branch_amplitudes(n, circ, side, z.reshape(-1, 1))
+    c = J.juqcs_branch_amplitudes(n, circ, side, np.stack([z, np.zeros_like(z)], axis=1))
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("n, words, top", [(100, 2, 1 << 40), (128, 1, 0), (241, 4, 0)])
+def test_branch_wide_rejects(J, n, words, top):
+    # a bit at or above n, too few words, more than 240 qubits
+    side = W.block_parts(n, 8) if n <= 240 else np.zeros(n, dtype=np.uint8)
+    z = np.zeros((1, words), dtype=np.uint64)
+    z[0, -1] = top
+    with pytest.raises(J.JuqcsError) as e:
+        J.juqcs_branch_amplitudes(n, W.ghz(n), side, z)
+    assert e.value.status == J.ERR_ARG

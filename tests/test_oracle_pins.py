@@ -245,23 +245,11 @@ def test_ghz_via_decomposition(golden):
     assert abs(got[2]) < 1e-15
 
 
-def cnot_cut_circuit(seed: int):
-    """8 qubits cut 4|4, Haar layers with CNOTs across the cut in both
-    directions and one CZ: 5 crossing gates."""
-    n = 8
-    side = W.block_parts(n, 2)
-    recs = [W.haar_layer(n, seed)]
-    recs += [W.gate(W.OP_CNOT, 1, 5), W.gate(W.OP_CNOT, 6, 2), W.gate(W.OP_CNOT, 0, 1)]
-    recs += [W.haar_layer(n, seed + 1), W.gate(W.OP_CZ, 3, 4), W.gate(W.OP_CNOT, 7, 0)]
-    recs += [W.haar_layer(n, seed + 2), W.gate(W.OP_CNOT, 2, 7), W.gate(W.OP_CNOT, 4, 5)]
-    return n, side, W.concat(*recs)
-
-
 @pytest.mark.parametrize("seed", [11, 12])
 def test_eq3_crossing_cnots_match_full_state_and_projectors(seed):
     # a crossing CNOT is its CZ between Hadamards on the target; the
     # projector sum uses |1><1| (x) X directly, with no Hadamards
-    n, side, circ = cnot_cut_circuit(seed)
+    n, side, circ = W.cnot_cut_circuit(seed)
     assert len(dec.crossing_gates(circ, side)) == 5
     full = sv.run_circuit(n, circ)
     zs = np.arange(1 << n)
