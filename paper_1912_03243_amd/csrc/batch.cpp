@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "juqcs_internal.hpp"
@@ -618,17 +619,15 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     }
     first[P] = o;
   }
-  size_t sbytes[kBranchMaxParts], per_branch = 0;
-  for (int p = 0; p < P; ++p) {
-    sbytes[p] = (size_t)8 << nloc[p];
-    per_branch += align256(sbytes[p]);
-  }
+  size_t sbytes[kBranchMaxParts];
+  for (int p = 0; p < P; ++p) sbytes[p] = align256((size_t)8 << nloc[p]);
   // bitstrings -> per-part indices on the device; acc holds the running sum
   uint64_t* dz = nullptr;
   uint32_t* zp = nullptr;
   int32_t* dtab = nullptr;
   double* acc = nullptr;
   char* states = nullptr;
+  void* dsum = nullptr;  // per-group branch table of the sum kernel
   hipError_t e = hipSuccess;
   {
     e = hipMalloc((void**)&dz, count * words * sizeof(uint64_t));
@@ -645,26 +644,73 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     (void)hipFree(dz);
     dz = nullptr;
   }
-  // group size: branches whose P part-states are resident at a time
-  long long G = group_size > 0 ? group_size : 0;
-  if (G == 0) {
+  // A part state depends only on the branch bits of the crossings that touch
+  // its part, so the branches of a group that agree on those bits share it:
+  // each group simulates its distinct part states once.  Groups take
+  // branches in order while the distinct states fit the memory budget (or
+  // group_size branches when that is given).
+  uint64_t xmask[kBranchMaxParts] = {};
+  for (int p = 0; p < P; ++p)
+    for (auto& sl : slot[p]) xmask[p] |= 1ull << sl.second;
+  size_t budget = 0;
+  {
     size_t freeb = 0, totalb = 0;
     (void)hipMemGetInfo(&freeb, &totalb);
-    const size_t budget = std::min<size_t>(freeb / 2, (size_t)64 << 30);
-    G = std::max<long long>(1, (long long)(budget / per_branch));
+    budget = std::min<size_t>(freeb / 2, (size_t)64 << 30);
   }
-  G = std::min(G, nb);
-  if (e == hipSuccess) e = hipMalloc((void**)&states, per_branch * G);
+  struct Group {
+    long long b0 = 0, g = 0;
+    std::vector<long long> rep[kBranchMaxParts];  // a branch of each distinct state, per part
+    std::vector<int32_t> idx;                    // g x P: state of (branch, part) within its part
+    size_t bytes = 0;
+  };
+  std::vector<Group> groups;
+  size_t max_bytes = 0;
+  {
+    std::unordered_map<uint64_t, int32_t> seen[kBranchMaxParts];
+    long long b = 0;
+    while (b < nb) {
+      Group gr;
+      gr.b0 = b;
+      for (int p = 0; p < P; ++p) seen[p].clear();
+      while (b < nb && (group_size <= 0 || gr.g < group_size)) {
+        size_t extra = 0;
+        for (int p = 0; p < P; ++p)
+          if (!seen[p].count(b & xmask[p])) extra += sbytes[p];
+        if (gr.g > 0 && group_size <= 0 && gr.bytes + extra > budget) break;
+        for (int p = 0; p < P; ++p) {
+          auto it = seen[p].find(b & xmask[p]);
+          if (it == seen[p].end()) {
+            it = seen[p].emplace(b & xmask[p], (int32_t)gr.rep[p].size()).first;
+            gr.rep[p].push_back(b);
+          }
+          gr.idx.push_back(it->second);
+        }
+        gr.bytes += extra;
+        ++gr.g;
+        ++b;
+      }
+      max_bytes = std::max(max_bytes, gr.bytes);
+      groups.push_back(std::move(gr));
+    }
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&states, max_bytes);
   juqcs_status rc = JUQCS_OK;
   if (e != hipSuccess) rc = hip_fail(e, "branch set-up");
-  for (long long b0 = 0; rc == JUQCS_OK && b0 < nb; b0 += G) {
-    const long long g = std::min(G, nb - b0);
+  for (size_t gi = 0; rc == JUQCS_OK && gi < groups.size(); ++gi) {
+    const Group& gr = groups[gi];
+    // circuits part by part: first[p] .. first[p + 1]
+    int32_t first[kBranchMaxParts + 1] = {};
+    for (int p = 0; p < P; ++p) first[p + 1] = first[p] + (int32_t)gr.rep[p].size();
     juqcs_batch B;
-    B.count = (int)(P * g);
+    B.count = first[P];
     std::vector<TilePlan> plans(B.count);
-    for (long long j = 0; j < g; ++j) {
-      const long long br = b0 + j;
-      for (int p = 0; p < P; ++p) {
+    B.n.assign(B.count, 0);
+    B.state_off.assign(B.count, 0);
+    uint64_t off = 0;
+    for (int p = 0; p < P; ++p)
+      for (size_t r = 0; r < gr.rep[p].size(); ++r) {
+        const long long br = gr.rep[p][r];
         std::vector<Gate> hg = part[p];
         for (auto& sl : slot[p]) branch_diag(((br >> sl.second) & 1) ? -1 : 1, hg[sl.first].m);
         // the plan's ops refer to the schedule's relabeled gate copies
@@ -674,27 +720,52 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
             std::memcpy(tg[t].m, hg[tsched[p].tsrc[t]].m, sizeof(tg[t].m));
         TilePlan pl = tmpl[p];
         rebuild_mats(tg, &pl);
-        // circuits [p g, (p + 1) g): part p of each branch of the group
-        plans[(size_t)(p * g + j)] = std::move(pl);
+        const int c = first[p] + (int)r;
+        plans[c] = std::move(pl);
+        B.n[c] = nloc[p];
+        B.state_off[c] = off;
+        off += sbytes[p];
+        set_layout(&B, c, tsched[p].final_pos);
       }
-    }
-    B.n.assign(B.count, 0);
-    B.state_off.assign(B.count, 0);
-    uint64_t off = 0;
-    for (int c = 0; c < B.count; ++c) {
-      const int p = (int)(c / g);
-      B.n[c] = nloc[p];
-      B.state_off[c] = off;
-      off += align256(sbytes[p]);
-    }
-    for (int c = 0; c < B.count; ++c) set_layout(&B, c, tsched[c / g].final_pos);
     B.states = states;
     rc = build_device(&B, plans);
     if (rc == JUQCS_OK) rc = run_device(&B, s);
     if (rc == JUQCS_OK) {
-      const bool last = b0 + g >= nb;
-      e = launch_branch_gather_accum(B.states, B.d_state_off, P, g, zp, (long long)count, acc, last,
-                                     std::ldexp(1.0, -m), s);
+      // the branch table: the circuit of every (branch, part), as bytes of
+      // one word per branch for the on-chip sum, else as int32 entries
+      const bool lds = B.count <= kBranchSumValues;
+      std::vector<uint64_t> t8;
+      std::vector<int32_t> t32;
+      if (lds) {
+        t8.assign(gr.g, 0);
+        for (long long j = 0; j < gr.g; ++j)
+          for (int p = 0; p < P; ++p)
+            t8[j] |= (uint64_t)(first[p] + gr.idx[j * P + p]) << (8 * p);
+      } else {
+        t32.resize((size_t)gr.g * P);
+        for (long long j = 0; j < gr.g; ++j)
+          for (int p = 0; p < P; ++p) t32[j * P + p] = first[p] + gr.idx[j * P + p];
+      }
+      const size_t tbytes = lds ? t8.size() * 8 : t32.size() * 4;
+      (void)hipFree(dsum);
+      dsum = nullptr;
+      e = hipMalloc(&dsum, tbytes);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dsum, lds ? (const void*)t8.data() : (const void*)t32.data(), tbytes,
+                           hipMemcpyHostToDevice, s);
+      const bool last = gi + 1 == groups.size();
+      const double scale = std::ldexp(1.0, -m);
+      if (e == hipSuccess) {
+        if (lds) {
+          BranchParts bp{};
+          for (int p = 0; p <= P; ++p) bp.first[p] = first[p];
+          e = launch_branch_sum_lds(B.states, B.d_state_off, P, bp, gr.g, (const uint64_t*)dsum, zp,
+                                    (long long)count, acc, last, scale, s);
+        } else {
+          e = launch_branch_gather_accum(B.states, B.d_state_off, P, gr.g, (const int32_t*)dsum, zp,
+                                         (long long)count, acc, last, scale, s);
+        }
+      }
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) rc = hip_fail(e, "branch sum");
     }
@@ -706,6 +777,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     if (e != hipSuccess) rc = hip_fail(e, "branch result copy");
   }
   (void)hipFree(states);
+  (void)hipFree(dsum);
   (void)hipFree(zp);
   (void)hipFree(dtab);
   (void)hipFree(acc);

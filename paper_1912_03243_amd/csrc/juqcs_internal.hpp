@@ -248,10 +248,25 @@ constexpr int kBranchTabInts = kBranchMaxParts + 1 + 2 * kBranchMaxQubits;
 hipError_t launch_branch_split(const uint64_t* z, int words, long long count, int P,
                                const int32_t* tab, uint32_t* zp, hipStream_t s);
 // acc[k] += sum over the group's g branches (in order) of prod_p
-// psi_{p g + j}[zp[p count + k]] (FP64); the last group multiplies by scale.
+// psi_{tab[j P + p]}[zp[p count + k]] (FP64); the last group multiplies by
+// scale.  States are read where they lie.
 hipError_t launch_branch_gather_accum(const char* states, const uint64_t* state_off, int P,
-                                      long long g, const uint32_t* zp, long long count,
-                                      double* acc, bool last, double scale, hipStream_t s);
+                                      long long g, const int32_t* tab, const uint32_t* zp,
+                                      long long count, double* acc, bool last, double scale,
+                                      hipStream_t s);
+// The same sum when the group has at most kBranchSumValues states, stored
+// part by part (part p: circuits first[p] .. first[p + 1]): every thread
+// gathers its coefficient's amplitude of each state into LDS once, then sums
+// the branches from there; byte p of tab8[j] is branch j's circuit of part p.
+constexpr int kBranchSumValues = 48;
+constexpr int kBranchSumThreads = 128;
+struct BranchParts {
+  int32_t first[kBranchMaxParts + 1];
+};
+hipError_t launch_branch_sum_lds(const char* states, const uint64_t* state_off, int P,
+                                 const BranchParts& parts, long long g, const uint64_t* tab8,
+                                 const uint32_t* zp, long long count, double* acc, bool last,
+                                 double scale, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Host-side planning (planner.cpp)

@@ -318,11 +318,12 @@ __global__ __launch_bounds__(kThreads) void k_branch_split(const uint64_t* __res
 }
 
 // Eq. (3) over one group of g branches, one thread per bitstring: the
-// product over parts in FP64, added to acc in branch order.
+// product over parts in FP64, added to acc in branch order.  tab[j P + p] is
+// the circuit holding part p of branch j (wave-uniform loads).
 __global__ __launch_bounds__(kThreads) void k_branch_gather_accum(
     const char* __restrict__ states, const uint64_t* __restrict__ state_off, int P, long long g,
-    const uint32_t* __restrict__ zp, long long count, double* __restrict__ acc, int last,
-    double scale) {
+    const int32_t* __restrict__ tab, const uint32_t* __restrict__ zp, long long count,
+    double* __restrict__ acc, int last, double scale) {
   const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (k >= count) return;
   uint32_t zi[kBranchMaxParts];
@@ -330,16 +331,64 @@ __global__ __launch_bounds__(kThreads) void k_branch_gather_accum(
   for (int p = 0; p < kBranchMaxParts; ++p) zi[p] = p < P ? zp[(size_t)p * count + k] : 0u;
   double re = acc[2 * k], im = acc[2 * k + 1];
   for (long long j = 0; j < g; ++j) {
-    const cplx<float> a = reinterpret_cast<const cplx<float>*>(states + state_off[j])[zi[0]];
+    const int32_t* t = tab + j * P;
+    const cplx<float> a = reinterpret_cast<const cplx<float>*>(states + state_off[t[0]])[zi[0]];
     double pr = a.re, pi = a.im;
 #pragma unroll
     for (int p = 1; p < kBranchMaxParts; ++p) {
       if (p < P) {
-        const cplx<float> b = reinterpret_cast<const cplx<float>*>(states + state_off[p * g + j])[zi[p]];
+        const cplx<float> b = reinterpret_cast<const cplx<float>*>(states + state_off[t[p]])[zi[p]];
         const double br = b.re, bi = b.im;
-        const double t = pr * br - pi * bi;
+        const double u = pr * br - pi * bi;
         pi = pr * bi + pi * br;
-        pr = t;
+        pr = u;
+      }
+    }
+    re += pr;
+    im += pi;
+  }
+  if (last) {
+    re *= scale;
+    im *= scale;
+  }
+  acc[2 * k] = re;
+  acc[2 * k + 1] = im;
+}
+
+// The same sum from LDS: each thread first gathers its coefficient's
+// amplitude of every state of the group (at most kBranchSumValues) into its
+// own LDS column (conflict-free: value c of thread t at c * threads + t),
+// then runs the branches from there.  Threads share nothing, so there is no
+// barrier.  Same arithmetic, in the same order, as k_branch_gather_accum.
+__global__ __launch_bounds__(kBranchSumThreads) void k_branch_sum_lds(
+    const char* __restrict__ states, const uint64_t* __restrict__ state_off, int P, BranchParts bp,
+    long long g, const uint64_t* __restrict__ tab8, const uint32_t* __restrict__ zp, long long count,
+    double* __restrict__ acc, int last, double scale) {
+  extern __shared__ cplx<float> vals[];
+  const int tid = threadIdx.x;
+  const long long k = (long long)blockIdx.x * kBranchSumThreads + tid;
+  if (k >= count) return;
+#pragma unroll
+  for (int p = 0; p < kBranchMaxParts; ++p) {
+    if (p < P) {
+      const uint32_t zi = zp[(size_t)p * count + k];
+      for (int c = bp.first[p]; c < bp.first[p + 1]; ++c)
+        vals[c * kBranchSumThreads + tid] = reinterpret_cast<const cplx<float>*>(states + state_off[c])[zi];
+    }
+  }
+  double re = acc[2 * k], im = acc[2 * k + 1];
+  for (long long j = 0; j < g; ++j) {
+    const uint64_t t = tab8[j];
+    const cplx<float> a = vals[(int)(t & 0xff) * kBranchSumThreads + tid];
+    double pr = a.re, pi = a.im;
+#pragma unroll
+    for (int p = 1; p < kBranchMaxParts; ++p) {
+      if (p < P) {
+        const cplx<float> b = vals[(int)((t >> (8 * p)) & 0xff) * kBranchSumThreads + tid];
+        const double br = b.re, bi = b.im;
+        const double u = pr * br - pi * bi;
+        pi = pr * bi + pi * br;
+        pr = u;
       }
     }
     re += pr;
@@ -411,12 +460,31 @@ hipError_t launch_branch_split(const uint64_t* z, int words, long long count, in
 }
 
 hipError_t launch_branch_gather_accum(const char* states, const uint64_t* state_off, int P,
-                                      long long g, const uint32_t* zp, long long count,
-                                      double* acc, bool last, double scale, hipStream_t s) {
+                                      long long g, const int32_t* tab, const uint32_t* zp,
+                                      long long count, double* acc, bool last, double scale,
+                                      hipStream_t s) {
   if (count == 0) return hipSuccess;
   if (P < 1 || P > kBranchMaxParts || g < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_branch_gather_accum, dim3((unsigned)((count + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, states, state_off, P, g, zp, count, acc, last ? 1 : 0, scale);
+                     dim3(kThreads), 0, s, states, state_off, P, g, tab, zp, count, acc, last ? 1 : 0,
+                     scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_branch_sum_lds(const char* states, const uint64_t* state_off, int P,
+                                 const BranchParts& parts, long long g, const uint64_t* tab8,
+                                 const uint32_t* zp, long long count, double* acc, bool last,
+                                 double scale, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (P < 1 || P > kBranchMaxParts || g < 1) return hipErrorInvalidValue;
+  const int values = parts.first[P];
+  if (values < 1 || values > kBranchSumValues || parts.first[0] != 0) return hipErrorInvalidValue;
+  for (int p = 0; p < P; ++p)
+    if (parts.first[p + 1] < parts.first[p]) return hipErrorInvalidValue;
+  const size_t lds = (size_t)values * kBranchSumThreads * sizeof(cplx<float>);
+  hipLaunchKernelGGL(k_branch_sum_lds, dim3((unsigned)((count + kBranchSumThreads - 1) / kBranchSumThreads)),
+                     dim3(kBranchSumThreads), lds, s, states, state_off, P, parts, g, tab8, zp, count, acc,
+                     last ? 1 : 0, scale);
   return hipGetLastError();
 }
 

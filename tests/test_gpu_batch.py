@@ -215,6 +215,22 @@ def test_branch_every_coefficient(J, group):
         assert np.array_equal(got, ref)
 
 
+def test_branch_sum_paths_agree(J):
+    # a group of more than 48 distinct part states is summed from where the
+    # states lie, a smaller one from LDS: same arithmetic in the same order,
+    # so the same bits
+    announce("branch-sum-paths")
+    circ, side = W.grid_circuit(4, 4, 6, 3, max_cross=None)
+    n = 16
+    assert len(odec.crossing_gates(circ, side)) >= 5   # 2 parts x 2^m states > 48
+    z = np.random.default_rng(3).integers(0, 1 << n, 300, dtype=np.uint64)
+    big = J.juqcs_branch_amplitudes(n, circ, side, z)
+    small = J.juqcs_branch_amplitudes(n, circ, side, z, group_size=4)
+    assert np.array_equal(big, small)
+    full = sv.run_circuit(n, circ)
+    assert_c64(big, full[z.astype(np.int64)])
+
+
 def test_branch_rejects_too_many_parts(J):
     side = np.arange(9, dtype=np.uint8)  # 9 parts
     with pytest.raises(J.JuqcsError) as e:
