@@ -337,11 +337,15 @@ juqcs_status juqcs_batch_destroy(juqcs_batch* b);
  * [0, 2^m) uses s_k = +1 if bit k of b is 0, else -1, for the k-th
  * crossing gate in circuit order, and applies
  * diag(e^{i(x s_k - pi/4)}, e^{-i(x s_k - pi/4)}) to both of its qubits at
- * that position.  Every branch's P part-states are simulated in C64 as
- * batches (group_size branches resident at a time, 0 = automatic), and the
- * result 2^-m sum_b prod_p A_{b,p}(z_p) is summed in FP64 on the device
- * (Eq. (3)), in branch order for every coefficient (the same result for any
- * group size).  Only CZ and CNOT may cross between parts
+ * that position.  The part-states are simulated in C64 as batches: a part
+ * state depends only on the bits of the crossings that touch its part, and
+ * branches that agree on the first crossings share the states' common
+ * gates, so each group of branches (group_size of them, rounded down to a
+ * power of two; 0 = as many as fit) runs every part as a tree that splits
+ * at its crossings.  The result 2^-m sum_b prod_p A_{b,p}(z_p) is summed in
+ * FP64 on the device (Eq. (3)), over the branches in tree order (b with its
+ * bits reversed, ascending) for every coefficient, the same result for any
+ * group size.  Only CZ and CNOT may cross between parts
  * (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.  z: count uint64 (host);
  * out: 2*count doubles (host).  Synchronises hip_stream.  The library
  * allocates the device memory this needs (the part-states of a group, the

@@ -121,6 +121,7 @@ struct juqcs_batch {
   std::vector<int> kin;  // chosen on-chip fusion width per circuit
   std::vector<int8_t> pos;  // kMaxBatchQubits per circuit: physical bit of each qubit at the end
   int8_t* d_pos = nullptr;
+  std::vector<char> keep;   // per circuit (empty: none): start from the state in the buffer, not |0...0>
   hipStream_t last_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -187,7 +188,7 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
       g.circuit = c;
       g.pass = first_pass[c] + i;
       g.chunk_tiles = chunk;
-      g.init = i == 0 ? 1 : 0;
+      g.init = (i == 0 && (B->keep.empty() || !B->keep[c])) ? 1 : 0;
       groups.push_back(g);
     }
     B->tasks += ntiles * (int64_t)p.passes.size();
@@ -595,12 +596,91 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     part[p].push_back(g);
   }
   if (count == 0) return JUQCS_OK;
-  const long long nb = 1ll << m;
-  // template plans, one per part; branches only change the diagonal values
-  TilePlan tmpl[kBranchMaxParts];
-  TileSchedule tsched[kBranchMaxParts];
-  for (int p = 0; p < P; ++p) plan_circuit(nloc[p], part[p], 2, true, &tmpl[p], &tsched[p]);
-  // split table: each part's qubits and their physical bits in the final layout
+  size_t sbytes[kBranchMaxParts];
+  for (int p = 0; p < P; ++p) sbytes[p] = align256((size_t)8 << nloc[p]);
+  // Branches are grouped by the bits of the first L crossings (circuit
+  // order; those bits are fixed within a group, the others free).  Inside a
+  // group a part's states form a tree: the gates before its first crossing
+  // run once, and every run of its crossings (consecutive gates of the
+  // part) splits each state into one copy per setting of their free bits,
+  // which then runs the gates up to the next run.  The leaves are the
+  // part's states for every setting of its own free crossings; branches
+  // that agree on those share a leaf.
+  size_t budget = 0;
+  {
+    size_t freeb = 0, totalb = 0;
+    (void)hipMemGetInfo(&freeb, &totalb);
+    budget = std::min<size_t>(freeb / 2, (size_t)64 << 30);
+  }
+  auto free_bits = [&](int p, int L) {
+    int R = 0;
+    for (auto& sl : slot[p]) R += sl.second >= L ? 1 : 0;
+    return R;
+  };
+  auto leaf_bytes = [&](int L) {
+    size_t t = 0;
+    for (int p = 0; p < P; ++p) t += sbytes[p] << free_bits(p, L);
+    return t;
+  };
+  int L = 0;
+  if (group_size > 0) {
+    int lg = 0;
+    while (lg < m && (2ll << lg) <= group_size) ++lg;
+    L = m - lg;
+  } else {
+    while (L < m && leaf_bytes(L) > budget) ++L;
+  }
+  const long long gsize = 1ll << (m - L), ngroups = 1ll << L;
+  // Segments do not depend on L: a part's circuit is cut before every run of
+  // its crossings, whether their bits are fixed by the group or free, so a
+  // leaf goes through the same plans, and holds the same bits, for any
+  // group size.
+  struct Seg {
+    int g0 = 0, g1 = 0;       // gates [g0, g1) of the part
+    std::vector<int> ks;      // crossings whose diagonals open it
+    int nfree = 0;            // of them with k >= L
+    TilePlan tmpl;            // plan with placeholder diagonals
+    TileSchedule sched;
+  };
+  std::vector<Seg> segs[kBranchMaxParts];
+  std::vector<int> freek[kBranchMaxParts];    // free crossings of each part, circuit order
+  std::vector<int> phys_final[kBranchMaxParts];
+  for (int p = 0; p < P; ++p) {
+    const std::vector<std::pair<int, int>>& fr = slot[p];  // (gate index, crossing), circuit order
+    for (auto& f : fr)
+      if (f.second >= L) freek[p].push_back(f.second);
+    const int ng = (int)part[p].size();
+    Seg pre;
+    pre.g0 = 0;
+    pre.g1 = fr.empty() ? ng : fr[0].first;
+    segs[p].push_back(std::move(pre));
+    for (size_t i = 0; i < fr.size();) {
+      size_t j = i + 1;
+      while (j < fr.size() && fr[j].first == fr[j - 1].first + 1) ++j;
+      Seg sg;
+      sg.g0 = fr[i].first;
+      sg.g1 = j < fr.size() ? fr[j].first : ng;
+      for (size_t t = i; t < j; ++t) {
+        sg.ks.push_back(fr[t].second);
+        sg.nfree += fr[t].second >= L ? 1 : 0;
+      }
+      segs[p].push_back(std::move(sg));
+      i = j;
+    }
+    // plan every segment where the previous one left the qubits
+    std::vector<int> pos(nloc[p]);
+    for (int q = 0; q < nloc[p]; ++q) pos[q] = q;
+    for (Seg& sg : segs[p]) {
+      std::vector<Gate> gs(part[p].begin() + sg.g0, part[p].begin() + sg.g1);
+      for (Gate& g : gs)
+        for (int j = 0; j < g.nq; ++j) g.q[j] = pos[g.q[j]];
+      plan_circuit(nloc[p], gs, 2, true, &sg.tmpl, &sg.sched);
+      if (!sg.sched.final_pos.empty())
+        for (int q = 0; q < nloc[p]; ++q) pos[q] = sg.sched.final_pos[pos[q]];
+    }
+    phys_final[p] = pos;
+  }
+  // split table: each part's qubits and their physical bits at the leaves
   std::vector<int32_t> tab(kBranchTabInts, 0);
   {
     int32_t* first = tab.data();
@@ -611,165 +691,155 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       first[p] = o;
       for (int q = 0; q < n; ++q) {
         if (side[q] != p) continue;
-        const int r = local[q];
         qs[o] = q;
-        phys[o] = r < (int)tsched[p].final_pos.size() ? tsched[p].final_pos[r] : r;
+        phys[o] = phys_final[p][local[q]];
         ++o;
       }
     }
     first[P] = o;
   }
-  size_t sbytes[kBranchMaxParts];
-  for (int p = 0; p < P; ++p) sbytes[p] = align256((size_t)8 << nloc[p]);
+  // leaves part by part: leaf l of part p (bit R-1-i of l = free crossing i)
+  int32_t first[kBranchMaxParts + 1] = {};
+  size_t base[kBranchMaxParts] = {}, total = 0;
+  for (int p = 0; p < P; ++p) {
+    first[p + 1] = first[p] + (1 << freek[p].size());
+    base[p] = total;
+    total += sbytes[p] << freek[p].size();
+  }
+  const int nleaves = first[P];
+  std::vector<uint64_t> leaf_off(nleaves);
+  for (int p = 0; p < P; ++p)
+    for (int l = 0; l < (1 << freek[p].size()); ++l) leaf_off[first[p] + l] = base[p] + (size_t)l * sbytes[p];
+  // the sum runs over branches in tree order: t ascending, where bit
+  // m-1-k of t is crossing k's bit; a group is a range of t
+  auto branch_of = [&](long long t) {
+    long long b = 0;
+    for (int k = 0; k < m; ++k) b |= ((t >> (m - 1 - k)) & 1) << k;
+    return b;
+  };
+  const bool lds = nleaves <= kBranchSumValues;
+  std::vector<uint64_t> t8;
+  std::vector<int32_t> t32;
+  if (lds) t8.assign(gsize, 0);
+  else t32.resize((size_t)gsize * P);
+  for (long long j = 0; j < gsize; ++j) {
+    const long long b = branch_of(j);  // the free bits (the group adds only fixed ones)
+    for (int p = 0; p < P; ++p) {
+      const int R = (int)freek[p].size();
+      int l = 0;
+      for (int i = 0; i < R; ++i) l |= (int)((b >> freek[p][i]) & 1) << (R - 1 - i);
+      if (lds) t8[j] |= (uint64_t)(first[p] + l) << (8 * p);
+      else t32[(size_t)j * P + p] = first[p] + l;
+    }
+  }
   // bitstrings -> per-part indices on the device; acc holds the running sum
   uint64_t* dz = nullptr;
   uint32_t* zp = nullptr;
   int32_t* dtab = nullptr;
   double* acc = nullptr;
   char* states = nullptr;
-  void* dsum = nullptr;  // per-group branch table of the sum kernel
-  hipError_t e = hipSuccess;
-  {
-    e = hipMalloc((void**)&dz, count * words * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&zp, (size_t)P * count * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&dtab, tab.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&acc, count * 2 * sizeof(double));
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(dz, z, count * words * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_branch_split(dz, words, (long long)count, P, dtab, zp, s);
-    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, count * 2 * sizeof(double), s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(dz);
-    dz = nullptr;
-  }
-  // A part state depends only on the branch bits of the crossings that touch
-  // its part, so the branches of a group that agree on those bits share it:
-  // each group simulates its distinct part states once.  Groups take
-  // branches in order while the distinct states fit the memory budget (or
-  // group_size branches when that is given).
-  uint64_t xmask[kBranchMaxParts] = {};
-  for (int p = 0; p < P; ++p)
-    for (auto& sl : slot[p]) xmask[p] |= 1ull << sl.second;
-  size_t budget = 0;
-  {
-    size_t freeb = 0, totalb = 0;
-    (void)hipMemGetInfo(&freeb, &totalb);
-    budget = std::min<size_t>(freeb / 2, (size_t)64 << 30);
-  }
-  struct Group {
-    long long b0 = 0, g = 0;
-    std::vector<long long> rep[kBranchMaxParts];  // a branch of each distinct state, per part
-    std::vector<int32_t> idx;                    // g x P: state of (branch, part) within its part
-    size_t bytes = 0;
-  };
-  std::vector<Group> groups;
-  size_t max_bytes = 0;
-  {
-    std::unordered_map<uint64_t, int32_t> seen[kBranchMaxParts];
-    long long b = 0;
-    while (b < nb) {
-      Group gr;
-      gr.b0 = b;
-      for (int p = 0; p < P; ++p) seen[p].clear();
-      while (b < nb && (group_size <= 0 || gr.g < group_size)) {
-        size_t extra = 0;
-        for (int p = 0; p < P; ++p)
-          if (!seen[p].count(b & xmask[p])) extra += sbytes[p];
-        if (gr.g > 0 && group_size <= 0 && gr.bytes + extra > budget) break;
-        for (int p = 0; p < P; ++p) {
-          auto it = seen[p].find(b & xmask[p]);
-          if (it == seen[p].end()) {
-            it = seen[p].emplace(b & xmask[p], (int32_t)gr.rep[p].size()).first;
-            gr.rep[p].push_back(b);
-          }
-          gr.idx.push_back(it->second);
-        }
-        gr.bytes += extra;
-        ++gr.g;
-        ++b;
-      }
-      max_bytes = std::max(max_bytes, gr.bytes);
-      groups.push_back(std::move(gr));
-    }
-  }
-  if (e == hipSuccess) e = hipMalloc((void**)&states, max_bytes);
+  uint64_t* doff = nullptr;
+  void* dsum = nullptr;
+  const size_t tbytes = lds ? t8.size() * 8 : t32.size() * 4;
+  hipError_t e = hipMalloc((void**)&dz, count * words * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&zp, (size_t)P * count * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&dtab, tab.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&acc, count * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&doff, nleaves * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc(&dsum, tbytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&states, total);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dz, z, count * words * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(doff, leaf_off.data(), nleaves * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dsum, lds ? (const void*)t8.data() : (const void*)t32.data(), tbytes,
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_branch_split(dz, words, (long long)count, P, dtab, zp, s);
+  if (e == hipSuccess) e = hipMemsetAsync(acc, 0, count * 2 * sizeof(double), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dz);
   juqcs_status rc = JUQCS_OK;
   if (e != hipSuccess) rc = hip_fail(e, "branch set-up");
-  for (size_t gi = 0; rc == JUQCS_OK && gi < groups.size(); ++gi) {
-    const Group& gr = groups[gi];
-    // circuits part by part: first[p] .. first[p + 1]
-    int32_t first[kBranchMaxParts + 1] = {};
-    for (int p = 0; p < P; ++p) first[p + 1] = first[p] + (int32_t)gr.rep[p].size();
-    juqcs_batch B;
-    B.count = first[P];
-    std::vector<TilePlan> plans(B.count);
-    B.n.assign(B.count, 0);
-    B.state_off.assign(B.count, 0);
-    uint64_t off = 0;
-    for (int p = 0; p < P; ++p)
-      for (size_t r = 0; r < gr.rep[p].size(); ++r) {
-        const long long br = gr.rep[p][r];
-        std::vector<Gate> hg = part[p];
-        for (auto& sl : slot[p]) branch_diag(((br >> sl.second) & 1) ? -1 : 1, hg[sl.first].m);
-        // the plan's ops refer to the schedule's relabeled gate copies
-        std::vector<Gate> tg = tsched[p].tgates.empty() ? hg : tsched[p].tgates;
-        if (!tsched[p].tgates.empty())
-          for (size_t t = 0; t < tg.size(); ++t)
-            std::memcpy(tg[t].m, hg[tsched[p].tsrc[t]].m, sizeof(tg[t].m));
-        TilePlan pl = tmpl[p];
-        rebuild_mats(tg, &pl);
-        const int c = first[p] + (int)r;
-        plans[c] = std::move(pl);
-        B.n[c] = nloc[p];
-        B.state_off[c] = off;
-        off += sbytes[p];
-        set_layout(&B, c, tsched[p].final_pos);
+  size_t rounds = 0;
+  for (int p = 0; p < P; ++p) rounds = std::max(rounds, segs[p].size());
+  for (long long gi = 0; rc == JUQCS_OK && gi < ngroups; ++gi) {
+    for (size_t r = 0; rc == JUQCS_OK && r < rounds; ++r) {
+      juqcs_batch B;
+      std::vector<TilePlan> plans;
+      for (int p = 0; p < P && rc == JUQCS_OK; ++p) {
+        if (r >= segs[p].size()) continue;
+        const Seg& sg = segs[p][r];
+        const int R = (int)freek[p].size();
+        int done = 0;  // free bits split before this segment
+        for (size_t i = 0; i < r; ++i) done += segs[p][i].nfree;
+        const int rb = sg.nfree, after = R - done - rb;
+        const long long parents = 1ll << done, children = 1ll << rb;
+        for (long long a = 0; a < parents; ++a)
+          for (long long c = 0; c < children; ++c) {
+            const long long leaf = (a << (R - done)) + (c << after);
+            // diagonal values: fixed crossings from the group, this
+            // segment's free ones from the child's bits
+            std::vector<Gate> hg(part[p].begin() + sg.g0, part[p].begin() + sg.g1);
+            for (auto& sl : slot[p]) {
+              if (sl.first < sg.g0 || sl.first >= sg.g1) continue;
+              int bit;
+              if (sl.second < L) {
+                bit = (int)((gi >> (L - 1 - sl.second)) & 1);
+              } else {  // j-th free crossing of the segment (fixed ones come first)
+                const int j = (int)(std::find(sg.ks.begin(), sg.ks.end(), sl.second) - sg.ks.begin()) -
+                              ((int)sg.ks.size() - sg.nfree);
+                bit = (int)((c >> (rb - 1 - j)) & 1);
+              }
+              branch_diag(bit ? -1 : 1, hg[sl.first - sg.g0].m);
+            }
+            std::vector<Gate> tg = sg.sched.tgates.empty() ? hg : sg.sched.tgates;
+            if (!sg.sched.tgates.empty())
+              for (size_t t = 0; t < tg.size(); ++t)
+                std::memcpy(tg[t].m, hg[sg.sched.tsrc[t]].m, sizeof(tg[t].m));
+            TilePlan pl = sg.tmpl;
+            rebuild_mats(tg, &pl);
+            plans.push_back(std::move(pl));
+            B.n.push_back(nloc[p]);
+            B.state_off.push_back(base[p] + (size_t)leaf * sbytes[p]);
+            B.keep.push_back(r > 0 ? 1 : 0);
+            if (r > 0 && c > 0) {  // the child starts as a copy of its parent
+              const size_t from = base[p] + (size_t)(a << (R - done)) * sbytes[p];
+              e = hipMemcpyAsync(states + B.state_off.back(), states + from, sbytes[p],
+                                 hipMemcpyDeviceToDevice, s);
+              if (e != hipSuccess) rc = hip_fail(e, "branch state copy");
+            }
+          }
       }
-    B.states = states;
-    rc = build_device(&B, plans);
-    if (rc == JUQCS_OK) rc = run_device(&B, s);
-    if (rc == JUQCS_OK) {
-      // the branch table: the circuit of every (branch, part), as bytes of
-      // one word per branch for the on-chip sum, else as int32 entries
-      const bool lds = B.count <= kBranchSumValues;
-      std::vector<uint64_t> t8;
-      std::vector<int32_t> t32;
-      if (lds) {
-        t8.assign(gr.g, 0);
-        for (long long j = 0; j < gr.g; ++j)
-          for (int p = 0; p < P; ++p)
-            t8[j] |= (uint64_t)(first[p] + gr.idx[j * P + p]) << (8 * p);
-      } else {
-        t32.resize((size_t)gr.g * P);
-        for (long long j = 0; j < gr.g; ++j)
-          for (int p = 0; p < P; ++p) t32[j * P + p] = first[p] + gr.idx[j * P + p];
-      }
-      const size_t tbytes = lds ? t8.size() * 8 : t32.size() * 4;
-      (void)hipFree(dsum);
-      dsum = nullptr;
-      e = hipMalloc(&dsum, tbytes);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(dsum, lds ? (const void*)t8.data() : (const void*)t32.data(), tbytes,
-                           hipMemcpyHostToDevice, s);
-      const bool last = gi + 1 == groups.size();
-      const double scale = std::ldexp(1.0, -m);
-      if (e == hipSuccess) {
-        if (lds) {
-          BranchParts bp{};
-          for (int p = 0; p <= P; ++p) bp.first[p] = first[p];
-          e = launch_branch_sum_lds(B.states, B.d_state_off, P, bp, gr.g, (const uint64_t*)dsum, zp,
-                                    (long long)count, acc, last, scale, s);
-        } else {
-          e = launch_branch_gather_accum(B.states, B.d_state_off, P, gr.g, (const int32_t*)dsum, zp,
-                                         (long long)count, acc, last, scale, s);
+      B.count = (int)plans.size();
+      B.states = states;
+      if (rc == JUQCS_OK && B.count > 0) {
+        rc = build_device(&B, plans);
+        if (rc == JUQCS_OK) rc = run_device(&B, s);
+        if (rc == JUQCS_OK) {
+          e = hipStreamSynchronize(s);
+          if (e != hipSuccess) rc = hip_fail(e, "branch batch");
         }
+      }
+      free_batch(&B);
+    }
+    if (rc == JUQCS_OK) {
+      const bool last = gi + 1 == ngroups;
+      const double scale = std::ldexp(1.0, -m);
+      if (lds) {
+        BranchParts bp{};
+        for (int p = 0; p <= P; ++p) bp.first[p] = first[p];
+        e = launch_branch_sum_lds(states, doff, P, bp, gsize, (const uint64_t*)dsum, zp, (long long)count,
+                                  acc, last, scale, s);
+      } else {
+        e = launch_branch_gather_accum(states, doff, P, gsize, (const int32_t*)dsum, zp, (long long)count,
+                                       acc, last, scale, s);
       }
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) rc = hip_fail(e, "branch sum");
     }
-    free_batch(&B);
   }
   if (rc == JUQCS_OK) {
     e = hipMemcpyAsync(out, acc, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -778,6 +848,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   }
   (void)hipFree(states);
   (void)hipFree(dsum);
+  (void)hipFree(doff);
   (void)hipFree(zp);
   (void)hipFree(dtab);
   (void)hipFree(acc);
