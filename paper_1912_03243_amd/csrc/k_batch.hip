@@ -288,10 +288,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_norms(const char* __restrict
   }
 }
 
-// Eq. (3), one group of g branches: acc[k] += prod_p A[(p g + j) m + k] for
-// j = 0..g-1 in order (complex, FP64; parts multiplied in order p =
-// 0..P-1).  One thread per coefficient, so the sum over all branches runs
-// in branch order whatever the group size.
 // Per-part bitstrings z_p of Eq. (3), each mapped through its part state's
 // layout: zp[p count + k] (one thread per bitstring).
 __global__ __launch_bounds__(kThreads) void k_branch_split(const uint64_t* __restrict__ z, int words,
@@ -318,8 +314,10 @@ __global__ __launch_bounds__(kThreads) void k_branch_split(const uint64_t* __res
 }
 
 // Eq. (3) over one group of g branches, one thread per bitstring: the
-// product over parts in FP64, added to acc in branch order.  tab[j P + p] is
-// the circuit holding part p of branch j (wave-uniform loads).
+// product over parts in FP64 (p = 0..P-1), added to acc for j = 0..g-1 in
+// order, so the sum over all groups runs in one order whatever the group
+// size.  tab[j P + p] is the state holding part p of branch j (wave-uniform
+// loads).
 __global__ __launch_bounds__(kThreads) void k_branch_gather_accum(
     const char* __restrict__ states, const uint64_t* __restrict__ state_off, int P, long long g,
     const int32_t* __restrict__ tab, const uint32_t* __restrict__ zp, long long count,
