@@ -119,12 +119,14 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only the reference copy kernel (counter calibration)")
     ap.add_argument("--workload", default="brick30",
-                    choices=["brick30", "batch4096", "grid48", "ghz128", "large34", "large36", "ghz33",
-                             "ghz36"],
+                    choices=["brick30", "batch4096", "grid48", "grid42", "ghz128", "large34", "large36",
+                             "ghz33", "ghz36"],
                     help="brick30 is the headline configuration; the others are the batched, "
                          "decomposition and large-state configurations")
     ap.add_argument("--count", type=int, default=4096, help="batch4096: number of circuits")
     ap.add_argument("--coeffs", type=int, default=27, help="ghz128: log2 of the extracted coefficients")
+    ap.add_argument("--cross", type=int, default=12,
+                    help="grid42: crossing CZs kept (S of the decomposition, 2^S branches)")
     ap.add_argument("--group", type=int, default=0,
                     help="grid48, ghz128: branches resident at a time (0 = automatic)")
     ap.add_argument("--autotune", type=int, default=0, help="batch4096: timed-trial autotuner")
@@ -391,6 +393,37 @@ def other_workload(args, juqcs, W, dev, stream):
                                    "per second, an effective rate since shared gates run once)",
                        "gates": int(len(circ)), "branches": 1 << m, "bitstrings": int(z.size)},
             "check": {"sum_abs2_of_1024_amps": float(np.sum(np.abs(out["a"]) ** 2))},
+        })
+    elif args.workload == "grid42":
+        # Section 4's random-circuit runs: 42 qubits cut into two halves of 21,
+        # M = 2^20 coefficients; the time per gate grows with 2^S, S the
+        # number of decomposed CZs (here the first S crossing CZs are kept)
+        rows, cols, depth = 7, 6, 12
+        circ, side = W.grid_circuit(rows, cols, depth, seed=7, max_cross=args.cross)
+        n = rows * cols
+        M = 1 << 20
+        z = W.bitstrings(n, M, seed=1007)
+        out = {}
+
+        def run():
+            out["a"] = juqcs.juqcs_branch_amplitudes(n, circ, side, z, group_size=args.group,
+                                                     stream=stream)
+
+        ms = _timed(run, args.steps, args.warmup, stream)
+        a = out["a"]
+        S = int(np.sum((side[circ["q0"]] != side[np.maximum(circ["q1"], 0)])
+                       & (circ["op"] == W.OP_CZ)))
+        res.update({
+            "value": len(circ) / (ms / 1e3), "ms_per_step": ms, "dtype": "f32",
+            "config": {"workload": f"grid42: 7x6 grid, depth {depth}, Haar U(2) + 4 CZ edge patterns, "
+                                   f"21|21 cut with S={S} decomposed CZs -> {1 << S} branch pairs of "
+                                   "21-qubit complex64 half-states run as trees; 2^20 coefficients "
+                                   "summed over branches in FP64 (value: gates of the 42-qubit circuit "
+                                   "per second, the inverse of the paper's time per gate)",
+                       "gates": int(len(circ)), "crossings": S, "branches": 1 << S, "bitstrings": M,
+                       "group": args.group},
+            "ms_per_gate": ms / len(circ),
+            "check": {"mean_abs2_times_2^n": float(np.mean(np.abs(a) ** 2) * 2.0 ** n)},
         })
     elif args.workload == "ghz128":
         # Section 4's scaling run at its largest size: the GHZ circuit on 128
