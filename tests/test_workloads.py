@@ -51,3 +51,29 @@ def test_mixed_circuit_pairs_are_distinct():
     two = g[g["op"] >= W.OP_CNOT]
     assert np.all(two["q0"] != two["q1"])
     assert 0.25 < len(two) / len(g) < 0.55
+
+
+def test_wide_bitstrings_round_trip():
+    # little-endian words: qubit q is bit q % 64 of word q // 64
+    for n in (64, 100, 128, 240):
+        z = W.bitstrings_wide(n, 32, seed=n)
+        assert z.shape == (32, (n + 63) // 64) and z.dtype == np.uint64
+        ints = W.words_to_ints(z)
+        assert max(v.bit_length() for v in ints) <= n
+        assert np.array_equal(W.ints_to_words(ints, n), z)
+    one = W.ints_to_words([1 << 100], 128)
+    assert one.tolist() == [[0, 1 << 36]]
+
+
+def test_block_parts_and_ghz_crossings():
+    side = W.block_parts(128, 8)
+    assert np.array_equal(np.bincount(side), [16] * 8)
+    assert np.array_equal(np.bincount(W.block_parts(10, 3)), [4, 3, 3])
+    # the GHZ chain crosses every block boundary once
+    assert len(dec.crossing_gates(W.ghz(128), side)) == 7
+
+
+def test_grid42_cut():
+    circ, side = W.grid_circuit(7, 6, 12, seed=7, max_cross=12)
+    assert np.array_equal(np.bincount(side), [21, 21])
+    assert len(dec.crossing_gates(circ, side)) == 12
