@@ -375,6 +375,9 @@ __global__ __launch_bounds__(kBranchSumThreads) void k_branch_sum_lds(
     }
   }
   double re = acc[2 * k], im = acc[2 * k + 1];
+  // independent products of consecutive branches interleave; the sum keeps
+  // its order
+#pragma unroll 4
   for (long long j = 0; j < g; ++j) {
     const uint64_t t = tab8[j];
     const cplx<float> a = vals[(int)(t & 0xff) * kBranchSumThreads + tid];
