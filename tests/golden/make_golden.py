@@ -8,7 +8,7 @@ into a low and a high half, every CZ across the cut is split with Eq. (2),
 and <z|C|0> = 2^-S sum_s A_s(z_low) B_s(z_high) in FP64.  The decomposition
 is pinned against the full state vector in tests/test_oracle_pins.py.
 
-usage: python tests/golden/make_golden.py brick30 [brick28 brick34 brick36]
+usage: python tests/golden/make_golden.py brick30 [brick28 brick34 brick36 grid48m2 grid42m3]
 """
 import os
 import sys
@@ -26,7 +26,9 @@ from paper_1912_03243_amd import workloads as W  # noqa: E402
 # name: (n, layers, circuit seed, bitstring seed, count)
 # grid48m2: the 6x8 grid circuit (depth 8, seed 5) keeping only its first two
 # cut-crossing CZs, amplitudes by Eq. (3) over the 24|24 column cut.
-GRID_SETS = {"grid48m2": (6, 8, 8, 5, 2, 1005, 64)}
+# grid42m3: the 7x6 grid circuit (depth 12, seed 7) keeping its first three,
+# over the 21|21 column cut.
+GRID_SETS = {"grid48m2": (6, 8, 8, 5, 2, 1005, 64), "grid42m3": (7, 6, 12, 7, 3, 1007, 64)}
 SETS = {
     "brick30": (30, 20, 2, 1002, 256),
     "brick28": (28, 16, 3, 1003, 256),

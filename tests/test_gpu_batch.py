@@ -255,8 +255,9 @@ def test_branch_ghz48_closed_form(J, golden):
     assert np.all(np.abs(got[2:]) < 1e-7)
 
 
-def test_branch_grid48_against_stored_oracle_values(J):
-    name = "grid48m2"
+@pytest.mark.parametrize("name", ["grid48m2", "grid42m3"])
+def test_branch_grid_against_stored_oracle_values(J, name):
+    # full-size halves (24 and 21 qubits) against the oracle's own branch sum
     if not os.path.exists(path_for(name)):
         pytest.skip("stored amplitudes not generated")
     rows, cols, depth, seed, mcross, _, _ = GRID_SETS[name]
