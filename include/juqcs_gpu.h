@@ -369,6 +369,19 @@ juqcs_status juqcs_branch_amplitudes_wide(int n, const juqcs_gate* gates,
                                           int group_size, double* out,
                                           void* hip_stream);
 
+/* The same with the bitstrings and the result on the device: d_z holds
+ * count*words uint64 (layout as above) and d_out 2*count doubles, both in
+ * device memory, so M can be large without host copies.  Bitstrings with a
+ * bit at or above n are found on the device (JUQCS_ERR_ARG, out zeroed).
+ * The result is complete when the call returns (it synchronises
+ * hip_stream).  Other arguments, results and errors as for
+ * juqcs_branch_amplitudes_wide. */
+juqcs_status juqcs_branch_amplitudes_device(int n, const juqcs_gate* gates,
+                                            size_t gate_count, const uint8_t* side,
+                                            const uint64_t* d_z, int words, size_t count,
+                                            int group_size, double* d_out,
+                                            void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Utilities
  * ---------------------------------------------------------------------- */

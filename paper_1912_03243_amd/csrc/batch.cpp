@@ -519,9 +519,11 @@ void branch_diag(int s, C* d) {
 
 // Eq. (3) for count bitstrings of words 64-bit words each (see
 // juqcs_branch_amplitudes_wide).
+// dev: z and out are device pointers (the bitstrings are checked on the
+// device), else host arrays.
 juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count, const uint8_t* side,
                                const uint64_t* z, int words, size_t count, int group_size, double* out,
-                               hipStream_t s) {
+                               hipStream_t s, bool dev) {
   if (n < 2 || n > kBranchMaxQubits) return fail(JUQCS_ERR_ARG, "n must be in [2, 240]");
   if (words < (n + 63) / 64 || words > kBranchMaxWords)
     return fail(JUQCS_ERR_ARG, "words must be in [ceil(n / 64), 4]");
@@ -541,7 +543,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   for (int p = 0; p < P; ++p)
     if (nloc[p] < 1 || nloc[p] > 30) return fail(JUQCS_ERR_ARG, "each part needs 1..30 qubits");
   // bits at or above n must be clear (only the words that can hold them)
-  for (int w = n / 64; w < words; ++w) {
+  for (int w = n / 64; !dev && w < words; ++w) {
     const int lo = std::max(0, n - 64 * w);
     const uint64_t bad = lo >= 64 ? 0 : ~0ull << lo;
     for (size_t k = 0; k < count; ++k)
@@ -733,22 +735,26 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     }
   }
   // bitstrings -> per-part indices on the device; acc holds the running sum
+  // (the caller's out when it is on the device)
   uint64_t* dz = nullptr;
   uint32_t* zp = nullptr;
   int32_t* dtab = nullptr;
-  double* acc = nullptr;
+  int* dbad = nullptr;
+  double* acc = dev ? out : nullptr;
   char* states = nullptr;
   uint64_t* doff = nullptr;
   void* dsum = nullptr;
   const size_t tbytes = lds ? t8.size() * 8 : t32.size() * 4;
-  hipError_t e = hipMalloc((void**)&dz, count * words * sizeof(uint64_t));
+  hipError_t e = hipSuccess;
+  if (!dev) e = hipMalloc((void**)&dz, count * words * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMalloc((void**)&zp, (size_t)P * count * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&dtab, tab.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&acc, count * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dbad, sizeof(int));
+  if (e == hipSuccess && !dev) e = hipMalloc((void**)&acc, count * 2 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&doff, nleaves * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMalloc(&dsum, tbytes);
   if (e == hipSuccess) e = hipMalloc((void**)&states, total);
-  if (e == hipSuccess)
+  if (e == hipSuccess && !dev)
     e = hipMemcpyAsync(dz, z, count * words * sizeof(uint64_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
@@ -757,12 +763,17 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   if (e == hipSuccess)
     e = hipMemcpyAsync(dsum, lds ? (const void*)t8.data() : (const void*)t32.data(), tbytes,
                        hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_branch_split(dz, words, (long long)count, P, dtab, zp, s);
+  if (e == hipSuccess) e = hipMemsetAsync(dbad, 0, sizeof(int), s);
+  if (e == hipSuccess)
+    e = launch_branch_split(dev ? z : dz, words, (long long)count, P, n, dtab, zp, dbad, s);
   if (e == hipSuccess) e = hipMemsetAsync(acc, 0, count * 2 * sizeof(double), s);
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(dz);
   juqcs_status rc = JUQCS_OK;
   if (e != hipSuccess) rc = hip_fail(e, "branch set-up");
+  else if (bad) rc = fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
   size_t rounds = 0;
   for (int p = 0; p < P; ++p) rounds = std::max(rounds, segs[p].size());
   for (long long gi = 0; rc == JUQCS_OK && gi < ngroups; ++gi) {
@@ -841,7 +852,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       if (e != hipSuccess) rc = hip_fail(e, "branch sum");
     }
   }
-  if (rc == JUQCS_OK) {
+  if (rc == JUQCS_OK && !dev) {
     e = hipMemcpyAsync(out, acc, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "branch result copy");
@@ -851,7 +862,8 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   (void)hipFree(doff);
   (void)hipFree(zp);
   (void)hipFree(dtab);
-  (void)hipFree(acc);
+  (void)hipFree(dbad);
+  if (!dev) (void)hipFree(acc);
   return rc;
 }
 
@@ -863,7 +875,7 @@ extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, 
                                                 void* hip_stream) {
   if (n < 2 || n > 62) return fail(JUQCS_ERR_ARG, "n must be in [2, 62]");
   return branch_amplitudes(n, gates, gate_count, side, z, 1, count, group_size, out,
-                           (hipStream_t)hip_stream);
+                           (hipStream_t)hip_stream, false);
 }
 
 extern "C" juqcs_status juqcs_branch_amplitudes_wide(int n, const juqcs_gate* gates, size_t gate_count,
@@ -871,5 +883,14 @@ extern "C" juqcs_status juqcs_branch_amplitudes_wide(int n, const juqcs_gate* ga
                                                      size_t count, int group_size, double* out,
                                                      void* hip_stream) {
   return branch_amplitudes(n, gates, gate_count, side, z, words, count, group_size, out,
-                           (hipStream_t)hip_stream);
+                           (hipStream_t)hip_stream, false);
+}
+
+extern "C" juqcs_status juqcs_branch_amplitudes_device(int n, const juqcs_gate* gates,
+                                                       size_t gate_count, const uint8_t* side,
+                                                       const uint64_t* d_z, int words, size_t count,
+                                                       int group_size, double* d_out,
+                                                       void* hip_stream) {
+  return branch_amplitudes(n, gates, gate_count, side, d_z, words, count, group_size, d_out,
+                           (hipStream_t)hip_stream, true);
 }

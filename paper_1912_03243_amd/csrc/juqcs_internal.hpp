@@ -245,8 +245,9 @@ constexpr int kBranchMaxWords = 4;    // 64-bit words per bitstring
 // lists, then kBranchMaxQubits qubit numbers (part by part, ascending), then
 // the physical bit of each in its part state.
 constexpr int kBranchTabInts = kBranchMaxParts + 1 + 2 * kBranchMaxQubits;
-hipError_t launch_branch_split(const uint64_t* z, int words, long long count, int P,
-                               const int32_t* tab, uint32_t* zp, hipStream_t s);
+// Sets *bad (device int) when a bitstring has a bit at or above n.
+hipError_t launch_branch_split(const uint64_t* z, int words, long long count, int P, int n,
+                               const int32_t* tab, uint32_t* zp, int* bad, hipStream_t s);
 // acc[k] += sum over the group's g branches (in order) of prod_p
 // psi_{tab[j P + p]}[zp[p count + k]] (FP64); the last group multiplies by
 // scale.  States are read where they lie.

@@ -290,16 +290,23 @@ __global__ __launch_bounds__(kThreads) void k_batch_norms(const char* __restrict
 
 // Per-part bitstrings z_p of Eq. (3), each mapped through its part state's
 // layout: zp[p count + k] (one thread per bitstring).
+// A bitstring with a bit at or above n sets *bad.
 __global__ __launch_bounds__(kThreads) void k_branch_split(const uint64_t* __restrict__ z, int words,
-                                                           long long count, int P,
+                                                           long long count, int P, int n,
                                                            const int32_t* __restrict__ tab,
-                                                           uint32_t* __restrict__ zp) {
+                                                           uint32_t* __restrict__ zp, int* __restrict__ bad) {
   const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (k >= count) return;
   const uint64_t* row = z + k * words;
   uint64_t w[kBranchMaxWords];
+  uint64_t over = 0;
 #pragma unroll
-  for (int i = 0; i < kBranchMaxWords; ++i) w[i] = i < words ? row[i] : 0;
+  for (int i = 0; i < kBranchMaxWords; ++i) {
+    w[i] = i < words ? row[i] : 0;
+    const int lo = n - 64 * i;  // bits of word i below n
+    over |= lo >= 64 ? 0 : lo <= 0 ? w[i] : w[i] >> lo;
+  }
+  if (over) atomicOr(bad, 1);
   const int32_t* qs = tab + kBranchMaxParts + 1;
   const int32_t* phys = qs + kBranchMaxQubits;
   for (int p = 0; p < P; ++p) {
@@ -451,12 +458,12 @@ hipError_t launch_batch_norms(const char* states, const uint64_t* state_off, con
   return hipGetLastError();
 }
 
-hipError_t launch_branch_split(const uint64_t* z, int words, long long count, int P,
-                               const int32_t* tab, uint32_t* zp, hipStream_t s) {
+hipError_t launch_branch_split(const uint64_t* z, int words, long long count, int P, int n,
+                               const int32_t* tab, uint32_t* zp, int* bad, hipStream_t s) {
   if (count == 0) return hipSuccess;
   if (words < 1 || words > kBranchMaxWords || P < 1 || P > kBranchMaxParts) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_branch_split, dim3((unsigned)((count + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                     s, z, words, count, P, tab, zp);
+                     s, z, words, count, P, n, tab, zp, bad);
   return hipGetLastError();
 }
 

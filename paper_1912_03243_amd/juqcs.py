@@ -95,6 +95,7 @@ _SIGS = {
                                 _DP, _P],
     "juqcs_branch_amplitudes_wide": [_I, _P, _S, ct.POINTER(ct.c_uint8), ct.POINTER(_U64), _I, _S,
                                      _I, _DP, _P],
+    "juqcs_branch_amplitudes_device": [_I, _P, _S, ct.POINTER(ct.c_uint8), _P, _I, _S, _I, _P, _P],
     "juqcs_copy": [_P, _P, _S, _P],
 }
 EXPORTED = sorted(list(_SIGS) + ["juqcs_last_error", "juqcs_version"])
@@ -188,6 +189,24 @@ def juqcs_branch_amplitudes(n: int, gates, side, z, group_size: int = 0, stream=
                                             _dptr(out), _stream_handle(stream)),
                "juqcs_branch_amplitudes")
     return out.view(np.complex128)  # (re, im) pairs
+
+
+def juqcs_branch_amplitudes_device(n: int, gates, side, z, out, group_size: int = 0, stream=None):
+    """juqcs_branch_amplitudes with device tensors: z an int64 (count, words)
+    tensor of little-endian 64-bit words, out a float64 tensor of 2*count
+    (re, im) pairs, both on the GPU (torch owns the memory)."""
+    g = _gates(gates)
+    side = np.ascontiguousarray(side, dtype=np.uint8)
+    if z.dim() != 2 or not z.is_contiguous() or z.dtype.itemsize != 8:
+        raise ValueError("z: contiguous (count, words) tensor of 64-bit words")
+    if out.numel() != 2 * z.shape[0] or not out.is_contiguous() or out.element_size() != 8:
+        raise ValueError("out: contiguous float64 tensor of 2*count elements")
+    _check(_lib.juqcs_branch_amplitudes_device(n, g.ctypes.data, g.size,
+                                               side.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                                               z.data_ptr(), z.shape[1], z.shape[0], group_size,
+                                               out.data_ptr(), _stream_handle(stream)),
+           "juqcs_branch_amplitudes_device")
+    return out
 
 
 # ---- State --------------------------------------------------------------------

@@ -373,6 +373,34 @@ def test_branch_wide_matches_narrow(J):
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+def test_branch_device_matches_host(J):
+    # bitstrings and result in device memory: the same kernels, the same bits
+    import torch
+    announce("branch-device")
+    n, nparts = 100, 5
+    circ = W.concat(ghz_blocks(n, [(0, n)]), W.haar_layer(n, 21))
+    side = W.block_parts(n, nparts)
+    z = W.bitstrings_wide(n, 4096, 23)
+    host = J.juqcs_branch_amplitudes(n, circ, side, z)
+    dz = torch.from_numpy(z.view(np.int64)).cuda()
+    out = torch.empty(2 * z.shape[0], dtype=torch.float64, device="cuda")
+    J.juqcs_branch_amplitudes_device(n, circ, side, dz, out)
+    dev = out.cpu().numpy().view(np.complex128)
+    assert np.array_equal(dev, host)
+
+
+def test_branch_device_rejects_bits_above_n(J):
+    import torch
+    n = 100
+    z = np.zeros((8, 2), dtype=np.uint64)
+    z[5, 1] = np.uint64(1 << 40)  # qubit 104
+    dz = torch.from_numpy(z.view(np.int64)).cuda()
+    out = torch.empty(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(J.JuqcsError) as e:
+        J.juqcs_branch_amplitudes_device(n, W.ghz(n), W.block_parts(n, 5), dz, out)
+    assert e.value.status == J.ERR_ARG
+
+
 @pytest.mark.parametrize("n, words, top", [(100, 2, 1 << 40), (128, 1, 0), (241, 4, 0)])
 def test_branch_wide_rejects(J, n, words, top):
     # a bit at or above n, too few words, more than 240 qubits
