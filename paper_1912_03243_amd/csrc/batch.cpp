@@ -517,6 +517,101 @@ void branch_diag(int s, C* d) {
   d[3] = {e1.real(), e1.imag()};
 }
 
+// One segment of a part circuit: the gates from one run of its crossings
+// (consecutive gates of the part) up to the next run.
+struct BranchSeg {
+  int g0 = 0, g1 = 0;       // gates [g0, g1) of the part
+  std::vector<int> ks;      // crossings whose diagonals open it, circuit order
+  int nfree = 0;            // of them with bits free within a group
+  std::vector<Gate> gates;  // its gates, qubits where the previous segment left them
+  TilePlan tmpl;            // plan with placeholder diagonals
+  TileSchedule sched;
+};
+
+// One part of a decomposition: its circuit with a placeholder diagonal at
+// every crossing, and that circuit cut into segments.
+struct BranchPart {
+  int nloc = 0;
+  size_t sbytes = 0;                       // state bytes (C64, 256-aligned)
+  std::vector<Gate> gates;                 // local qubits
+  std::vector<std::pair<int, int>> slots;  // (gate index, crossing) of each diagonal, circuit order
+  std::vector<BranchSeg> segs;             // segs[0]: the gates before the first crossing
+  std::vector<int> freek;                  // crossings with free bits, circuit order
+  std::vector<int> phys;                   // physical bit of each local qubit at the leaves
+  int free_bits(int L) const {
+    int R = 0;
+    for (auto& sl : slots) R += sl.second >= L ? 1 : 0;
+    return R;
+  }
+};
+
+// Cuts the part before every run of its crossings, whether their bits are
+// fixed by the group (crossings < L) or free: the cut points do not depend
+// on L, so a leaf goes through the same plans, and holds the same bits, for
+// any group size.  Each segment is planned where the previous one left the
+// qubits.
+void cut_part(BranchPart* bp, int L) {
+  const std::vector<std::pair<int, int>>& fr = bp->slots;
+  const int ng = (int)bp->gates.size();
+  bp->segs.clear();
+  bp->freek.clear();
+  for (auto& f : fr)
+    if (f.second >= L) bp->freek.push_back(f.second);
+  BranchSeg pre;
+  pre.g1 = fr.empty() ? ng : fr[0].first;
+  bp->segs.push_back(std::move(pre));
+  for (size_t i = 0; i < fr.size();) {
+    size_t j = i + 1;
+    while (j < fr.size() && fr[j].first == fr[j - 1].first + 1) ++j;
+    BranchSeg sg;
+    sg.g0 = fr[i].first;
+    sg.g1 = j < fr.size() ? fr[j].first : ng;
+    for (size_t t = i; t < j; ++t) {
+      sg.ks.push_back(fr[t].second);
+      sg.nfree += fr[t].second >= L ? 1 : 0;
+    }
+    bp->segs.push_back(std::move(sg));
+    i = j;
+  }
+  std::vector<int> pos(bp->nloc);
+  for (int q = 0; q < bp->nloc; ++q) pos[q] = q;
+  for (BranchSeg& sg : bp->segs) {
+    sg.gates.assign(bp->gates.begin() + sg.g0, bp->gates.begin() + sg.g1);
+    for (Gate& g : sg.gates)
+      for (int j = 0; j < g.nq; ++j) g.q[j] = pos[g.q[j]];
+    plan_circuit(bp->nloc, sg.gates, 2, true, &sg.tmpl, &sg.sched);
+    if (!sg.sched.final_pos.empty())
+      for (int q = 0; q < bp->nloc; ++q) pos[q] = sg.sched.final_pos[pos[q]];
+  }
+  bp->phys = pos;
+}
+
+// The plan of one tree node: segment sg of the part with its diagonals set,
+// fixed crossings (< L) from the bits of group gi, free ones from the bits
+// of child c (the segment's first free crossing is its top bit).
+TilePlan node_plan(const BranchPart& bp, const BranchSeg& sg, long long gi, int L, long long c) {
+  std::vector<Gate> hg = sg.gates;
+  const int nfixed = (int)sg.ks.size() - sg.nfree;
+  for (auto& sl : bp.slots) {
+    if (sl.first < sg.g0 || sl.first >= sg.g1) continue;
+    int bit;
+    if (sl.second < L) {
+      bit = (int)((gi >> (L - 1 - sl.second)) & 1);
+    } else {
+      const int j = (int)(std::find(sg.ks.begin(), sg.ks.end(), sl.second) - sg.ks.begin()) - nfixed;
+      bit = (int)((c >> (sg.nfree - 1 - j)) & 1);
+    }
+    branch_diag(bit ? -1 : 1, hg[sl.first - sg.g0].m);
+  }
+  // the plan's ops refer to the schedule's relabeled gate copies
+  std::vector<Gate> tg = sg.sched.tgates.empty() ? hg : sg.sched.tgates;
+  if (!sg.sched.tgates.empty())
+    for (size_t t = 0; t < tg.size(); ++t) std::memcpy(tg[t].m, hg[sg.sched.tsrc[t]].m, sizeof(tg[t].m));
+  TilePlan pl = sg.tmpl;
+  rebuild_mats(tg, &pl);
+  return pl;
+}
+
 // Eq. (3) for count bitstrings of words 64-bit words each (see
 // juqcs_branch_amplitudes_wide).
 // dev: z and out are device pointers (the bitstrings are checked on the
@@ -551,8 +646,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   }
   // part circuits with placeholder diagonals at every crossing gate; a
   // crossing CNOT is its CZ between Hadamards on the target (H X H = Z)
-  std::vector<Gate> part[kBranchMaxParts];
-  std::vector<std::pair<int, int>> slot[kBranchMaxParts];  // (gate index in part, crossing number)
+  BranchPart parts[kBranchMaxParts];
   int m = 0;
   std::string err;
   const double s2 = 1.0 / std::sqrt(2.0);
@@ -577,7 +671,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       h.m[1] = {s2, 0};
       h.m[2] = {s2, 0};
       h.m[3] = {-s2, 0};
-      if (op == JUQCS_OP_CNOT) part[pt].push_back(h);
+      if (op == JUQCS_OP_CNOT) parts[pt].gates.push_back(h);
       for (int j = 0; j < 2; ++j) {
         const int q = g.q[j], p = side[q];
         Gate d{};
@@ -586,42 +680,38 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
         d.q[1] = -1;
         branch_diag(1, d.m);
         d.diag = true;
-        slot[p].push_back({(int)part[p].size(), m});
-        part[p].push_back(d);
+        parts[p].slots.push_back({(int)parts[p].gates.size(), m});
+        parts[p].gates.push_back(d);
       }
-      if (op == JUQCS_OP_CNOT) part[pt].push_back(h);
+      if (op == JUQCS_OP_CNOT) parts[pt].gates.push_back(h);
       ++m;
       continue;
     }
     const int p = side[g.q[0]];
     for (int j = 0; j < g.nq; ++j) g.q[j] = local[g.q[j]];
-    part[p].push_back(g);
+    parts[p].gates.push_back(g);
   }
   if (count == 0) return JUQCS_OK;
-  size_t sbytes[kBranchMaxParts];
-  for (int p = 0; p < P; ++p) sbytes[p] = align256((size_t)8 << nloc[p]);
+  for (int p = 0; p < P; ++p) {
+    parts[p].nloc = nloc[p];
+    parts[p].sbytes = align256((size_t)8 << nloc[p]);
+  }
   // Branches are grouped by the bits of the first L crossings (circuit
   // order; those bits are fixed within a group, the others free).  Inside a
   // group a part's states form a tree: the gates before its first crossing
-  // run once, and every run of its crossings (consecutive gates of the
-  // part) splits each state into one copy per setting of their free bits,
-  // which then runs the gates up to the next run.  The leaves are the
-  // part's states for every setting of its own free crossings; branches
-  // that agree on those share a leaf.
+  // run once, and every run of its crossings splits each state into one
+  // copy per setting of their free bits, which then runs the gates up to
+  // the next run.  The leaves are the part's states for every setting of
+  // its own free crossings; branches that agree on those share a leaf.
   size_t budget = 0;
   {
     size_t freeb = 0, totalb = 0;
     (void)hipMemGetInfo(&freeb, &totalb);
     budget = std::min<size_t>(freeb / 2, (size_t)64 << 30);
   }
-  auto free_bits = [&](int p, int L) {
-    int R = 0;
-    for (auto& sl : slot[p]) R += sl.second >= L ? 1 : 0;
-    return R;
-  };
   auto leaf_bytes = [&](int L) {
     size_t t = 0;
-    for (int p = 0; p < P; ++p) t += sbytes[p] << free_bits(p, L);
+    for (int p = 0; p < P; ++p) t += parts[p].sbytes << parts[p].free_bits(L);
     return t;
   };
   int L = 0;
@@ -633,55 +723,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     while (L < m && leaf_bytes(L) > budget) ++L;
   }
   const long long gsize = 1ll << (m - L), ngroups = 1ll << L;
-  // Segments do not depend on L: a part's circuit is cut before every run of
-  // its crossings, whether their bits are fixed by the group or free, so a
-  // leaf goes through the same plans, and holds the same bits, for any
-  // group size.
-  struct Seg {
-    int g0 = 0, g1 = 0;       // gates [g0, g1) of the part
-    std::vector<int> ks;      // crossings whose diagonals open it
-    int nfree = 0;            // of them with k >= L
-    TilePlan tmpl;            // plan with placeholder diagonals
-    TileSchedule sched;
-  };
-  std::vector<Seg> segs[kBranchMaxParts];
-  std::vector<int> freek[kBranchMaxParts];    // free crossings of each part, circuit order
-  std::vector<int> phys_final[kBranchMaxParts];
-  for (int p = 0; p < P; ++p) {
-    const std::vector<std::pair<int, int>>& fr = slot[p];  // (gate index, crossing), circuit order
-    for (auto& f : fr)
-      if (f.second >= L) freek[p].push_back(f.second);
-    const int ng = (int)part[p].size();
-    Seg pre;
-    pre.g0 = 0;
-    pre.g1 = fr.empty() ? ng : fr[0].first;
-    segs[p].push_back(std::move(pre));
-    for (size_t i = 0; i < fr.size();) {
-      size_t j = i + 1;
-      while (j < fr.size() && fr[j].first == fr[j - 1].first + 1) ++j;
-      Seg sg;
-      sg.g0 = fr[i].first;
-      sg.g1 = j < fr.size() ? fr[j].first : ng;
-      for (size_t t = i; t < j; ++t) {
-        sg.ks.push_back(fr[t].second);
-        sg.nfree += fr[t].second >= L ? 1 : 0;
-      }
-      segs[p].push_back(std::move(sg));
-      i = j;
-    }
-    // plan every segment where the previous one left the qubits
-    std::vector<int> pos(nloc[p]);
-    for (int q = 0; q < nloc[p]; ++q) pos[q] = q;
-    for (Seg& sg : segs[p]) {
-      std::vector<Gate> gs(part[p].begin() + sg.g0, part[p].begin() + sg.g1);
-      for (Gate& g : gs)
-        for (int j = 0; j < g.nq; ++j) g.q[j] = pos[g.q[j]];
-      plan_circuit(nloc[p], gs, 2, true, &sg.tmpl, &sg.sched);
-      if (!sg.sched.final_pos.empty())
-        for (int q = 0; q < nloc[p]; ++q) pos[q] = sg.sched.final_pos[pos[q]];
-    }
-    phys_final[p] = pos;
-  }
+  for (int p = 0; p < P; ++p) cut_part(&parts[p], L);
   // split table: each part's qubits and their physical bits at the leaves
   std::vector<int32_t> tab(kBranchTabInts, 0);
   {
@@ -694,7 +736,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       for (int q = 0; q < n; ++q) {
         if (side[q] != p) continue;
         qs[o] = q;
-        phys[o] = phys_final[p][local[q]];
+        phys[o] = parts[p].phys[local[q]];
         ++o;
       }
     }
@@ -704,14 +746,15 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   int32_t first[kBranchMaxParts + 1] = {};
   size_t base[kBranchMaxParts] = {}, total = 0;
   for (int p = 0; p < P; ++p) {
-    first[p + 1] = first[p] + (1 << freek[p].size());
+    first[p + 1] = first[p] + (1 << parts[p].freek.size());
     base[p] = total;
-    total += sbytes[p] << freek[p].size();
+    total += parts[p].sbytes << parts[p].freek.size();
   }
   const int nleaves = first[P];
   std::vector<uint64_t> leaf_off(nleaves);
   for (int p = 0; p < P; ++p)
-    for (int l = 0; l < (1 << freek[p].size()); ++l) leaf_off[first[p] + l] = base[p] + (size_t)l * sbytes[p];
+    for (int l = 0; l < (1 << parts[p].freek.size()); ++l)
+      leaf_off[first[p] + l] = base[p] + (size_t)l * parts[p].sbytes;
   // the sum runs over branches in tree order: t ascending, where bit
   // m-1-k of t is crossing k's bit; a group is a range of t
   auto branch_of = [&](long long t) {
@@ -727,9 +770,10 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   for (long long j = 0; j < gsize; ++j) {
     const long long b = branch_of(j);  // the free bits (the group adds only fixed ones)
     for (int p = 0; p < P; ++p) {
-      const int R = (int)freek[p].size();
+      const std::vector<int>& fk = parts[p].freek;
+      const int R = (int)fk.size();
       int l = 0;
-      for (int i = 0; i < R; ++i) l |= (int)((b >> freek[p][i]) & 1) << (R - 1 - i);
+      for (int i = 0; i < R; ++i) l |= (int)((b >> fk[i]) & 1) << (R - 1 - i);
       if (lds) t8[j] |= (uint64_t)(first[p] + l) << (8 * p);
       else t32[(size_t)j * P + p] = first[p] + l;
     }
@@ -775,51 +819,30 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   if (e != hipSuccess) rc = hip_fail(e, "branch set-up");
   else if (bad) rc = fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
   size_t rounds = 0;
-  for (int p = 0; p < P; ++p) rounds = std::max(rounds, segs[p].size());
+  for (int p = 0; p < P; ++p) rounds = std::max(rounds, parts[p].segs.size());
   for (long long gi = 0; rc == JUQCS_OK && gi < ngroups; ++gi) {
     for (size_t r = 0; rc == JUQCS_OK && r < rounds; ++r) {
+      // round r: segment r of every part, for every node of that level
       juqcs_batch B;
       std::vector<TilePlan> plans;
       for (int p = 0; p < P && rc == JUQCS_OK; ++p) {
-        if (r >= segs[p].size()) continue;
-        const Seg& sg = segs[p][r];
-        const int R = (int)freek[p].size();
+        const BranchPart& bp = parts[p];
+        if (r >= bp.segs.size()) continue;
+        const BranchSeg& sg = bp.segs[r];
+        const int R = (int)bp.freek.size();
         int done = 0;  // free bits split before this segment
-        for (size_t i = 0; i < r; ++i) done += segs[p][i].nfree;
-        const int rb = sg.nfree, after = R - done - rb;
-        const long long parents = 1ll << done, children = 1ll << rb;
-        for (long long a = 0; a < parents; ++a)
-          for (long long c = 0; c < children; ++c) {
-            const long long leaf = (a << (R - done)) + (c << after);
-            // diagonal values: fixed crossings from the group, this
-            // segment's free ones from the child's bits
-            std::vector<Gate> hg(part[p].begin() + sg.g0, part[p].begin() + sg.g1);
-            for (auto& sl : slot[p]) {
-              if (sl.first < sg.g0 || sl.first >= sg.g1) continue;
-              int bit;
-              if (sl.second < L) {
-                bit = (int)((gi >> (L - 1 - sl.second)) & 1);
-              } else {  // j-th free crossing of the segment (fixed ones come first)
-                const int j = (int)(std::find(sg.ks.begin(), sg.ks.end(), sl.second) - sg.ks.begin()) -
-                              ((int)sg.ks.size() - sg.nfree);
-                bit = (int)((c >> (rb - 1 - j)) & 1);
-              }
-              branch_diag(bit ? -1 : 1, hg[sl.first - sg.g0].m);
-            }
-            std::vector<Gate> tg = sg.sched.tgates.empty() ? hg : sg.sched.tgates;
-            if (!sg.sched.tgates.empty())
-              for (size_t t = 0; t < tg.size(); ++t)
-                std::memcpy(tg[t].m, hg[sg.sched.tsrc[t]].m, sizeof(tg[t].m));
-            TilePlan pl = sg.tmpl;
-            rebuild_mats(tg, &pl);
-            plans.push_back(std::move(pl));
-            B.n.push_back(nloc[p]);
-            B.state_off.push_back(base[p] + (size_t)leaf * sbytes[p]);
+        for (size_t i = 0; i < r; ++i) done += bp.segs[i].nfree;
+        const int after = R - done - sg.nfree;
+        for (long long a = 0; a < (1ll << done); ++a)
+          for (long long c = 0; c < (1ll << sg.nfree); ++c) {
+            const long long parent = a << (R - done), leaf = parent + (c << after);
+            plans.push_back(node_plan(bp, sg, gi, L, c));
+            B.n.push_back(bp.nloc);
+            B.state_off.push_back(base[p] + (size_t)leaf * bp.sbytes);
             B.keep.push_back(r > 0 ? 1 : 0);
             if (r > 0 && c > 0) {  // the child starts as a copy of its parent
-              const size_t from = base[p] + (size_t)(a << (R - done)) * sbytes[p];
-              e = hipMemcpyAsync(states + B.state_off.back(), states + from, sbytes[p],
-                                 hipMemcpyDeviceToDevice, s);
+              e = hipMemcpyAsync(states + B.state_off.back(), states + base[p] + (size_t)parent * bp.sbytes,
+                                 bp.sbytes, hipMemcpyDeviceToDevice, s);
               if (e != hipSuccess) rc = hip_fail(e, "branch state copy");
             }
           }
