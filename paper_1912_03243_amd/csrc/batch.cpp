@@ -868,8 +868,18 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
         e = launch_branch_sum_lds(states, doff, P, bp, gsize, (const uint64_t*)dsum, zp, (long long)count,
                                   acc, last, scale, s);
       } else {
-        e = launch_branch_gather_accum(states, doff, P, gsize, (const int32_t*)dsum, zp, (long long)count,
-                                       acc, last, scale, s);
+        // Many coefficients read every state at random places: in chunks of
+        // branches whose states fit the 256 MiB last-level cache those reads
+        // stay on chip, at the price of one more pass over acc per chunk.
+        size_t per = 0;
+        for (int p = 0; p < P; ++p) per += parts[p].sbytes;
+        const long long chunk =
+            count >= (1u << 16) ? std::max<long long>(1, (long long)(((size_t)128 << 20) / per)) : gsize;
+        for (long long j0 = 0; e == hipSuccess && j0 < gsize; j0 += chunk) {
+          const long long c = std::min(chunk, gsize - j0);
+          e = launch_branch_gather_accum(states, doff, P, c, (const int32_t*)dsum + j0 * P, zp,
+                                         (long long)count, acc, last && j0 + c >= gsize, scale, s);
+        }
       }
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) rc = hip_fail(e, "branch sum");
