@@ -373,6 +373,22 @@ def test_branch_wide_matches_narrow(J):
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+def test_branch_without_crossings_and_empty(J):
+    # no gate crosses the parts (one branch, m = 0): a product state, whose
+    # coefficient is prod_q U_q[z_q, 0]; and no bitstrings at all
+    announce("branch-m0")
+    n = 30
+    layer = W.haar_layer(n, 31)
+    side = W.block_parts(n, 3)
+    zs = W.words_to_ints(W.bitstrings_wide(n, 32, 32)) + [0, (1 << n) - 1]
+    got = J.juqcs_branch_amplitudes(n, layer, side, np.array(zs, dtype=np.uint64))
+    u = layer["u"].reshape(n, 2, 2, 2)
+    u = u[..., 0] + 1j * u[..., 1]
+    want = np.array([np.prod([u[q, (z >> q) & 1, 0] for q in range(n)]) for z in zs])
+    assert_c64(got, want)
+    assert J.juqcs_branch_amplitudes(n, layer, side, np.zeros(0, dtype=np.uint64)).size == 0
+
+
 def test_branch_device_matches_host(J):
     # bitstrings and result in device memory: the same kernels, the same bits
     import torch
