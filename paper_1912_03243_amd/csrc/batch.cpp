@@ -22,7 +22,7 @@ using namespace juqcs;
 namespace {
 
 using C = cplx<double>;
-constexpr int kChunkTiles = 8;
+constexpr int kChunkTiles = 32;
 
 juqcs_status fail(juqcs_status st, const std::string& msg) {
   set_error(msg);
