@@ -382,25 +382,40 @@ __global__ __launch_bounds__(kBranchSumThreads) void k_branch_sum_lds(
     }
   }
   double re = acc[2 * k], im = acc[2 * k + 1];
-  // independent products of consecutive branches interleave; the sum keeps
-  // its order
-#pragma unroll 4
+  // Prefix products over the parts, kept from branch to branch: branch j
+  // recomputes them only from the first part whose state differs from
+  // branch j-1's (a wave-uniform test on the table words), so parts whose
+  // crossings come early are multiplied once per run of branches.  The
+  // products are the same values, in the same order, as in
+  // k_branch_gather_accum.  Entries past the last part repeat the full
+  // product, so it is always pr[kBranchMaxParts - 1].
+  double pr[kBranchMaxParts], pi[kBranchMaxParts];
+  uint64_t prev = 0;
   for (long long j = 0; j < g; ++j) {
     const uint64_t t = tab8[j];
-    const cplx<float> a = vals[(int)(t & 0xff) * kBranchSumThreads + tid];
-    double pr = a.re, pi = a.im;
+    const uint64_t diff = t ^ prev;
+    const int p0 = j == 0 ? 0 : diff ? __builtin_ctzll(diff) >> 3 : kBranchMaxParts;
+    prev = t;
 #pragma unroll
-    for (int p = 1; p < kBranchMaxParts; ++p) {
+    for (int p = 0; p < kBranchMaxParts; ++p) {
+      if (p < p0) continue;
       if (p < P) {
         const cplx<float> b = vals[(int)((t >> (8 * p)) & 0xff) * kBranchSumThreads + tid];
-        const double br = b.re, bi = b.im;
-        const double u = pr * br - pi * bi;
-        pi = pr * bi + pi * br;
-        pr = u;
+        if (p == 0) {
+          pr[0] = b.re;
+          pi[0] = b.im;
+        } else {
+          const double br = b.re, bi = b.im;
+          pr[p] = pr[p - 1] * br - pi[p - 1] * bi;
+          pi[p] = pr[p - 1] * bi + pi[p - 1] * br;
+        }
+      } else {
+        pr[p] = pr[p - 1];
+        pi[p] = pi[p - 1];
       }
     }
-    re += pr;
-    im += pi;
+    re += pr[kBranchMaxParts - 1];
+    im += pi[kBranchMaxParts - 1];
   }
   if (last) {
     re *= scale;
