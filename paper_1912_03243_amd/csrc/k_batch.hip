@@ -335,22 +335,34 @@ __global__ __launch_bounds__(kThreads) void k_branch_gather_accum(
 #pragma unroll
   for (int p = 0; p < kBranchMaxParts; ++p) zi[p] = p < P ? zp[(size_t)p * count + k] : 0u;
   double re = acc[2 * k], im = acc[2 * k + 1];
+  // prefix products over the parts, recomputed from the first part whose
+  // state differs from the previous branch's (as in k_branch_sum_lds)
+  double pr[kBranchMaxParts], pi[kBranchMaxParts];
   for (long long j = 0; j < g; ++j) {
     const int32_t* t = tab + j * P;
-    const cplx<float> a = reinterpret_cast<const cplx<float>*>(states + state_off[t[0]])[zi[0]];
-    double pr = a.re, pi = a.im;
+    int p0 = 0;
+    if (j > 0)
+      while (p0 < P && t[p0] == t[p0 - P]) ++p0;  // wave-uniform
 #pragma unroll
-    for (int p = 1; p < kBranchMaxParts; ++p) {
+    for (int p = 0; p < kBranchMaxParts; ++p) {
+      if (p < p0) continue;
       if (p < P) {
         const cplx<float> b = reinterpret_cast<const cplx<float>*>(states + state_off[t[p]])[zi[p]];
-        const double br = b.re, bi = b.im;
-        const double u = pr * br - pi * bi;
-        pi = pr * bi + pi * br;
-        pr = u;
+        if (p == 0) {
+          pr[0] = b.re;
+          pi[0] = b.im;
+        } else {
+          const double br = b.re, bi = b.im;
+          pr[p] = pr[p - 1] * br - pi[p - 1] * bi;
+          pi[p] = pr[p - 1] * bi + pi[p - 1] * br;
+        }
+      } else {
+        pr[p] = pr[p - 1];
+        pi[p] = pi[p - 1];
       }
     }
-    re += pr;
-    im += pi;
+    re += pr[kBranchMaxParts - 1];
+    im += pi[kBranchMaxParts - 1];
   }
   if (last) {
     re *= scale;
