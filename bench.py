@@ -375,10 +375,11 @@ def other_workload(args, juqcs, W, dev, stream):
         circ, side = W.grid_circuit()
         z = W.bitstrings(48, 1024, seed=1005)
         out = {}
+        work = juqcs.branch_workspace(48, circ, side, 1, z.size, args.group, True, dev)
 
         def run():
             out["a"] = juqcs.juqcs_branch_amplitudes(48, circ, side, z, group_size=args.group,
-                                                     stream=stream)
+                                                     stream=stream, work=work)
 
         ms = _timed(run, args.steps, args.warmup, stream)
         m = 10
@@ -404,10 +405,11 @@ def other_workload(args, juqcs, W, dev, stream):
         M = 1 << 20
         z = W.bitstrings(n, M, seed=1007)
         out = {}
+        work = juqcs.branch_workspace(n, circ, side, 1, M, args.group, True, dev)
 
         def run():
             out["a"] = juqcs.juqcs_branch_amplitudes(n, circ, side, z, group_size=args.group,
-                                                     stream=stream)
+                                                     stream=stream, work=work)
 
         ms = _timed(run, args.steps, args.warmup, stream)
         a = out["a"]
@@ -439,10 +441,11 @@ def other_workload(args, juqcs, W, dev, stream):
         # bitstrings and coefficients resident in HBM for the timed steps
         dz = torch.from_numpy(z.view(np.int64)).to(dev)
         dout = torch.empty(2 * M, dtype=torch.float64, device=dev)
+        work = juqcs.branch_workspace(n, circ, side, z.shape[1], M, args.group, False, dev)
 
         def run():
             juqcs.juqcs_branch_amplitudes_device(n, circ, side, dz, dout, group_size=args.group,
-                                                 stream=stream)
+                                                 stream=stream, work=work)
 
         ms = _timed(run, args.steps, args.warmup, stream)
         # the same with host bitstrings in and host coefficients out (PCIe)

@@ -18,8 +18,10 @@
  *     with bit t clear and j = i + 2^t, (psi_i, psi_j) <- U (psi_i, psi_j);
  *   - a 2^k x 2^k matrix m has row/column index r = sum_j b_{targets[j]} 2^j,
  *     row-major, (re, im) pairs: m[2*(row*2^k + col) + {0,1}];
- *   - device buffers are borrowed, never freed by the library; the caller
- *     keeps them alive until juqcs_state_destroy returns;
+ *   - the library never allocates device memory: every device buffer,
+ *     workspaces included, is the caller's (sizing calls give the sizes),
+ *     borrowed and never freed by the library; the caller keeps it alive
+ *     until the handle using it is destroyed;
  *   - host arrays passed in are copied before the call returns;
  *   - every apply call is asynchronous on the handle's HIP stream; calls that
  *     return host data (amplitudes, norm, expectations) synchronise it;
@@ -105,10 +107,11 @@ juqcs_status juqcs_state_bytes(int n, juqcs_dtype dtype, int block_bits,
                                size_t* work_bytes);
 
 /* Wrap caller-owned device buffers (sizes at least those of
- * juqcs_state_bytes; d_scales may be NULL unless ENC2; d_work may be NULL,
- * then the library allocates its own workspace and frees it on destroy).
- * hip_stream is a hipStream_t (NULL = default stream).  The amplitudes are
- * not initialised: call juqcs_state_init.  Errors: ARG, SIZE, DTYPE, HIP. */
+ * juqcs_state_bytes; d_scales may be NULL unless ENC2; d_work is required,
+ * 256-byte aligned: the library never allocates device memory).  hip_stream
+ * is a hipStream_t (NULL = default stream).  The amplitudes are not
+ * initialised: call juqcs_state_init.  Errors: ARG (null or misaligned
+ * buffer), SIZE (buffer smaller than juqcs_state_bytes says), DTYPE. */
 juqcs_status juqcs_state_create(juqcs_state** out, int n, juqcs_dtype dtype,
                                 int block_bits, void* d_amps, size_t amp_bytes,
                                 void* d_scales, size_t scale_bytes,
@@ -119,7 +122,8 @@ juqcs_status juqcs_state_create(juqcs_state** out, int n, juqcs_dtype dtype,
 juqcs_status juqcs_state_destroy(juqcs_state* st);
 
 /* psi = |basis_index> (the computer starts in |0...0>, Section 4 before
- * Eq. (3)); resets the qubit permutation to identity.  Errors: ARG. */
+ * Eq. (3)); resets the qubit permutation to identity and the global factor
+ * to 1.  Errors: ARG. */
 juqcs_status juqcs_state_init(juqcs_state* st, uint64_t basis_index);
 
 /* Switch the handle's stream. */
@@ -129,8 +133,10 @@ juqcs_status juqcs_state_set_stream(juqcs_state* st, void* hip_stream);
  * Single gates (Section 2, Eq. (1)); one pass over the touched amplitudes
  * ---------------------------------------------------------------------- */
 
-/* Eq. (1) on target t.  Diagonal matrices only touch the amplitudes whose
- * factor differs from 1.  Errors: QUBIT, ARG (null u), NUMERIC. */
+/* Eq. (1) on target t.  A diagonal matrix diag(a, b) with a != 0 is applied
+ * as a diag(1, b/a): the factor a goes into the state's FP64 global factor
+ * (juqcs_get_global_factor) and only the amplitudes with bit t set are
+ * touched.  Errors: QUBIT, ARG (null u), NUMERIC. */
 juqcs_status juqcs_apply_1q(juqcs_state* st, int t, const double u[8]);
 
 /* Controlled-U: Eq. (1) on target t for the indices whose bit c is 1
@@ -209,7 +215,8 @@ juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates,
  * ---------------------------------------------------------------------- */
 
 /* out[2k], out[2k+1] = re, im of <idx[k]|psi> (logical basis index; ENC2
- * amplitudes are decoded).  Host arrays; synchronises the stream.
+ * amplitudes are decoded; the global factor is applied in FP64).  Host
+ * arrays, staged through the workspace; synchronises the stream.
  * (Section 4: the M requested coefficients.)  Errors: ARG, HIP. */
 juqcs_status juqcs_amplitudes(juqcs_state* st, const uint64_t* idx,
                               size_t count, double* out);
@@ -219,9 +226,25 @@ juqcs_status juqcs_amplitudes(juqcs_state* st, const uint64_t* idx,
 juqcs_status juqcs_amplitudes_device(juqcs_state* st, const uint64_t* d_idx,
                                      size_t count, double* d_out);
 
-/* out = sum_i |psi_i|^2, FP64 accumulation in a fixed order (deterministic).
+/* out = |g|^2 sum_i |psi_i|^2 (g: the global factor), FP64 accumulation in
+ * a fixed order (deterministic).  Section 2: the state is normalised.
  * Synchronises.  Errors: HIP, NUMERIC (result not finite). */
 juqcs_status juqcs_norm(juqcs_state* st, double* out);
+
+/* The state's FP64 complex global factor g (Section 2: the normalisation of
+ * the state; phases and scalar weights).  The logical state is g times the
+ * stored amplitudes: amplitudes, norm and expectation values include it,
+ * and setting or multiplying it touches no amplitude.  g = (re, im).
+ * juqcs_state_init resets it to 1.  Errors: ARG (null), NUMERIC
+ * (non-finite). */
+juqcs_status juqcs_set_global_factor(juqcs_state* st, const double g[2]);
+juqcs_status juqcs_mul_global_factor(juqcs_state* st, const double f[2]);
+juqcs_status juqcs_get_global_factor(const juqcs_state* st, double g[2]);
+
+/* Renormalises through the global factor: g <- g / sqrt(N), N the norm
+ * before (returned in *norm_before if not NULL).  One read pass, no write.
+ * Errors: HIP, NUMERIC (zero or non-finite norm). */
+juqcs_status juqcs_renormalize(juqcs_state* st, double* norm_before);
 
 /* Multiplies every amplitude by the real factor (FP64 for C128, FP32 for
  * C64; ENC2 scales are multiplied).  Used to renormalise by 1/sqrt(norm). */
@@ -275,18 +298,39 @@ juqcs_status juqcs_decode2(const void* d_codes, const void* d_scales,
 typedef struct juqcs_batch juqcs_batch; /* opaque */
 
 /* Builds a batch of count circuits: circuit i has n[i] qubits (1..30) and
- * gate records gates[offsets[i] .. offsets[i+1]).  States are C64 in
- * d_states at byte offsets state_offset[i] (each 8 * 2^n[i] bytes, caller
- * allocated, disjoint, 16-byte aligned); every circuit starts from
- * |0...0>.  Each circuit is planned into on-chip tile passes (tiles of up
- * to 2^13 amplitudes); the fusion width inside a pass (1..4 qubits) is
- * opts->fuse_k, or chosen per circuit when fuse_k is 0: by a cost model, or
- * by timed trials when opts->autotune is 1.  The work list is uploaded into
- * library-owned device memory.  Errors: ARG, QUBIT, NUMERIC, HIP. */
+ * gate records gates[offsets[i] .. offsets[i+1]).  States are C64 in the
+ * caller's d_states (states_bytes bytes, 16-byte aligned) at byte offsets
+ * state_offset[i] (each 8 * 2^n[i] bytes, 16-byte aligned, inside the buffer
+ * and disjoint: JUQCS_ERR_SIZE / JUQCS_ERR_ARG otherwise, checked before any
+ * device work); every circuit starts from |0...0>.  Each circuit is planned
+ * on the host into on-chip tile passes (tiles of up to 2^13 amplitudes);
+ * the fusion width inside a pass (1..4 qubits) is opts->fuse_k, or chosen
+ * per circuit by a cost model when fuse_k is 0 (juqcs_batch_autotune
+ * replaces it with timed trials).  No device memory is touched: bind a
+ * workspace of juqcs_batch_bytes bytes before running.  Errors: ARG, SIZE,
+ * QUBIT, NUMERIC. */
 juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
                                 const juqcs_gate* gates, const int64_t* offsets,
-                                void* d_states, const uint64_t* state_offset,
+                                void* d_states, size_t states_bytes,
+                                const uint64_t* state_offset,
                                 const juqcs_plan_opts* opts);
+
+/* Device workspace the batch's current plans need (the work list plus a
+ * read-out staging area of 4 MiB). */
+juqcs_status juqcs_batch_bytes(const juqcs_batch* b, size_t* work_bytes);
+
+/* Uploads the work list into the caller's workspace (256-byte aligned, at
+ * least juqcs_batch_bytes; the caller keeps it alive until destroy or the
+ * next bind).  Synchronises hip_stream.  Errors: ARG, SIZE, HIP. */
+juqcs_status juqcs_batch_bind(juqcs_batch* b, void* d_work, size_t work_bytes,
+                              void* hip_stream);
+
+/* Autotuner: for every qubit count of the batch, times one of its circuits
+ * run alone with in-pass fusion widths 1..4 (on that circuit's state region
+ * and the bound workspace, on hip_stream) and re-plans every circuit with
+ * the fastest width of its qubit count.  The batch is then unbound: query
+ * juqcs_batch_bytes and bind again.  Errors: ARG (not bound), HIP. */
+juqcs_status juqcs_batch_autotune(juqcs_batch* b, void* hip_stream);
 
 /* Runs the whole batch on hip_stream (asynchronous): one persistent kernel
  * per pass round (round r applies pass r of every circuit that has one; the
@@ -314,13 +358,22 @@ juqcs_status juqcs_batch_fusion(const juqcs_batch* b, int* kin);
 juqcs_status juqcs_batch_layout(const juqcs_batch* b, int c, int* phys);
 
 /* out[2*(c*m+k)], out[2*(c*m+k)+1] = amplitude idx[c*m+k] of circuit c
- * (logical index; host arrays, FP64 pairs; an index >= 2^n gives NaN).
- * Synchronises. */
+ * (logical index; host arrays, FP64 pairs; an index >= 2^n gives NaN),
+ * staged through the workspace in chunks of circuits.  Synchronises.
+ * Errors: ARG (not bound), SIZE (m above 174762), HIP. */
 juqcs_status juqcs_batch_amplitudes(juqcs_batch* b, const uint64_t* idx, int m,
                                     double* out, void* hip_stream);
 
+/* The same with idx (count*m uint64) and out (2*count*m doubles) in device
+ * memory; asynchronous on hip_stream. */
+juqcs_status juqcs_batch_amplitudes_device(juqcs_batch* b, const uint64_t* d_idx, int m,
+                                           double* d_out, void* hip_stream);
+
 /* out[c] = FP64 norm of circuit c (fixed-order sum).  Synchronises. */
 juqcs_status juqcs_batch_norms(juqcs_batch* b, double* out, void* hip_stream);
+
+/* The same into device memory (count doubles); asynchronous. */
+juqcs_status juqcs_batch_norms_device(juqcs_batch* b, double* d_out, void* hip_stream);
 
 juqcs_status juqcs_batch_destroy(juqcs_batch* b);
 
@@ -347,14 +400,18 @@ juqcs_status juqcs_batch_destroy(juqcs_batch* b);
  * bits reversed, ascending) for every coefficient, the same result for any
  * group size.  Only CZ and CNOT may cross between parts
  * (JUQCS_ERR_UNSUPPORTED otherwise); m <= 20.  z: count uint64 (host);
- * out: 2*count doubles (host).  Synchronises hip_stream.  The library
- * allocates the device memory this needs (the part-states of a group, the
- * per-part indices and the running sum: 4 P + 16 bytes per bitstring) and
- * frees it before returning. */
+ * out: 2*count doubles (host).  Synchronises hip_stream.  d_work: the
+ * caller's device workspace (256-byte aligned) for the part states of a
+ * group, the per-part indices, the running sum (4 P + 16 bytes per
+ * bitstring, plus 8 words bytes for host bitstrings) and the tree rounds'
+ * work lists; juqcs_branch_bytes gives its size.  group_size 0 takes the
+ * largest group that fits work_bytes; a group size that does not fit is
+ * JUQCS_ERR_SIZE.  count = 0 needs no workspace. */
 juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates,
                                      size_t gate_count, const uint8_t* side,
                                      const uint64_t* z, size_t count,
                                      int group_size, double* out,
+                                     void* d_work, size_t work_bytes,
                                      void* hip_stream);
 
 /* The same for circuits of up to 240 qubits (eight parts of 30), such as
@@ -367,6 +424,7 @@ juqcs_status juqcs_branch_amplitudes_wide(int n, const juqcs_gate* gates,
                                           size_t gate_count, const uint8_t* side,
                                           const uint64_t* z, int words, size_t count,
                                           int group_size, double* out,
+                                          void* d_work, size_t work_bytes,
                                           void* hip_stream);
 
 /* The same with the bitstrings and the result on the device: d_z holds
@@ -380,7 +438,19 @@ juqcs_status juqcs_branch_amplitudes_device(int n, const juqcs_gate* gates,
                                             size_t gate_count, const uint8_t* side,
                                             const uint64_t* d_z, int words, size_t count,
                                             int group_size, double* d_out,
+                                            void* d_work, size_t work_bytes,
                                             void* hip_stream);
+
+/* Device workspace of the decomposition calls above for these arguments:
+ * *min_bytes for groups of one branch (the least any run needs), *bytes for
+ * group_size (0: every branch in one group).  host_io = 1 for
+ * juqcs_branch_amplitudes and _wide (bitstrings and result staged in the
+ * workspace), 0 for _device.  Host work only (the circuit is planned).
+ * Errors: as for juqcs_branch_amplitudes_wide, ARG for null outputs. */
+juqcs_status juqcs_branch_bytes(int n, const juqcs_gate* gates, size_t gate_count,
+                                const uint8_t* side, int words, size_t count,
+                                int group_size, int host_io, size_t* min_bytes,
+                                size_t* bytes);
 
 /* ------------------------------------------------------------------------
  * Utilities

@@ -61,8 +61,11 @@ struct juqcs_state {
   void* scales;
   char* work;
   size_t work_bytes;
-  bool own_work;
   hipStream_t stream;
+  // FP64 complex factor of the whole state: the logical state is gf times
+  // the stored amplitudes (phases and scalar weights are absorbed here
+  // instead of passes over the data)
+  C gf{1.0, 0.0};
   int phys[64];  // logical qubit -> physical bit
   size_t ring;   // next free offset inside the ring
   // per-pass timing of juqcs_run_circuit when profiling (else empty)
@@ -303,9 +306,20 @@ Gate make_gate1(int t, const C u[4]) {
   return g;
 }
 
-juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g) {
+juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g0) {
   hipError_t e = hipSuccess;
+  Gate g = g0;
+  if (g.nq == 1 && g.diag && !is_one(g.m[0]) && (g.m[0].re != 0.0 || g.m[0].im != 0.0)) {
+    // diag(a, b) = a diag(1, b / a): the factor a goes into the state's FP64
+    // global factor, and only the half with the target bit set is touched
+    const C a = g.m[0], b = g.m[3];
+    const double den = a.re * a.re + a.im * a.im;
+    g.m[0] = C{1.0, 0.0};
+    g.m[3] = C{(b.re * a.re + b.im * a.im) / den, (b.im * a.re - b.re * a.im) / den};
+    st->gf = cmul(st->gf, a);
+  }
   if (st->dt == JUQCS_ENC2) {
+    if (g.nq == 1 && g.diag && is_one(g.m[0]) && is_one(g.m[3])) return JUQCS_OK;
     std::vector<Gate> one{g};
     return tile_gates(st, one, 0, 0, nullptr);
   }
@@ -313,12 +327,13 @@ juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g) {
   prof_begin(st);
   if (g.nq == 1) {
     const C* u = g.m;
+    const C d1 = u[3];
     if (g.diag && is_one(u[0])) {
-      if (is_one(u[3])) {
+      if (is_one(d1)) {
         prof_end(st);
-        return JUQCS_OK;  // identity
+        return JUQCS_OK;  // identity (up to the global factor)
       }
-      e = launch_diag(st->dt, st->amps, st->n, uint64_t(1) << g.q[0], u[3], st->stream);
+      e = launch_diag(st->dt, st->amps, st->n, uint64_t(1) << g.q[0], d1, st->stream);
       st->bytes += 0.5 * full;
     } else {
       e = launch_1q(st->dt, st->amps, st->n, g.q[0], -1, u, st->stream);
@@ -505,7 +520,9 @@ juqcs_status juqcs_state_create(juqcs_state** out, int n, juqcs_dtype dt, int bl
     if (!d_scales) return fail(JUQCS_ERR_ARG, "null scale buffer");
     if (scale_bytes < need_s) return fail(JUQCS_ERR_SIZE, "scale buffer too small");
   }
-  if (d_work && work_bytes < need_w) return fail(JUQCS_ERR_SIZE, "workspace too small");
+  if (!d_work) return fail(JUQCS_ERR_ARG, "null workspace (juqcs_state_bytes gives its size)");
+  if (((uintptr_t)d_work & 255) != 0) return fail(JUQCS_ERR_ARG, "workspace not 256-byte aligned");
+  if (work_bytes < need_w) return fail(JUQCS_ERR_SIZE, "workspace too small");
   juqcs_state* st = new juqcs_state();
   st->n = n;
   st->dt = dt;
@@ -513,19 +530,8 @@ juqcs_status juqcs_state_create(juqcs_state** out, int n, juqcs_dtype dt, int bl
   st->amps = d_amps;
   st->scales = d_scales;
   st->stream = (hipStream_t)hip_stream;
-  st->own_work = false;
-  if (d_work) {
-    st->work = (char*)d_work;
-    st->work_bytes = work_bytes;
-  } else {
-    hipError_t e = hipMalloc((void**)&st->work, need_w);
-    if (e != hipSuccess) {
-      delete st;
-      return hip_fail(e, "workspace hipMalloc");
-    }
-    st->work_bytes = need_w;
-    st->own_work = true;
-  }
+  st->work = (char*)d_work;
+  st->work_bytes = work_bytes;
   st->ring = kRingOff;
   for (int q = 0; q < 64; ++q) st->phys[q] = q;
   *out = st;
@@ -534,10 +540,6 @@ juqcs_status juqcs_state_create(juqcs_state** out, int n, juqcs_dtype dt, int bl
 
 juqcs_status juqcs_state_destroy(juqcs_state* st) {
   if (!st) return JUQCS_OK;
-  if (st->own_work) {
-    (void)hipStreamSynchronize(st->stream);
-    (void)hipFree(st->work);
-  }
   delete st;
   return JUQCS_OK;
 }
@@ -552,6 +554,7 @@ juqcs_status juqcs_state_init(juqcs_state* st, uint64_t basis_index) {
   if (check_state(st)) return JUQCS_ERR_ARG;
   if (st->n < 64 && (basis_index >> st->n) != 0) return fail(JUQCS_ERR_ARG, "basis index >= 2^n");
   for (int q = 0; q < 64; ++q) st->phys[q] = q;
+  st->gf = C{1.0, 0.0};
   hipError_t e = launch_init(st->dt, st->amps, st->scales, st->n, st->B, basis_index, st->stream);
   if (e != hipSuccess) return hip_fail(e, "init launch");
   return JUQCS_OK;
@@ -697,7 +700,7 @@ juqcs_status juqcs_amplitudes_device(juqcs_state* st, const uint64_t* d_idx, siz
   int8_t phys[64];
   for (int q = 0; q < 64; ++q) phys[q] = (int8_t)st->phys[q];
   hipError_t e = launch_gather(st->dt, st->amps, st->scales, st->n, st->B, d_idx, count, phys,
-                               d_out, st->stream);
+                               st->gf, d_out, st->stream);
   if (e != hipSuccess) return hip_fail(e, "gather launch");
   return JUQCS_OK;
 }
@@ -733,7 +736,43 @@ juqcs_status juqcs_norm(juqcs_state* st, double* out) {
   e = hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
   if (juqcs_status rc = sync(st)) return rc;
+  *out *= st->gf.re * st->gf.re + st->gf.im * st->gf.im;
   if (!std::isfinite(*out)) return fail(JUQCS_ERR_NUMERIC, "norm is not finite");
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_set_global_factor(juqcs_state* st, const double g[2]) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!g) return fail(JUQCS_ERR_ARG, "null factor");
+  if (!finite8(g, 2)) return fail(JUQCS_ERR_NUMERIC, "non-finite factor");
+  st->gf = C{g[0], g[1]};
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_mul_global_factor(juqcs_state* st, const double f[2]) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!f) return fail(JUQCS_ERR_ARG, "null factor");
+  if (!finite8(f, 2)) return fail(JUQCS_ERR_NUMERIC, "non-finite factor");
+  st->gf = cmul(st->gf, C{f[0], f[1]});
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_get_global_factor(const juqcs_state* st, double g[2]) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!g) return fail(JUQCS_ERR_ARG, "null output");
+  g[0] = st->gf.re;
+  g[1] = st->gf.im;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_renormalize(juqcs_state* st, double* norm_before) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  double nrm = 0.0;
+  if (juqcs_status rc = juqcs_norm(st, &nrm)) return rc;
+  if (!(nrm > 0.0)) return fail(JUQCS_ERR_NUMERIC, "cannot renormalise a zero state");
+  const double f = 1.0 / std::sqrt(nrm);
+  st->gf = C{st->gf.re * f, st->gf.im * f};
+  if (norm_before) *norm_before = nrm;
   return JUQCS_OK;
 }
 
@@ -784,8 +823,9 @@ juqcs_status juqcs_expectations(juqcs_state* st, double* out) {
   e = hipMemcpyAsync(sums.data(), res, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
   if (juqcs_status rc = sync(st)) return rc;
+  const double g2 = st->gf.re * st->gf.re + st->gf.im * st->gf.im;
   for (int q = 0; q < n; ++q)
-    for (int c = 0; c < 3; ++c) out[3 * q + c] = 0.5 * (1.0 - sums[3 * st->phys[q] + c]);
+    for (int c = 0; c < 3; ++c) out[3 * q + c] = 0.5 * (1.0 - g2 * sums[3 * st->phys[q] + c]);
   return JUQCS_OK;
 }
 

@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -106,6 +107,52 @@ void parallel_for(int count, F f) {
   for (auto& x : th) x.join();
 }
 
+// Byte layout of a batch work list in device memory (every part 256-aligned).
+struct ListLayout {
+  size_t o_groups = 0, o_passes = 0, o_ops = 0, o_mats = 0, o_tickets = 0, o_soff = 0, o_nq = 0,
+         o_pos = 0, total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kMaxBatchQubits = 32;            // layout entries per circuit
+constexpr size_t kBatchStage = size_t(4) << 20;  // read-out staging after the list
+
+// Layout of a list of count circuits with the given totals of passes (one
+// group per pass), ops and coefficients, and the most passes of one circuit.
+ListLayout list_layout(int64_t count, int64_t passes, int64_t ops, int64_t mats, int64_t nrounds) {
+  ListLayout l;
+  l.o_groups = 0;
+  l.o_passes = align256(l.o_groups + passes * sizeof(BatchGroup));
+  l.o_ops = align256(l.o_passes + passes * sizeof(BatchPass));
+  l.o_mats = align256(l.o_ops + std::max<int64_t>(ops, 1) * sizeof(TileOp));
+  l.o_tickets = align256(l.o_mats + std::max<int64_t>(mats, 1) * sizeof(cplx<float>));
+  l.o_soff = align256(l.o_tickets + std::max<int64_t>(nrounds, 1) * sizeof(uint64_t));
+  l.o_nq = align256(l.o_soff + count * sizeof(uint64_t));
+  l.o_pos = align256(l.o_nq + count * sizeof(int32_t));
+  l.total = align256(l.o_pos + (size_t)count * kMaxBatchQubits);
+  return l;
+}
+
+ListLayout list_layout_of(const std::vector<TilePlan>& plans) {
+  int64_t passes = 0, ops = 0, mats = 0, rounds = 0;
+  for (const TilePlan& p : plans) {
+    passes += (int64_t)p.passes.size();
+    ops += (int64_t)p.ops.size();
+    mats += (int64_t)p.mats.size();
+    rounds = std::max<int64_t>(rounds, (int64_t)p.passes.size());
+  }
+  return list_layout((int64_t)plans.size(), passes, ops, mats, rounds);
+}
+
+// Host image of a work list: uploaded as is, then addressed through lay.
+struct HostList {
+  std::vector<char> image;
+  ListLayout lay;
+  BatchDevice dev{};  // round tables and counts; device pointers set by bind_list
+  int64_t tasks = 0, gate_apps = 0, passes = 0;
+};
+
 }  // namespace
 
 struct juqcs_batch {
@@ -113,15 +160,20 @@ struct juqcs_batch {
   std::vector<int32_t> n;
   std::vector<uint64_t> state_off;
   char* states = nullptr;
-  char* dbuf = nullptr;
+  std::vector<std::vector<Gate>> dec;  // decoded gates (the autotuner re-plans from them)
+  bool relabel = true;
+  HostList list;
+  std::vector<int> kin;     // chosen on-chip fusion width per circuit
+  std::vector<int8_t> pos;  // kMaxBatchQubits per circuit: physical bit of each qubit at the end
+  std::vector<char> keep;   // per circuit (empty: none): start from the state in the buffer, not |0...0>
+  // caller-owned workspace: the uploaded list, then the read-out staging
+  char* work = nullptr;
+  size_t work_bytes = 0;
+  bool bound = false;
   BatchDevice dev{};
   uint64_t* d_state_off = nullptr;
   int32_t* d_nq = nullptr;
-  int64_t tasks = 0, gate_apps = 0, passes = 0;
-  std::vector<int> kin;  // chosen on-chip fusion width per circuit
-  std::vector<int8_t> pos;  // kMaxBatchQubits per circuit: physical bit of each qubit at the end
   int8_t* d_pos = nullptr;
-  std::vector<char> keep;   // per circuit (empty: none): start from the state in the buffer, not |0...0>
   hipStream_t last_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -130,18 +182,13 @@ struct juqcs_batch {
 
 namespace {
 
-void free_batch(juqcs_batch* b) {
+void drop_graph(juqcs_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->dbuf) (void)hipFree(b->dbuf);
   b->gexec = nullptr;
   b->graph = nullptr;
-  b->dbuf = nullptr;
+  b->graph_stream = nullptr;
 }
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-constexpr int kMaxBatchQubits = 32;  // layout entries per circuit
 
 // Layout entries of circuit c from a schedule's final positions.
 void set_layout(juqcs_batch* B, int c, const std::vector<int>& final_pos) {
@@ -154,14 +201,14 @@ void set_layout(juqcs_batch* B, int c, const std::vector<int>& final_pos) {
     B->pos[(size_t)c * kMaxBatchQubits + q] = (int8_t)final_pos[q];
 }
 
-// Lays the plans out as one device work list (pass-major groups).
-juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
+// Lays the plans out as one work list image (pass-major groups).
+juqcs_status make_list(juqcs_batch* B, const std::vector<TilePlan>& plans, HostList* L) {
   std::vector<BatchPass> passes;
   std::vector<TileOp> ops;
   std::vector<cplx<float>> mats;
   std::vector<BatchGroup> groups;
   std::vector<int> first_pass(B->count);
-  B->tasks = B->gate_apps = B->passes = 0;
+  L->tasks = L->gate_apps = L->passes = 0;
   for (int c = 0; c < B->count; ++c) {
     const TilePlan& p = plans[c];
     first_pass[c] = (int)passes.size();
@@ -191,16 +238,16 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
       g.init = (i == 0 && (B->keep.empty() || !B->keep[c])) ? 1 : 0;
       groups.push_back(g);
     }
-    B->tasks += ntiles * (int64_t)p.passes.size();
-    B->passes += (int64_t)p.passes.size();
-    B->gate_apps += p.gates;
+    L->tasks += ntiles * (int64_t)p.passes.size();
+    L->passes += (int64_t)p.passes.size();
+    L->gate_apps += p.gates;
   }
   // pass-major order: pass index within the circuit, then circuit
   std::stable_sort(groups.begin(), groups.end(), [&](const BatchGroup& a, const BatchGroup& b) {
     return (a.pass - first_pass[a.circuit]) < (b.pass - first_pass[b.circuit]);
   });
   // rounds: groups of the same pass index, contiguous after the sort
-  BatchDevice& d = B->dev;
+  BatchDevice& d = L->dev;
   d.round_group.clear();
   d.round_chunk.clear();
   long long next = 0;
@@ -221,76 +268,77 @@ juqcs_status build_device(juqcs_batch* B, const std::vector<TilePlan>& plans) {
   d.nrounds = round + 1;
   d.round_group.push_back((int32_t)groups.size());
   d.round_chunk.push_back(next);
-  // one device buffer for everything
-  const size_t o_groups = 0;
-  const size_t o_passes = align256(o_groups + groups.size() * sizeof(BatchGroup));
-  const size_t o_ops = align256(o_passes + passes.size() * sizeof(BatchPass));
-  const size_t o_mats = align256(o_ops + std::max<size_t>(ops.size(), 1) * sizeof(TileOp));
-  const size_t o_tickets = align256(o_mats + std::max<size_t>(mats.size(), 1) * sizeof(cplx<float>));
-  const size_t o_soff = align256(o_tickets + std::max(d.nrounds, 1) * sizeof(uint64_t));
-  const size_t o_nq = align256(o_soff + B->count * sizeof(uint64_t));
-  const size_t o_pos = align256(o_nq + B->count * sizeof(int32_t));
-  const size_t total = align256(o_pos + (size_t)B->count * kMaxBatchQubits);
-  if (B->pos.size() != (size_t)B->count * kMaxBatchQubits) set_layout(B, 0, {});
-  std::vector<char> host(total, 0);
-  std::memcpy(host.data() + o_groups, groups.data(), groups.size() * sizeof(BatchGroup));
-  std::memcpy(host.data() + o_passes, passes.data(), passes.size() * sizeof(BatchPass));
-  std::memcpy(host.data() + o_ops, ops.data(), ops.size() * sizeof(TileOp));
-  std::memcpy(host.data() + o_mats, mats.data(), mats.size() * sizeof(cplx<float>));
-  std::memcpy(host.data() + o_soff, B->state_off.data(), B->count * sizeof(uint64_t));
-  std::memcpy(host.data() + o_nq, B->n.data(), B->count * sizeof(int32_t));
-  std::memcpy(host.data() + o_pos, B->pos.data(), B->pos.size());
-  hipError_t e = hipMalloc((void**)&B->dbuf, total);
-  if (e != hipSuccess) return hip_fail(e, "batch hipMalloc");
-  e = hipMemcpy(B->dbuf, host.data(), total, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "batch upload");
-  d.groups = (const BatchGroup*)(B->dbuf + o_groups);
   d.ngroups = (int)groups.size();
-  d.passes = (const BatchPass*)(B->dbuf + o_passes);
-  d.ops = (const TileOp*)(B->dbuf + o_ops);
-  d.mats = (const cplx<float>*)(B->dbuf + o_mats);
-  d.tickets = (uint64_t*)(B->dbuf + o_tickets);
   d.count = B->count;
   d.nchunks = next;
-  B->d_state_off = (uint64_t*)(B->dbuf + o_soff);
-  B->d_nq = (int32_t*)(B->dbuf + o_nq);
-  B->d_pos = (int8_t*)(B->dbuf + o_pos);
+  L->lay = list_layout(B->count, (int64_t)passes.size(), (int64_t)ops.size(), (int64_t)mats.size(),
+                       d.nrounds);
+  const ListLayout& l = L->lay;
+  if (B->pos.size() != (size_t)B->count * kMaxBatchQubits) set_layout(B, 0, {});
+  L->image.assign(l.total, 0);
+  char* h = L->image.data();
+  std::memcpy(h + l.o_groups, groups.data(), groups.size() * sizeof(BatchGroup));
+  std::memcpy(h + l.o_passes, passes.data(), passes.size() * sizeof(BatchPass));
+  std::memcpy(h + l.o_ops, ops.data(), ops.size() * sizeof(TileOp));
+  std::memcpy(h + l.o_mats, mats.data(), mats.size() * sizeof(cplx<float>));
+  std::memcpy(h + l.o_soff, B->state_off.data(), B->count * sizeof(uint64_t));
+  std::memcpy(h + l.o_nq, B->n.data(), B->count * sizeof(int32_t));
+  std::memcpy(h + l.o_pos, B->pos.data(), B->pos.size());
   return JUQCS_OK;
 }
 
-juqcs_status run_device(juqcs_batch* B, hipStream_t s) {
-  hipError_t e = launch_batch(B->states, B->dev, s);
+// Uploads a list image into dbuf (at least L.lay.total bytes) on stream s and
+// points dev at it.
+juqcs_status bind_list(const HostList& L, char* dbuf, BatchDevice* dev, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(dbuf, L.image.data(), L.lay.total, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "batch list upload");
+  *dev = L.dev;
+  dev->groups = (const BatchGroup*)(dbuf + L.lay.o_groups);
+  dev->passes = (const BatchPass*)(dbuf + L.lay.o_passes);
+  dev->ops = (const TileOp*)(dbuf + L.lay.o_ops);
+  dev->mats = (const cplx<float>*)(dbuf + L.lay.o_mats);
+  dev->tickets = (uint64_t*)(dbuf + L.lay.o_tickets);
+  return JUQCS_OK;
+}
+
+juqcs_status run_device(char* states, const BatchDevice& d, hipStream_t s) {
+  hipError_t e = launch_batch(states, d, s);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
   return JUQCS_OK;
 }
 
 // Timed trial of one circuit's plan (used by the autotuner): runs it as a
-// one-circuit batch on the circuit's own state buffer.
-double time_plan(char* states, uint64_t off, int n, const TilePlan& plan, hipStream_t s) {
-  juqcs_batch B;
-  B.count = 1;
-  B.n = {n};
-  B.state_off = {off};
-  B.states = states;
+// one-circuit batch on the circuit's own state region, with its work list
+// at the start of the batch's workspace.  Infinite when the list does not fit.
+double time_plan(juqcs_batch* B, int c, const TilePlan& plan, hipStream_t s) {
+  juqcs_batch T;
+  T.count = 1;
+  T.n = {B->n[c]};
+  T.state_off = {B->state_off[c]};
   std::vector<TilePlan> plans{plan};
-  if (build_device(&B, plans) != JUQCS_OK) {
-    free_batch(&B);
-    return 1e30;
-  }
+  HostList L;
+  if (make_list(&T, plans, &L) != JUQCS_OK || L.lay.total > B->work_bytes) return 1e30;
+  BatchDevice d{};
+  if (bind_list(L, B->work, &d, s) != JUQCS_OK) return 1e30;
   hipEvent_t a, b;
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
-  (void)run_device(&B, s);  // warm
+  (void)run_device(B->states, d, s);  // warm
   (void)hipEventRecord(a, s);
-  (void)run_device(&B, s);
+  (void)run_device(B->states, d, s);
   (void)hipEventRecord(b, s);
   (void)hipEventSynchronize(b);
   float ms = 1e30f;
   (void)hipEventElapsedTime(&ms, a, b);
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  free_batch(&B);
   return ms;
+}
+
+juqcs_status check_bound(const juqcs_batch* B) {
+  if (!B) return fail(JUQCS_ERR_ARG, "null batch");
+  if (!B->bound) return fail(JUQCS_ERR_ARG, "batch has no workspace bound (juqcs_batch_bind)");
+  return JUQCS_OK;
 }
 
 }  // namespace
@@ -299,21 +347,29 @@ extern "C" {
 
 juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
                                 const juqcs_gate* gates, const int64_t* offsets, void* d_states,
-                                const uint64_t* state_offset, const juqcs_plan_opts* opts) {
+                                size_t states_bytes, const uint64_t* state_offset,
+                                const juqcs_plan_opts* opts) {
   if (!out) return fail(JUQCS_ERR_ARG, "null output pointer");
   *out = nullptr;
   if (count < 1) return fail(JUQCS_ERR_ARG, "count must be >= 1");
   if (!n || !offsets || !d_states || !state_offset) return fail(JUQCS_ERR_ARG, "null argument");
+  if (((uintptr_t)d_states & 15) != 0) return fail(JUQCS_ERR_ARG, "state buffer not 16-byte aligned");
   if (offsets[0] != 0) return fail(JUQCS_ERR_ARG, "offsets[0] must be 0");
+  std::vector<std::pair<uint64_t, uint64_t>> ranges(count);
   for (int c = 0; c < count; ++c) {
     if (n[c] < 1 || n[c] > 30) return fail(JUQCS_ERR_ARG, "batch circuits need 1 <= n <= 30");
     if (offsets[c + 1] < offsets[c]) return fail(JUQCS_ERR_ARG, "offsets must not decrease");
     if (state_offset[c] & 15) return fail(JUQCS_ERR_ARG, "state offsets must be 16-byte aligned");
+    const uint64_t bytes = uint64_t(8) << n[c];
+    if (state_offset[c] > states_bytes || bytes > states_bytes - state_offset[c])
+      return fail(JUQCS_ERR_SIZE, "circuit " + std::to_string(c) + ": state past the end of the buffer");
+    ranges[c] = {state_offset[c], state_offset[c] + bytes};
   }
+  std::sort(ranges.begin(), ranges.end());
+  for (int c = 1; c < count; ++c)
+    if (ranges[c].first < ranges[c - 1].second) return fail(JUQCS_ERR_ARG, "state regions overlap");
   if (offsets[count] > 0 && !gates) return fail(JUQCS_ERR_ARG, "null gate array");
   const int fuse = opts ? opts->fuse_k : 0;
-  const bool autotune = opts && opts->autotune;
-  const bool relabel = !opts || opts->relabel >= 0;
   if (opts && (opts->relabel < -1 || opts->relabel > 1)) return fail(JUQCS_ERR_ARG, "relabel must be -1, 0 or 1");
   if (fuse < 0 || fuse > 4) return fail(JUQCS_ERR_ARG, "batch fuse_k must be 0 (auto) or 1..4");
   auto* B = new juqcs_batch();
@@ -321,75 +377,47 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
   B->n.assign(n, n + count);
   B->state_off.assign(state_offset, state_offset + count);
   B->states = (char*)d_states;
+  B->relabel = !opts || opts->relabel >= 0;
   B->kin.assign(count, 2);
   set_layout(B, 0, {});
-  std::vector<TilePlan> plans(count);
-  std::vector<std::vector<Gate>> dec(count);
+  B->dec.resize(count);
   std::string err;
   for (int c = 0; c < count; ++c) {
-    dec[c].resize(offsets[c + 1] - offsets[c]);
+    B->dec[c].resize(offsets[c + 1] - offsets[c]);
     for (int64_t i = offsets[c]; i < offsets[c + 1]; ++i)
-      if (!decode_gate(gates[i], n[c], &dec[c][i - offsets[c]], &err)) {
+      if (!decode_gate(gates[i], n[c], &B->dec[c][i - offsets[c]], &err)) {
         delete B;
         const bool numeric = err.find("non-finite") != std::string::npos;
         return fail(numeric ? JUQCS_ERR_NUMERIC : JUQCS_ERR_QUBIT,
                     "circuit " + std::to_string(c) + ": " + err);
       }
   }
-  // fusion width: fixed, modelled, or measured (one trial per qubit count)
-  if (!autotune) {
-    parallel_for(count, [&](int c) {
-      TileSchedule sched;
-      schedule_circuit(n[c], dec[c], &sched, relabel);
-      set_layout(B, c, sched.final_pos);
-      if (fuse > 0) {
-        emit_schedule(sched, dec[c], fuse, &plans[c], 0, batch_mma_cap());
-        B->kin[c] = fuse;
-        return;
-      }
-      double best = 1e300;
-      for (int k = 2; k <= 4; ++k) {
-        TilePlan p;
-        emit_schedule(sched, dec[c], k, &p, 0, batch_mma_cap());
-        const double cst = plan_cost(p);
-        if (cst < best) {
-          best = cst;
-          plans[c] = std::move(p);
-          B->kin[c] = k;
-        }
-      }
-    });
-  }
-  std::map<int, int> measured;
-  for (int c = 0; autotune && c < count; ++c) {
-    {
-      auto it = measured.find(n[c]);
-      if (it == measured.end()) {
-        double best = 1e30;
-        int bk = 2;
-        for (int k = 1; k <= 4; ++k) {
-          TilePlan p;
-          plan_circuit(n[c], dec[c], k, relabel, &p);
-          const double t = time_plan(B->states, B->state_off[c], n[c], p, nullptr);
-          if (t < best) {
-            best = t;
-            bk = k;
-          }
-        }
-        it = measured.emplace(n[c], bk).first;
-      }
-      B->kin[c] = it->second;
+  // fusion width: fixed, or the cost model's choice per circuit (the timed
+  // trials of juqcs_batch_autotune may replace it)
+  std::vector<TilePlan> plans(count);
+  parallel_for(count, [&](int c) {
+    TileSchedule sched;
+    schedule_circuit(n[c], B->dec[c], &sched, B->relabel);
+    set_layout(B, c, sched.final_pos);
+    if (fuse > 0) {
+      emit_schedule(sched, B->dec[c], fuse, &plans[c], 0, batch_mma_cap());
+      B->kin[c] = fuse;
+      return;
     }
-  }
-  if (autotune)
-    parallel_for(count, [&](int c) {
-      TileSchedule sched;
-      plan_circuit(n[c], dec[c], B->kin[c], relabel, &plans[c], &sched);
-      set_layout(B, c, sched.final_pos);
-    });
-  juqcs_status rc = build_device(B, plans);
+    double best = 1e300;
+    for (int k = 2; k <= 4; ++k) {
+      TilePlan p;
+      emit_schedule(sched, B->dec[c], k, &p, 0, batch_mma_cap());
+      const double cst = plan_cost(p);
+      if (cst < best) {
+        best = cst;
+        plans[c] = std::move(p);
+        B->kin[c] = k;
+      }
+    }
+  });
+  juqcs_status rc = make_list(B, plans, &B->list);
   if (rc != JUQCS_OK) {
-    free_batch(B);
     delete B;
     return rc;
   }
@@ -397,19 +425,78 @@ juqcs_status juqcs_batch_create(juqcs_batch** out, int count, const int* n,
   return JUQCS_OK;
 }
 
-juqcs_status juqcs_batch_run(juqcs_batch* B, void* hip_stream) {
+juqcs_status juqcs_batch_bytes(const juqcs_batch* B, size_t* work_bytes) {
+  if (!B || !work_bytes) return fail(JUQCS_ERR_ARG, "null argument");
+  *work_bytes = align256(B->list.lay.total) + kBatchStage;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_bind(juqcs_batch* B, void* d_work, size_t work_bytes, void* hip_stream) {
   if (!B) return fail(JUQCS_ERR_ARG, "null batch");
+  if (!d_work) return fail(JUQCS_ERR_ARG, "null workspace");
+  if (((uintptr_t)d_work & 255) != 0) return fail(JUQCS_ERR_ARG, "workspace not 256-byte aligned");
+  size_t need = 0;
+  (void)juqcs_batch_bytes(B, &need);
+  if (work_bytes < need) return fail(JUQCS_ERR_SIZE, "batch workspace smaller than juqcs_batch_bytes");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (B->last_stream) (void)hipStreamSynchronize(B->last_stream);
+  drop_graph(B);
+  B->work = (char*)d_work;
+  B->work_bytes = work_bytes;
+  B->bound = false;
+  if (juqcs_status rc = bind_list(B->list, B->work, &B->dev, s)) return rc;
+  const ListLayout& l = B->list.lay;
+  B->d_state_off = (uint64_t*)(B->work + l.o_soff);
+  B->d_nq = (int32_t*)(B->work + l.o_nq);
+  B->d_pos = (int8_t*)(B->work + l.o_pos);
+  hipError_t e = hipStreamSynchronize(s);  // the host image may change after this call
+  if (e != hipSuccess) return hip_fail(e, "batch bind");
+  B->bound = true;
+  B->last_stream = s;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_autotune(juqcs_batch* B, void* hip_stream) {
+  if (juqcs_status rc = check_bound(B)) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  drop_graph(B);
+  B->bound = false;  // the trials overwrite the uploaded list
+  std::map<int, int> best_k;
+  for (int c = 0; c < B->count; ++c) {
+    if (best_k.count(B->n[c])) continue;
+    double best = 1e30;
+    int bk = B->kin[c];
+    for (int k = 1; k <= 4; ++k) {
+      TilePlan p;
+      plan_circuit(B->n[c], B->dec[c], k, B->relabel, &p);
+      const double t = time_plan(B, c, p, s);
+      if (t < best) {
+        best = t;
+        bk = k;
+      }
+    }
+    best_k[B->n[c]] = bk;
+  }
+  std::vector<TilePlan> plans(B->count);
+  parallel_for(B->count, [&](int c) {
+    B->kin[c] = best_k[B->n[c]];
+    TileSchedule sched;
+    plan_circuit(B->n[c], B->dec[c], B->kin[c], B->relabel, &plans[c], &sched);
+    set_layout(B, c, sched.final_pos);
+  });
+  return make_list(B, plans, &B->list);
+}
+
+juqcs_status juqcs_batch_run(juqcs_batch* B, void* hip_stream) {
+  if (juqcs_status rc = check_bound(B)) return rc;
   hipStream_t s = (hipStream_t)hip_stream;
   B->last_stream = s;
-  if (!s) return run_device(B, s);  // the legacy default stream cannot be captured
+  if (!s) return run_device(B->states, B->dev, s);  // the legacy default stream cannot be captured
   if (!B->gexec || B->graph_stream != s) {
-    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
-    if (B->graph) (void)hipGraphDestroy(B->graph);
-    B->gexec = nullptr;
-    B->graph = nullptr;
+    drop_graph(B);
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    juqcs_status rc = run_device(B, s);
+    juqcs_status rc = run_device(B->states, B->dev, s);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
     if (rc != JUQCS_OK) return rc;
@@ -434,9 +521,9 @@ juqcs_status juqcs_batch_wait(juqcs_batch* B) {
 juqcs_status juqcs_batch_stats(const juqcs_batch* B, int64_t* tasks, int64_t* gate_apps,
                                int64_t* passes) {
   if (!B) return fail(JUQCS_ERR_ARG, "null batch");
-  if (tasks) *tasks = B->tasks;
-  if (gate_apps) *gate_apps = B->gate_apps;
-  if (passes) *passes = B->passes;
+  if (tasks) *tasks = B->list.tasks;
+  if (gate_apps) *gate_apps = B->list.gate_apps;
+  if (passes) *passes = B->list.passes;
   return JUQCS_OK;
 }
 
@@ -453,47 +540,75 @@ juqcs_status juqcs_batch_fusion(const juqcs_batch* B, int* kin) {
   return JUQCS_OK;
 }
 
+juqcs_status juqcs_batch_amplitudes_device(juqcs_batch* B, const uint64_t* d_idx, int m,
+                                           double* d_out, void* hip_stream) {
+  if (juqcs_status rc = check_bound(B)) return rc;
+  if (m < 0 || (m > 0 && (!d_idx || !d_out))) return fail(JUQCS_ERR_ARG, "bad index list");
+  hipError_t e = launch_batch_gather(B->states, B->d_state_off, B->d_nq, B->d_pos, B->count, m, d_idx,
+                                     d_out, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "batch gather launch");
+  return JUQCS_OK;
+}
+
 juqcs_status juqcs_batch_amplitudes(juqcs_batch* B, const uint64_t* idx, int m, double* out,
                                     void* hip_stream) {
-  if (!B) return fail(JUQCS_ERR_ARG, "null batch");
+  if (juqcs_status rc = check_bound(B)) return rc;
   if (m < 0 || (m > 0 && (!idx || !out))) return fail(JUQCS_ERR_ARG, "bad index list");
-  const size_t total = (size_t)B->count * m;
-  if (total == 0) return JUQCS_OK;
+  if (m == 0) return JUQCS_OK;
   hipStream_t s = (hipStream_t)hip_stream;
-  uint64_t* d_idx = nullptr;
-  double* d_out = nullptr;
-  hipError_t e = hipMalloc((void**)&d_idx, total * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&d_out, total * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMemcpyAsync(d_idx, idx, total * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = launch_batch_gather(B->states, B->d_state_off, B->d_nq, B->d_pos, B->count, m, d_idx, d_out, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out, d_out, total * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(d_idx);
-  (void)hipFree(d_out);
-  if (e != hipSuccess) return hip_fail(e, "batch amplitudes");
+  // circuits in chunks whose indices and results fit the staging area
+  const size_t per = (size_t)m * (sizeof(uint64_t) + 2 * sizeof(double));
+  const int chunk = (int)std::max<size_t>(1, kBatchStage / per);
+  if ((size_t)m * (sizeof(uint64_t) + 2 * sizeof(double)) > kBatchStage)
+    return fail(JUQCS_ERR_SIZE, "too many amplitudes per circuit for the staging area");
+  char* stage = B->work + align256(B->list.lay.total);
+  uint64_t* d_idx = (uint64_t*)stage;
+  double* d_out = (double*)(stage + align256((size_t)chunk * m * sizeof(uint64_t)));
+  for (int c0 = 0; c0 < B->count; c0 += chunk) {
+    const int c1 = std::min(B->count, c0 + chunk);
+    const size_t k = (size_t)(c1 - c0) * m;
+    hipError_t e = hipMemcpyAsync(d_idx, idx + (size_t)c0 * m, k * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_batch_gather(B->states, B->d_state_off + c0, B->d_nq + c0,
+                              B->d_pos + (size_t)c0 * kMaxBatchQubits, c1 - c0, m, d_idx, d_out, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out + 2 * (size_t)c0 * m, d_out, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch amplitudes");
+  }
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_batch_norms_device(juqcs_batch* B, double* d_out, void* hip_stream) {
+  if (juqcs_status rc = check_bound(B)) return rc;
+  if (!d_out) return fail(JUQCS_ERR_ARG, "null output");
+  hipError_t e = launch_batch_norms(B->states, B->d_state_off, B->d_nq, B->count, d_out,
+                                    (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "batch norms launch");
   return JUQCS_OK;
 }
 
 juqcs_status juqcs_batch_norms(juqcs_batch* B, double* out, void* hip_stream) {
-  if (!B || !out) return fail(JUQCS_ERR_ARG, "null argument");
+  if (juqcs_status rc = check_bound(B)) return rc;
+  if (!out) return fail(JUQCS_ERR_ARG, "null output");
   hipStream_t s = (hipStream_t)hip_stream;
-  double* d_out = nullptr;
-  hipError_t e = hipMalloc((void**)&d_out, B->count * sizeof(double));
-  if (e == hipSuccess) e = launch_batch_norms(B->states, B->d_state_off, B->d_nq, B->count, d_out, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out, d_out, B->count * sizeof(double), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(d_out);
-  if (e != hipSuccess) return hip_fail(e, "batch norms");
+  double* d_out = (double*)(B->work + align256(B->list.lay.total));
+  const int chunk = (int)(kBatchStage / sizeof(double));
+  for (int c0 = 0; c0 < B->count; c0 += chunk) {
+    const int c1 = std::min(B->count, c0 + chunk);
+    hipError_t e = launch_batch_norms(B->states, B->d_state_off + c0, B->d_nq + c0, c1 - c0, d_out, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out + c0, d_out, (c1 - c0) * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch norms");
+  }
   return JUQCS_OK;
 }
 
 juqcs_status juqcs_batch_destroy(juqcs_batch* B) {
   if (!B) return JUQCS_OK;
   if (B->last_stream) (void)hipStreamSynchronize(B->last_stream);
-  free_batch(B);
+  drop_graph(B);
   delete B;
   return JUQCS_OK;
 }
@@ -545,18 +660,15 @@ struct BranchPart {
   }
 };
 
-// Cuts the part before every run of its crossings, whether their bits are
-// fixed by the group (crossings < L) or free: the cut points do not depend
-// on L, so a leaf goes through the same plans, and holds the same bits, for
-// any group size.  Each segment is planned where the previous one left the
-// qubits.
-void cut_part(BranchPart* bp, int L) {
+// Cuts the part before every run of its crossings (consecutive gates of the
+// part), whatever the group size: the cut points and the segments' plans do
+// not depend on which crossings a group fixes, so a leaf goes through the
+// same plans, and holds the same bits, for any group size.  Each segment is
+// planned where the previous one left the qubits.
+void cut_part(BranchPart* bp) {
   const std::vector<std::pair<int, int>>& fr = bp->slots;
   const int ng = (int)bp->gates.size();
   bp->segs.clear();
-  bp->freek.clear();
-  for (auto& f : fr)
-    if (f.second >= L) bp->freek.push_back(f.second);
   BranchSeg pre;
   pre.g1 = fr.empty() ? ng : fr[0].first;
   bp->segs.push_back(std::move(pre));
@@ -566,10 +678,7 @@ void cut_part(BranchPart* bp, int L) {
     BranchSeg sg;
     sg.g0 = fr[i].first;
     sg.g1 = j < fr.size() ? fr[j].first : ng;
-    for (size_t t = i; t < j; ++t) {
-      sg.ks.push_back(fr[t].second);
-      sg.nfree += fr[t].second >= L ? 1 : 0;
-    }
+    for (size_t t = i; t < j; ++t) sg.ks.push_back(fr[t].second);
     bp->segs.push_back(std::move(sg));
     i = j;
   }
@@ -584,6 +693,17 @@ void cut_part(BranchPart* bp, int L) {
       for (int q = 0; q < bp->nloc; ++q) pos[q] = sg.sched.final_pos[pos[q]];
   }
   bp->phys = pos;
+}
+
+// Marks the crossings >= L as free (their bits vary within a group).
+void set_free(BranchPart* bp, int L) {
+  bp->freek.clear();
+  for (auto& f : bp->slots)
+    if (f.second >= L) bp->freek.push_back(f.second);
+  for (BranchSeg& sg : bp->segs) {
+    sg.nfree = 0;
+    for (int k : sg.ks) sg.nfree += k >= L ? 1 : 0;
+  }
 }
 
 // The plan of one tree node: segment sg of the part with its diagonals set,
@@ -612,19 +732,29 @@ TilePlan node_plan(const BranchPart& bp, const BranchSeg& sg, long long gi, int 
   return pl;
 }
 
-// Eq. (3) for count bitstrings of words 64-bit words each (see
-// juqcs_branch_amplitudes_wide).
-// dev: z and out are device pointers (the bitstrings are checked on the
-// device), else host arrays.
-juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count, const uint8_t* side,
-                               const uint64_t* z, int words, size_t count, int group_size, double* out,
-                               hipStream_t s, bool dev) {
+// What the Eq. (3) driver derives from the circuit before it touches the
+// device: the parts, their circuits with a placeholder diagonal at every
+// crossing, and their segments' plans.
+struct BranchJob {
+  int n = 0, P = 0, m = 0, words = 0;
+  size_t count = 0;
+  bool host_io = false;  // bitstrings and result in host arrays (staged in the workspace)
+  int local[kBranchMaxQubits] = {};
+  int nloc[kBranchMaxParts] = {};
+  BranchPart parts[kBranchMaxParts];
+};
+
+juqcs_status branch_prepare(int n, const juqcs_gate* gates, size_t gate_count, const uint8_t* side,
+                            int words, size_t count, bool host_io, BranchJob* J) {
   if (n < 2 || n > kBranchMaxQubits) return fail(JUQCS_ERR_ARG, "n must be in [2, 240]");
   if (words < (n + 63) / 64 || words > kBranchMaxWords)
     return fail(JUQCS_ERR_ARG, "words must be in [ceil(n / 64), 4]");
-  if (!side || (count > 0 && (!z || !out)) || (gate_count > 0 && !gates))
-    return fail(JUQCS_ERR_ARG, "null argument");
+  if (!side || (gate_count > 0 && !gates)) return fail(JUQCS_ERR_ARG, "null argument");
   if (count > (size_t)1 << 31) return fail(JUQCS_ERR_SIZE, "at most 2^31 bitstrings");
+  J->n = n;
+  J->words = words;
+  J->count = count;
+  J->host_io = host_io;
   // parts and local qubit numbers (ascending order inside a part)
   int P = 0;
   for (int q = 0; q < n; ++q) {
@@ -632,21 +762,14 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       return fail(JUQCS_ERR_ARG, "side[q] must be < " + std::to_string(kBranchMaxParts));
     P = std::max(P, side[q] + 1);
   }
-  int local[kBranchMaxQubits], nloc[kBranchMaxParts] = {};
-  for (int q = 0; q < n; ++q) local[q] = nloc[side[q]]++;
+  for (int q = 0; q < n; ++q) J->local[q] = J->nloc[side[q]]++;
   if (P < 2) return fail(JUQCS_ERR_ARG, "at least two parts");
   for (int p = 0; p < P; ++p)
-    if (nloc[p] < 1 || nloc[p] > 30) return fail(JUQCS_ERR_ARG, "each part needs 1..30 qubits");
-  // bits at or above n must be clear (only the words that can hold them)
-  for (int w = n / 64; !dev && w < words; ++w) {
-    const int lo = std::max(0, n - 64 * w);
-    const uint64_t bad = lo >= 64 ? 0 : ~0ull << lo;
-    for (size_t k = 0; k < count; ++k)
-      if (z[k * words + w] & bad) return fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
-  }
+    if (J->nloc[p] < 1 || J->nloc[p] > 30) return fail(JUQCS_ERR_ARG, "each part needs 1..30 qubits");
+  J->P = P;
   // part circuits with placeholder diagonals at every crossing gate; a
   // crossing CNOT is its CZ between Hadamards on the target (H X H = Z)
-  BranchPart parts[kBranchMaxParts];
+  BranchPart* parts = J->parts;
   int m = 0;
   std::string err;
   const double s2 = 1.0 / std::sqrt(2.0);
@@ -665,7 +788,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       const int t = g.q[1], pt = side[t];  // CNOT: q1 is the target
       Gate h{};
       h.nq = 1;
-      h.q[0] = local[t];
+      h.q[0] = J->local[t];
       h.q[1] = -1;
       h.m[0] = {s2, 0};
       h.m[1] = {s2, 0};
@@ -676,7 +799,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
         const int q = g.q[j], p = side[q];
         Gate d{};
         d.nq = 1;
-        d.q[0] = local[q];
+        d.q[0] = J->local[q];
         d.q[1] = -1;
         branch_diag(1, d.m);
         d.diag = true;
@@ -688,14 +811,127 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       continue;
     }
     const int p = side[g.q[0]];
-    for (int j = 0; j < g.nq; ++j) g.q[j] = local[g.q[j]];
+    for (int j = 0; j < g.nq; ++j) g.q[j] = J->local[g.q[j]];
     parts[p].gates.push_back(g);
   }
-  if (count == 0) return JUQCS_OK;
+  J->m = m;
   for (int p = 0; p < P; ++p) {
-    parts[p].nloc = nloc[p];
-    parts[p].sbytes = align256((size_t)8 << nloc[p]);
+    parts[p].nloc = J->nloc[p];
+    parts[p].sbytes = align256((size_t)8 << J->nloc[p]);
+    cut_part(&parts[p]);
   }
+  return JUQCS_OK;
+}
+
+// Workspace of a decomposition run whose groups fix the first L crossings
+// (2^(m-L) branches per group); byte offsets in the caller's buffer.
+struct BranchLayout {
+  int L = 0;
+  long long gsize = 1, ngroups = 1;
+  int nleaves = 0;
+  bool lds = false;
+  int32_t first[kBranchMaxParts + 1] = {};  // leaves part by part
+  size_t base[kBranchMaxParts] = {};        // byte offset of part p's leaves in the state region
+  size_t o_z = 0, o_zp = 0, o_tab = 0, o_bad = 0, o_acc = 0, o_off = 0, o_sum = 0, o_states = 0,
+         o_list = 0, total = 0;
+};
+
+// Free bits of segment sg and of the segments before it, with the first L
+// crossings fixed.
+int seg_free(const BranchSeg& sg, int L) {
+  int f = 0;
+  for (int k : sg.ks) f += k >= L ? 1 : 0;
+  return f;
+}
+
+BranchLayout branch_layout(const BranchJob& J, int L) {
+  BranchLayout B;
+  const int P = J.P, m = J.m;
+  B.L = L;
+  B.gsize = 1ll << (m - L);
+  B.ngroups = 1ll << L;
+  size_t states = 0;
+  for (int p = 0; p < P; ++p) {
+    const int R = J.parts[p].free_bits(L);
+    B.first[p + 1] = B.first[p] + (1 << R);
+    B.base[p] = states;
+    states += J.parts[p].sbytes << R;
+  }
+  B.nleaves = B.first[P];
+  B.lds = B.nleaves <= kBranchSumValues;
+  // the largest tree round's work list
+  size_t rounds = 0;
+  for (int p = 0; p < P; ++p) rounds = std::max(rounds, J.parts[p].segs.size());
+  size_t list = 0;
+  for (size_t r = 0; r < rounds; ++r) {
+    int64_t count = 0, passes = 0, ops = 0, mats = 0, nr = 0;
+    for (int p = 0; p < P; ++p) {
+      const BranchPart& bp = J.parts[p];
+      if (r >= bp.segs.size()) continue;
+      int done = 0;
+      for (size_t i = 0; i < r; ++i) done += seg_free(bp.segs[i], L);
+      const int64_t nodes = int64_t(1) << (done + seg_free(bp.segs[r], L));
+      const TilePlan& t = bp.segs[r].tmpl;
+      // an empty segment still runs one pass (the tree node's copy or init)
+      const int64_t np = std::max<int64_t>(1, (int64_t)t.passes.size());
+      count += nodes;
+      passes += nodes * np;
+      ops += nodes * (int64_t)t.ops.size();
+      mats += nodes * (int64_t)t.mats.size();
+      nr = std::max(nr, np);
+    }
+    list = std::max(list, list_layout(count, passes, ops, mats, nr).total);
+  }
+  const size_t cnt = J.count;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  B.o_z = take(J.host_io ? cnt * J.words * sizeof(uint64_t) : 0);
+  B.o_zp = take((size_t)P * cnt * sizeof(uint32_t));
+  B.o_tab = take(kBranchTabInts * sizeof(int32_t));
+  B.o_bad = take(sizeof(int));
+  B.o_acc = take(J.host_io ? cnt * 2 * sizeof(double) : 0);
+  B.o_off = take((size_t)B.nleaves * sizeof(uint64_t));
+  B.o_sum = take(B.lds ? (size_t)B.gsize * sizeof(uint64_t) : (size_t)B.gsize * P * sizeof(int32_t));
+  B.o_states = take(states);
+  B.o_list = take(list);
+  B.total = o;
+  return B;
+}
+
+// L for a group size (rounded down to a power of two; 0 = every branch).
+int group_bits(int m, int group_size) {
+  if (group_size <= 0) return 0;
+  int lg = 0;
+  while (lg < m && (2ll << lg) <= group_size) ++lg;
+  return m - lg;
+}
+
+// Eq. (3) for count bitstrings of words 64-bit words each (see
+// juqcs_branch_amplitudes_wide), in the caller's workspace.  dev: z and out
+// are device pointers (the bitstrings are checked on the device), else host
+// arrays.
+juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count, const uint8_t* side,
+                               const uint64_t* z, int words, size_t count, int group_size, double* out,
+                               void* d_work, size_t work_bytes, hipStream_t s, bool dev) {
+  if (count > 0 && (!z || !out)) return fail(JUQCS_ERR_ARG, "null argument");
+  auto J = std::make_unique<BranchJob>();
+  if (juqcs_status rc = branch_prepare(n, gates, gate_count, side, words, count, !dev, J.get())) return rc;
+  // bits at or above n must be clear (only the words that can hold them)
+  for (int w = n / 64; !dev && w < words; ++w) {
+    const int lo = std::max(0, n - 64 * w);
+    const uint64_t bad = lo >= 64 ? 0 : ~0ull << lo;
+    for (size_t k = 0; k < count; ++k)
+      if (z[k * words + w] & bad) return fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
+  }
+  if (count == 0) return JUQCS_OK;
+  if (!d_work) return fail(JUQCS_ERR_ARG, "null workspace (juqcs_branch_bytes gives its size)");
+  if (((uintptr_t)d_work & 255) != 0) return fail(JUQCS_ERR_ARG, "workspace not 256-byte aligned");
+  const int P = J->P, m = J->m;
+  BranchPart* parts = J->parts;
   // Branches are grouped by the bits of the first L crossings (circuit
   // order; those bits are fixed within a group, the others free).  Inside a
   // group a part's states form a tree: the gates before its first crossing
@@ -703,27 +939,20 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   // copy per setting of their free bits, which then runs the gates up to
   // the next run.  The leaves are the part's states for every setting of
   // its own free crossings; branches that agree on those share a leaf.
-  size_t budget = 0;
-  {
-    size_t freeb = 0, totalb = 0;
-    (void)hipMemGetInfo(&freeb, &totalb);
-    budget = std::min<size_t>(freeb / 2, (size_t)64 << 30);
-  }
-  auto leaf_bytes = [&](int L) {
-    size_t t = 0;
-    for (int p = 0; p < P; ++p) t += parts[p].sbytes << parts[p].free_bits(L);
-    return t;
-  };
-  int L = 0;
+  BranchLayout lay;
   if (group_size > 0) {
-    int lg = 0;
-    while (lg < m && (2ll << lg) <= group_size) ++lg;
-    L = m - lg;
+    lay = branch_layout(*J, group_bits(m, group_size));
+    if (lay.total > work_bytes) return fail(JUQCS_ERR_SIZE, "workspace too small for the group size");
   } else {
-    while (L < m && leaf_bytes(L) > budget) ++L;
+    int L = 0;
+    while (L < m && branch_layout(*J, L).total > work_bytes) ++L;
+    lay = branch_layout(*J, L);
+    if (lay.total > work_bytes) return fail(JUQCS_ERR_SIZE, "workspace too small for one branch");
   }
-  const long long gsize = 1ll << (m - L), ngroups = 1ll << L;
-  for (int p = 0; p < P; ++p) cut_part(&parts[p], L);
+  const int L = lay.L;
+  const long long gsize = lay.gsize, ngroups = lay.ngroups;
+  for (int p = 0; p < P; ++p) set_free(&parts[p], L);
+  char* W = (char*)d_work;
   // split table: each part's qubits and their physical bits at the leaves
   std::vector<int32_t> tab(kBranchTabInts, 0);
   {
@@ -736,25 +965,17 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       for (int q = 0; q < n; ++q) {
         if (side[q] != p) continue;
         qs[o] = q;
-        phys[o] = parts[p].phys[local[q]];
+        phys[o] = parts[p].phys[J->local[q]];
         ++o;
       }
     }
     first[P] = o;
   }
-  // leaves part by part: leaf l of part p (bit R-1-i of l = free crossing i)
-  int32_t first[kBranchMaxParts + 1] = {};
-  size_t base[kBranchMaxParts] = {}, total = 0;
-  for (int p = 0; p < P; ++p) {
-    first[p + 1] = first[p] + (1 << parts[p].freek.size());
-    base[p] = total;
-    total += parts[p].sbytes << parts[p].freek.size();
-  }
-  const int nleaves = first[P];
+  const int nleaves = lay.nleaves;
   std::vector<uint64_t> leaf_off(nleaves);
   for (int p = 0; p < P; ++p)
     for (int l = 0; l < (1 << parts[p].freek.size()); ++l)
-      leaf_off[first[p] + l] = base[p] + (size_t)l * parts[p].sbytes;
+      leaf_off[lay.first[p] + l] = lay.base[p] + (size_t)l * parts[p].sbytes;
   // the sum runs over branches in tree order: t ascending, where bit
   // m-1-k of t is crossing k's bit; a group is a range of t
   auto branch_of = [&](long long t) {
@@ -762,7 +983,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     for (int k = 0; k < m; ++k) b |= ((t >> (m - 1 - k)) & 1) << k;
     return b;
   };
-  const bool lds = nleaves <= kBranchSumValues;
+  const bool lds = lay.lds;
   std::vector<uint64_t> t8;
   std::vector<int32_t> t32;
   if (lds) t8.assign(gsize, 0);
@@ -774,32 +995,24 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       const int R = (int)fk.size();
       int l = 0;
       for (int i = 0; i < R; ++i) l |= (int)((b >> fk[i]) & 1) << (R - 1 - i);
-      if (lds) t8[j] |= (uint64_t)(first[p] + l) << (8 * p);
-      else t32[(size_t)j * P + p] = first[p] + l;
+      if (lds) t8[j] |= (uint64_t)(lay.first[p] + l) << (8 * p);
+      else t32[(size_t)j * P + p] = lay.first[p] + l;
     }
   }
   // bitstrings -> per-part indices on the device; acc holds the running sum
   // (the caller's out when it is on the device)
-  uint64_t* dz = nullptr;
-  uint32_t* zp = nullptr;
-  int32_t* dtab = nullptr;
-  int* dbad = nullptr;
-  double* acc = dev ? out : nullptr;
-  char* states = nullptr;
-  uint64_t* doff = nullptr;
-  void* dsum = nullptr;
+  uint64_t* dz = dev ? nullptr : (uint64_t*)(W + lay.o_z);
+  uint32_t* zp = (uint32_t*)(W + lay.o_zp);
+  int32_t* dtab = (int32_t*)(W + lay.o_tab);
+  int* dbad = (int*)(W + lay.o_bad);
+  double* acc = dev ? out : (double*)(W + lay.o_acc);
+  uint64_t* doff = (uint64_t*)(W + lay.o_off);
+  void* dsum = W + lay.o_sum;
+  char* states = W + lay.o_states;
+  char* dlist = W + lay.o_list;
   const size_t tbytes = lds ? t8.size() * 8 : t32.size() * 4;
   hipError_t e = hipSuccess;
-  if (!dev) e = hipMalloc((void**)&dz, count * words * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&zp, (size_t)P * count * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&dtab, tab.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&dbad, sizeof(int));
-  if (e == hipSuccess && !dev) e = hipMalloc((void**)&acc, count * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&doff, nleaves * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMalloc(&dsum, tbytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&states, total);
-  if (e == hipSuccess && !dev)
-    e = hipMemcpyAsync(dz, z, count * words * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+  if (!dev) e = hipMemcpyAsync(dz, z, count * words * sizeof(uint64_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -814,7 +1027,6 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   int bad = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(dz);
   juqcs_status rc = JUQCS_OK;
   if (e != hipSuccess) rc = hip_fail(e, "branch set-up");
   else if (bad) rc = fail(JUQCS_ERR_ARG, "bitstring >= 2^n");
@@ -838,10 +1050,10 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
             const long long parent = a << (R - done), leaf = parent + (c << after);
             plans.push_back(node_plan(bp, sg, gi, L, c));
             B.n.push_back(bp.nloc);
-            B.state_off.push_back(base[p] + (size_t)leaf * bp.sbytes);
+            B.state_off.push_back(lay.base[p] + (size_t)leaf * bp.sbytes);
             B.keep.push_back(r > 0 ? 1 : 0);
             if (r > 0 && c > 0) {  // the child starts as a copy of its parent
-              e = hipMemcpyAsync(states + B.state_off.back(), states + base[p] + (size_t)parent * bp.sbytes,
+              e = hipMemcpyAsync(states + B.state_off.back(), states + lay.base[p] + (size_t)parent * bp.sbytes,
                                  bp.sbytes, hipMemcpyDeviceToDevice, s);
               if (e != hipSuccess) rc = hip_fail(e, "branch state copy");
             }
@@ -850,21 +1062,26 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
       B.count = (int)plans.size();
       B.states = states;
       if (rc == JUQCS_OK && B.count > 0) {
-        rc = build_device(&B, plans);
-        if (rc == JUQCS_OK) rc = run_device(&B, s);
+        HostList hl;
+        BatchDevice d{};
+        rc = make_list(&B, plans, &hl);
+        if (rc == JUQCS_OK && hl.lay.total > lay.total - lay.o_list)
+          rc = fail(JUQCS_ERR_SIZE, "branch round list larger than its workspace share");
+        if (rc == JUQCS_OK) rc = bind_list(hl, dlist, &d, s);
+        if (rc == JUQCS_OK) rc = run_device(states, d, s);
         if (rc == JUQCS_OK) {
+          // the host image must outlive its upload
           e = hipStreamSynchronize(s);
           if (e != hipSuccess) rc = hip_fail(e, "branch batch");
         }
       }
-      free_batch(&B);
     }
     if (rc == JUQCS_OK) {
       const bool last = gi + 1 == ngroups;
       const double scale = std::ldexp(1.0, -m);
       if (lds) {
         BranchParts bp{};
-        for (int p = 0; p <= P; ++p) bp.first[p] = first[p];
+        for (int p = 0; p <= P; ++p) bp.first[p] = lay.first[p];
         e = launch_branch_sum_lds(states, doff, P, bp, gsize, (const uint64_t*)dsum, zp, (long long)count,
                                   acc, last, scale, s);
       } else {
@@ -890,40 +1107,49 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "branch result copy");
   }
-  (void)hipFree(states);
-  (void)hipFree(dsum);
-  (void)hipFree(doff);
-  (void)hipFree(zp);
-  (void)hipFree(dtab);
-  (void)hipFree(dbad);
-  if (!dev) (void)hipFree(acc);
   return rc;
 }
 
 }  // namespace
 
+extern "C" juqcs_status juqcs_branch_bytes(int n, const juqcs_gate* gates, size_t gate_count,
+                                           const uint8_t* side, int words, size_t count,
+                                           int group_size, int host_io, size_t* min_bytes,
+                                           size_t* bytes) {
+  if (!min_bytes || !bytes) return fail(JUQCS_ERR_ARG, "null output");
+  auto J = std::make_unique<BranchJob>();
+  if (juqcs_status rc = branch_prepare(n, gates, gate_count, side, words, count, host_io != 0, J.get()))
+    return rc;
+  *min_bytes = branch_layout(*J, J->m).total;
+  *bytes = branch_layout(*J, group_bits(J->m, group_size)).total;
+  return JUQCS_OK;
+}
+
 extern "C" juqcs_status juqcs_branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count,
                                                 const uint8_t* side, const uint64_t* z,
                                                 size_t count, int group_size, double* out,
+                                                void* d_work, size_t work_bytes,
                                                 void* hip_stream) {
   if (n < 2 || n > 62) return fail(JUQCS_ERR_ARG, "n must be in [2, 62]");
-  return branch_amplitudes(n, gates, gate_count, side, z, 1, count, group_size, out,
+  return branch_amplitudes(n, gates, gate_count, side, z, 1, count, group_size, out, d_work, work_bytes,
                            (hipStream_t)hip_stream, false);
 }
 
 extern "C" juqcs_status juqcs_branch_amplitudes_wide(int n, const juqcs_gate* gates, size_t gate_count,
                                                      const uint8_t* side, const uint64_t* z, int words,
                                                      size_t count, int group_size, double* out,
+                                                     void* d_work, size_t work_bytes,
                                                      void* hip_stream) {
-  return branch_amplitudes(n, gates, gate_count, side, z, words, count, group_size, out,
-                           (hipStream_t)hip_stream, false);
+  return branch_amplitudes(n, gates, gate_count, side, z, words, count, group_size, out, d_work,
+                           work_bytes, (hipStream_t)hip_stream, false);
 }
 
 extern "C" juqcs_status juqcs_branch_amplitudes_device(int n, const juqcs_gate* gates,
                                                        size_t gate_count, const uint8_t* side,
                                                        const uint64_t* d_z, int words, size_t count,
                                                        int group_size, double* d_out,
+                                                       void* d_work, size_t work_bytes,
                                                        void* hip_stream) {
-  return branch_amplitudes(n, gates, gate_count, side, d_z, words, count, group_size, d_out,
-                           (hipStream_t)hip_stream, true);
+  return branch_amplitudes(n, gates, gate_count, side, d_z, words, count, group_size, d_out, d_work,
+                           work_bytes, (hipStream_t)hip_stream, true);
 }

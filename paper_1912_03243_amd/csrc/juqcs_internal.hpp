@@ -160,7 +160,7 @@ hipError_t launch_norm(juqcs_dtype dt, const void* amps, const void* scales,
                        hipStream_t s);
 hipError_t launch_gather(juqcs_dtype dt, const void* amps, const void* scales,
                          int n, int block_bits, const uint64_t* idx,
-                         uint64_t count, const int8_t* phys, double* out,
+                         uint64_t count, const int8_t* phys, cplx<double> g, double* out,
                          hipStream_t s);
 hipError_t launch_scale(juqcs_dtype dt, void* amps, void* scales, int n,
                         int block_bits, double f, hipStream_t s);

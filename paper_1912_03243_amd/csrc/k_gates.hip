@@ -210,10 +210,16 @@ __device__ inline uint64_t to_phys(uint64_t z, int n, const PhysMap& m) {
   return out;
 }
 
+// out[k] = g psi[phys(idx[k])] in FP64 (g: the state's global factor).
+__device__ inline void put_amp(double* out, uint64_t k, double re, double im, cplx<double> g) {
+  out[2 * k] = g.re * re - g.im * im;
+  out[2 * k + 1] = g.re * im + g.im * re;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(const cplx<T>* __restrict__ psi, int n,
                                                      const uint64_t* __restrict__ idx,
-                                                     uint64_t count, PhysMap pm,
+                                                     uint64_t count, PhysMap pm, cplx<double> g,
                                                      double* __restrict__ out) {
   const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   if (k >= count) return;
@@ -223,8 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(const cplx<T>* __restrict__
     return;
   }
   const cplx<T> v = psi[to_phys(z, n, pm)];
-  out[2 * k] = (double)v.re;
-  out[2 * k + 1] = (double)v.im;
+  put_amp(out, k, (double)v.re, (double)v.im, g);
 }
 
 __global__ __launch_bounds__(kThreads) void k_gather_enc2(const char2* __restrict__ codes,
@@ -232,6 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_enc2(const char2* __restric
                                                           int n, int block_bits,
                                                           const uint64_t* __restrict__ idx,
                                                           uint64_t count, PhysMap pm,
+                                                          cplx<double> g,
                                                           double* __restrict__ out) {
   const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   if (k >= count) return;
@@ -242,8 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_enc2(const char2* __restric
   const uint64_t i = to_phys(idx[k], n, pm);
   const char2 q = codes[i];
   const float d = scales[i >> block_bits] / 127.0f;
-  out[2 * k] = (double)((float)q.x * d);
-  out[2 * k + 1] = (double)((float)q.y * d);
+  put_amp(out, k, (double)((float)q.x * d), (double)((float)q.y * d), g);
 }
 
 // --------------------------------------------------------------- scale ----
@@ -413,7 +418,7 @@ hipError_t launch_norm(juqcs_dtype dt, const void* amps, const void* scales, int
 
 hipError_t launch_gather(juqcs_dtype dt, const void* amps, const void* scales, int n,
                          int block_bits, const uint64_t* idx, uint64_t count,
-                         const int8_t* phys, double* out, hipStream_t s) {
+                         const int8_t* phys, cplx<double> g, double* out, hipStream_t s) {
   if (count == 0) return hipSuccess;
   PhysMap pm;
   pm.identity = 1;
@@ -423,13 +428,13 @@ hipError_t launch_gather(juqcs_dtype dt, const void* amps, const void* scales, i
   const dim3 grid(grid_for(count, kThreads));
   if (dt == JUQCS_C128)
     hipLaunchKernelGGL(k_gather<double>, grid, dim3(kThreads), 0, s, (const cplx<double>*)amps, n,
-                       idx, count, pm, out);
+                       idx, count, pm, g, out);
   else if (dt == JUQCS_C64)
     hipLaunchKernelGGL(k_gather<float>, grid, dim3(kThreads), 0, s, (const cplx<float>*)amps, n,
-                       idx, count, pm, out);
+                       idx, count, pm, g, out);
   else
     hipLaunchKernelGGL(k_gather_enc2, grid, dim3(kThreads), 0, s, (const char2*)amps,
-                       (const float*)scales, n, block_bits, idx, count, pm, out);
+                       (const float*)scales, n, block_bits, idx, count, pm, g, out);
   return hipGetLastError();
 }
 

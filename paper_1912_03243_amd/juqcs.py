@@ -80,22 +80,34 @@ _SIGS = {
     "juqcs_get_layout": [_P, ct.POINTER(_I)],
     "juqcs_encode2": [_P, _I, _U64, _I, _P, _P, _P],
     "juqcs_decode2": [_P, _P, _U64, _I, _P, _I, _P],
-    "juqcs_batch_create": [ct.POINTER(_P), _I, ct.POINTER(_I), _P, ct.POINTER(ct.c_int64), _P,
+    "juqcs_set_global_factor": [_P, _DP],
+    "juqcs_mul_global_factor": [_P, _DP],
+    "juqcs_get_global_factor": [_P, _DP],
+    "juqcs_renormalize": [_P, _DP],
+    "juqcs_batch_create": [ct.POINTER(_P), _I, ct.POINTER(_I), _P, ct.POINTER(ct.c_int64), _P, _S,
                            ct.POINTER(_U64), ct.POINTER(PlanOpts)],
+    "juqcs_batch_bytes": [_P, ct.POINTER(_S)],
+    "juqcs_batch_bind": [_P, _P, _S, _P],
+    "juqcs_batch_autotune": [_P, _P],
     "juqcs_batch_run": [_P, _P],
     "juqcs_batch_wait": [_P],
     "juqcs_batch_fusion": [_P, ct.POINTER(_I)],
     "juqcs_batch_layout": [_P, _I, ct.POINTER(_I)],
     "juqcs_batch_amplitudes": [_P, ct.POINTER(_U64), _I, _DP, _P],
+    "juqcs_batch_amplitudes_device": [_P, _P, _I, _P, _P],
     "juqcs_batch_norms": [_P, _DP, _P],
+    "juqcs_batch_norms_device": [_P, _P, _P],
     "juqcs_batch_stats": [_P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
                           ct.POINTER(ct.c_int64)],
     "juqcs_batch_destroy": [_P],
     "juqcs_branch_amplitudes": [_I, _P, _S, ct.POINTER(ct.c_uint8), ct.POINTER(_U64), _S, _I,
-                                _DP, _P],
+                                _DP, _P, _S, _P],
     "juqcs_branch_amplitudes_wide": [_I, _P, _S, ct.POINTER(ct.c_uint8), ct.POINTER(_U64), _I, _S,
-                                     _I, _DP, _P],
-    "juqcs_branch_amplitudes_device": [_I, _P, _S, ct.POINTER(ct.c_uint8), _P, _I, _S, _I, _P, _P],
+                                     _I, _DP, _P, _S, _P],
+    "juqcs_branch_amplitudes_device": [_I, _P, _S, ct.POINTER(ct.c_uint8), _P, _I, _S, _I, _P,
+                                       _P, _S, _P],
+    "juqcs_branch_bytes": [_I, _P, _S, ct.POINTER(ct.c_uint8), _I, _S, _I, _I, ct.POINTER(_S),
+                           ct.POINTER(_S)],
     "juqcs_copy": [_P, _P, _S, _P],
 }
 EXPORTED = sorted(list(_SIGS) + ["juqcs_last_error", "juqcs_version"])
@@ -169,42 +181,92 @@ def juqcs_copy(dst, src, nbytes: int, stream=None):
            "juqcs_copy")
 
 
-def juqcs_branch_amplitudes(n: int, gates, side, z, group_size: int = 0, stream=None) -> np.ndarray:
+def juqcs_branch_bytes(n: int, gates, side, words: int, count: int, group_size: int = 0,
+                       host_io: bool = True):
+    """(min_bytes, bytes): workspace of the decomposition for groups of one
+    branch, and for group_size (0: all branches in one group)."""
+    g = _gates(gates)
+    side = np.ascontiguousarray(side, dtype=np.uint8)
+    mn, full = _S(), _S()
+    _check(_lib.juqcs_branch_bytes(n, g.ctypes.data, g.size, side.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                                   words, count, group_size, int(host_io), ct.byref(mn), ct.byref(full)),
+           "juqcs_branch_bytes")
+    return mn.value, full.value
+
+
+# Workspace of a decomposition with group_size 0: all branches in one group
+# when that fits half the free device memory (at most about 64 GiB), else as much
+# as that budget holds (the library then takes the largest group that fits).
+_BRANCH_BUDGET = 66 << 30  # 64 GiB of part states plus the other arrays
+
+
+def branch_workspace(n, gates, side, words, count, group_size=0, host_io=True, device="cuda"):
+    """A torch device buffer for the decomposition calls (juqcs_branch_bytes'
+    size for group_size; for group_size 0 the budget above)."""
+    import torch
+    g = _gates(gates)
+    if count == 0:
+        return None
+    mn, full = juqcs_branch_bytes(n, g, side, words, count, group_size, host_io)
+    need = full
+    if group_size <= 0:
+        free, _ = torch.cuda.mem_get_info(torch.device(device))
+        need = max(mn, min(full, free // 2, _BRANCH_BUDGET))
+    return torch.empty(need, dtype=torch.uint8, device=device)
+
+
+def juqcs_branch_amplitudes(n: int, gates, side, z, group_size: int = 0, stream=None,
+                            device="cuda", work=None) -> np.ndarray:
     """<z|C|0> by the Eq. (3) decomposition.  z: a 1-D uint64 array of
     bitstrings (n <= 62), or a (count, words) array of little-endian uint64
-    words (n <= 240, juqcs_branch_amplitudes_wide)."""
+    words (n <= 240, juqcs_branch_amplitudes_wide).  The device workspace
+    is a torch buffer sized by juqcs_branch_bytes."""
     g = _gates(gates)
     side = np.ascontiguousarray(side, dtype=np.uint8)
     z = np.ascontiguousarray(z, dtype=np.uint64)
     count = z.shape[0] if z.ndim == 2 else z.size
+    words = z.shape[1] if z.ndim == 2 else 1
     out = np.empty(2 * count, dtype=np.float64)
     sp = side.ctypes.data_as(ct.POINTER(ct.c_uint8))
     zp = z.ctypes.data_as(ct.POINTER(_U64))
+    if work is None:
+        work = branch_workspace(n, g, side, words, count, group_size, True, device)
+    wp = work.data_ptr() if work is not None else None
+    wb = work.numel() if work is not None else 0
     if z.ndim == 2:
-        _check(_lib.juqcs_branch_amplitudes_wide(n, g.ctypes.data, g.size, sp, zp, z.shape[1], count,
-                                                 group_size, _dptr(out), _stream_handle(stream)),
+        _check(_lib.juqcs_branch_amplitudes_wide(n, g.ctypes.data, g.size, sp, zp, words, count,
+                                                 group_size, _dptr(out), wp, wb,
+                                                 _stream_handle(stream)),
                "juqcs_branch_amplitudes_wide")
     else:
         _check(_lib.juqcs_branch_amplitudes(n, g.ctypes.data, g.size, sp, zp, count, group_size,
-                                            _dptr(out), _stream_handle(stream)),
+                                            _dptr(out), wp, wb, _stream_handle(stream)),
                "juqcs_branch_amplitudes")
     return out.view(np.complex128)  # (re, im) pairs
 
 
-def juqcs_branch_amplitudes_device(n: int, gates, side, z, out, group_size: int = 0, stream=None):
+def juqcs_branch_amplitudes_device(n: int, gates, side, z, out, group_size: int = 0, stream=None,
+                                   work=None):
     """juqcs_branch_amplitudes with device tensors: z an int64 (count, words)
     tensor of little-endian 64-bit words, out a float64 tensor of 2*count
-    (re, im) pairs, both on the GPU (torch owns the memory)."""
+    (re, im) pairs, both on the GPU (torch owns the memory).  work: an
+    optional uint8 device tensor to use as the workspace (else one is
+    allocated for the call)."""
     g = _gates(gates)
     side = np.ascontiguousarray(side, dtype=np.uint8)
     if z.dim() != 2 or not z.is_contiguous() or z.dtype.itemsize != 8:
         raise ValueError("z: contiguous (count, words) tensor of 64-bit words")
     if out.numel() != 2 * z.shape[0] or not out.is_contiguous() or out.element_size() != 8:
         raise ValueError("out: contiguous float64 tensor of 2*count elements")
+    if work is None:
+        work = branch_workspace(n, g, side, z.shape[1], z.shape[0], group_size, False, z.device)
     _check(_lib.juqcs_branch_amplitudes_device(n, g.ctypes.data, g.size,
                                                side.ctypes.data_as(ct.POINTER(ct.c_uint8)),
                                                z.data_ptr(), z.shape[1], z.shape[0], group_size,
-                                               out.data_ptr(), _stream_handle(stream)),
+                                               out.data_ptr(),
+                                               work.data_ptr() if work is not None else None,
+                                               work.numel() if work is not None else 0,
+                                               _stream_handle(stream)),
            "juqcs_branch_amplitudes_device")
     return out
 
@@ -320,32 +382,68 @@ class State:
         _check(_lib.juqcs_get_layout(self.h, p), "juqcs_get_layout")
         return list(p)
 
+    def global_factor(self) -> complex:
+        g = np.zeros(2)
+        _check(_lib.juqcs_get_global_factor(self.h, _dptr(g)), "juqcs_get_global_factor")
+        return complex(g[0], g[1])
+
+    def set_global_factor(self, g: complex):
+        a = np.array([complex(g).real, complex(g).imag])
+        _check(_lib.juqcs_set_global_factor(self.h, _dptr(a)), "juqcs_set_global_factor")
+
+    def mul_global_factor(self, f: complex):
+        a = np.array([complex(f).real, complex(f).imag])
+        _check(_lib.juqcs_mul_global_factor(self.h, _dptr(a)), "juqcs_mul_global_factor")
+
+    def renormalize(self) -> float:
+        out = np.zeros(1)
+        _check(_lib.juqcs_renormalize(self.h, _dptr(out)), "juqcs_renormalize")
+        return float(out[0])
+
     def state_vector(self) -> np.ndarray:
-        """Whole state in logical order as complex128 (host copy).  The data
-        are read where they are (a qubit layout left by relabeling or
-        permute() is undone on the host), so reading never changes the
-        state (moving two-byte data would re-encode it)."""
+        """Whole state in logical order as complex128 (host copy), read by
+        the library: juqcs_amplitudes_device over every basis index (the
+        library maps each through the qubit layout, decodes two-byte
+        amplitudes and applies the global factor), in chunks of 2^22."""
         import torch
-        layout = self.layout()
+        count = 1 << self.n
+        chunk = min(count, 1 << 22)
+        dev = self.amps.device
+        idx = torch.empty(chunk, dtype=torch.int64, device=dev)
+        out = torch.empty(2 * chunk, dtype=torch.float64, device=dev)
+        res = np.empty(count, dtype=np.complex128)
+        for a in range(0, count, chunk):
+            torch.arange(a, a + chunk, dtype=torch.int64, device=dev, out=idx)
+            if self.stream is not None:
+                torch.cuda.current_stream(dev).synchronize()
+            _check(_lib.juqcs_amplitudes_device(self.h, idx.data_ptr(), chunk, out.data_ptr()),
+                   "juqcs_amplitudes_device")
+            self._sync()
+            res[a:a + chunk] = out.cpu().numpy().view(np.complex128)
+        return res
+
+    def _sync(self):
+        import torch
+        if self.stream is None:
+            torch.cuda.current_stream(self.amps.device).synchronize()
+        elif hasattr(self.stream, "synchronize"):
+            self.stream.synchronize()
+        else:
+            torch.cuda.synchronize(self.amps.device)
+
+    def raw_vector(self) -> np.ndarray:
+        """The stored C128/C64 amplitudes in physical order, without the
+        global factor (host copy)."""
+        import torch
+        self._sync()
         if self.dtype == C128:
             t = self.amps[: (1 << self.n) * 16].view(torch.float64)
         elif self.dtype == C64:
             t = self.amps[: (1 << self.n) * 8].view(torch.float32)
         else:
-            t = torch.empty(2 << self.n, dtype=torch.float32, device=self.amps.device)
-            juqcs_decode2(self.amps, self.scales, 1 << self.n, self.block_bits, t, C64,
-                          self.stream)
-        torch.cuda.synchronize()
+            raise ValueError("raw_vector: C128 or C64 states only (raw_codes for ENC2)")
         a = t.cpu().numpy().astype(np.float64)
-        phys = a[0::2] + 1j * a[1::2]
-        if layout == list(range(self.n)):
-            return phys
-        # logical index x sits at physical index sum_q bit_q(x) << layout[q]
-        x = np.arange(1 << self.n, dtype=np.int64)
-        p = np.zeros_like(x)
-        for q, pq in enumerate(layout):
-            p |= ((x >> q) & 1) << pq
-        return phys[p]
+        return a[0::2] + 1j * a[1::2]
 
     def raw_codes(self):
         """(codes int8 (2^n, 2), scales float32) of an ENC2 state (host copies)."""
@@ -359,10 +457,14 @@ class State:
 
 # ---- Batch --------------------------------------------------------------------
 class Batch:
-    """Many independent C64 circuits executed by one graph launch (one kernel per pass round)."""
+    """Many independent C64 circuits executed by one graph launch (one kernel
+    per pass round).  torch owns the state buffer and the workspace; the
+    library plans on the host (juqcs_batch_create), reports the workspace
+    size (juqcs_batch_bytes) and uploads its work list there
+    (juqcs_batch_bind)."""
 
     def __init__(self, circuits, device="cuda", states=None, fuse_k: int = 0,
-                 autotune: bool = False, relabel: int = 0):
+                 autotune: bool = False, relabel: int = 0, stream=None):
         import torch
         ns = np.array([n for n, _ in circuits], dtype=np.int32)
         offs = np.zeros(len(circuits) + 1, dtype=np.int64)
@@ -378,6 +480,7 @@ class Batch:
             run += int((s + 255) // 256 * 256)
         self.n = ns
         self.state_offset = soff
+        self.device = device
         self.states = states if states is not None else torch.empty(max(run, 256), dtype=torch.uint8,
                                                                      device=device)
         o = PlanOpts(mode=PLAN_TILE, fuse_k=fuse_k, autotune=int(autotune), relabel=relabel)
@@ -386,9 +489,29 @@ class Batch:
                                        ns.ctypes.data_as(ct.POINTER(_I)), allg.ctypes.data,
                                        offs.ctypes.data_as(ct.POINTER(ct.c_int64)),
                                        self.states.data_ptr(),
+                                       self.states.numel() * self.states.element_size(),
                                        soff.ctypes.data_as(ct.POINTER(_U64)), ct.byref(o)),
                "juqcs_batch_create")
         self.h = h
+        self.work = None
+        self._bind(stream)
+        if autotune:
+            _check(_lib.juqcs_batch_autotune(self.h, _stream_handle(stream)), "juqcs_batch_autotune")
+            self._bind(stream)
+
+    def bytes(self) -> int:
+        b = _S()
+        _check(_lib.juqcs_batch_bytes(self.h, ct.byref(b)), "juqcs_batch_bytes")
+        return b.value
+
+    def _bind(self, stream=None):
+        import torch
+        need = self.bytes()
+        if self.work is None or self.work.numel() < need:
+            self.work = None
+            self.work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        _check(_lib.juqcs_batch_bind(self.h, self.work.data_ptr(), self.work.numel(),
+                                     _stream_handle(stream)), "juqcs_batch_bind")
 
     def run(self, stream=None):
         _check(_lib.juqcs_batch_run(self.h, _stream_handle(stream)), "juqcs_batch_run")
@@ -411,11 +534,25 @@ class Batch:
                "juqcs_batch_amplitudes")
         return (out[0::2] + 1j * out[1::2]).reshape(z.shape)
 
+    def amplitudes_device(self, d_idx, m: int, d_out, stream=None):
+        """d_idx: (count*m) int64 device tensor; d_out: 2*count*m float64."""
+        if d_idx.numel() != len(self.n) * m or d_out.numel() != 2 * len(self.n) * m:
+            raise ValueError("d_idx: count*m indices, d_out: 2*count*m doubles")
+        _check(_lib.juqcs_batch_amplitudes_device(self.h, d_idx.data_ptr(), m, d_out.data_ptr(),
+                                                  _stream_handle(stream)),
+               "juqcs_batch_amplitudes_device")
+
     def norms(self, stream=None) -> np.ndarray:
         out = np.empty(len(self.n), dtype=np.float64)
         _check(_lib.juqcs_batch_norms(self.h, _dptr(out), _stream_handle(stream)),
                "juqcs_batch_norms")
         return out
+
+    def norms_device(self, d_out, stream=None):
+        if d_out.numel() != len(self.n):
+            raise ValueError("d_out: one double per circuit")
+        _check(_lib.juqcs_batch_norms_device(self.h, d_out.data_ptr(), _stream_handle(stream)),
+               "juqcs_batch_norms_device")
 
     def stats(self):
         a, b, c = ct.c_int64(), ct.c_int64(), ct.c_int64()
@@ -428,23 +565,21 @@ class Batch:
         _check(_lib.juqcs_batch_layout(self.h, i, p), "juqcs_batch_layout")
         return list(p)
 
-    def state_vector(self, i: int) -> np.ndarray:
-        """State of circuit i in logical order (the relabeled layout is undone
-        on the host)."""
+    def state_vector(self, i: int, stream=None) -> np.ndarray:
+        """State of circuit i in logical order, read by the library
+        (juqcs_batch_amplitudes_device over every basis index of circuit i;
+        the other circuits read index 0)."""
         import torch
-        torch.cuda.synchronize()
         n = int(self.n[i])
-        off = int(self.state_offset[i])
-        a = self.states[off: off + (8 << n)].view(torch.float32).cpu().numpy().astype(np.float64)
-        phys = a[0::2] + 1j * a[1::2]
-        layout = self.layout(i)
-        if layout == list(range(n)):
-            return phys
-        x = np.arange(1 << n, dtype=np.int64)
-        p = np.zeros_like(x)
-        for q, pq in enumerate(layout):
-            p |= ((x >> q) & 1) << pq
-        return phys[p]
+        count = len(self.n)
+        m = 1 << n
+        idx = torch.zeros((count, m), dtype=torch.int64, device=self.device)
+        idx[i] = torch.arange(m, dtype=torch.int64, device=self.device)
+        out = torch.empty(2 * count * m, dtype=torch.float64, device=self.device)
+        self.amplitudes_device(idx, m, out, stream)
+        torch.cuda.synchronize()
+        o = out.view(count, 2 * m)[i].cpu().numpy()
+        return o[0::2] + 1j * o[1::2]
 
     def close(self):
         if getattr(self, "h", None):

@@ -164,17 +164,34 @@ def layered_random_pairs(n: int, depth: int, rng: np.random.Generator) -> np.nda
     return concat(*out)
 
 
+def batch_shape(i: int, master_seed: int = 4, nmin: int = 12, nmax: int = 24,
+                dmin: int = 10, dmax: int = 40):
+    """(n, depth) of batch instance i (the first two draws of its seed)."""
+    rng = _rng(master_seed * (1 << 32) + i)
+    n = int(rng.integers(nmin, nmax + 1))
+    depth = int(rng.integers(dmin, dmax + 1))
+    return n, depth
+
+
+def batch_instance(i: int, master_seed: int = 4, nmin: int = 12, nmax: int = 24,
+                   dmin: int = 10, dmax: int = 40):
+    """Instance i of batch_instances: seed master*2^32 + i, n ~ U{nmin..nmax},
+    depth ~ U{dmin..dmax} (both inclusive), layered_random_pairs."""
+    rng = _rng(master_seed * (1 << 32) + i)
+    n = int(rng.integers(nmin, nmax + 1))
+    depth = int(rng.integers(dmin, dmax + 1))
+    return n, layered_random_pairs(n, depth, rng)
+
+
 def batch_instances(count: int, master_seed: int = 4, nmin: int = 12, nmax: int = 24,
                     dmin: int = 10, dmax: int = 40):
-    """Independent circuits; instance i draws from seed master*2^32 + i:
-    n ~ U{nmin..nmax}, depth ~ U{dmin..dmax} (both inclusive)."""
-    inst = []
-    for i in range(count):
-        rng = _rng(master_seed * (1 << 32) + i)
-        n = int(rng.integers(nmin, nmax + 1))
-        depth = int(rng.integers(dmin, dmax + 1))
-        inst.append((n, layered_random_pairs(n, depth, rng)))
-    return inst
+    """Independent circuits; instance i is batch_instance(i)."""
+    return [batch_instance(i, master_seed, nmin, nmax, dmin, dmax) for i in range(count)]
+
+
+def batch_bitstrings(i: int, n: int, count: int = 64) -> np.ndarray:
+    """The seeded bitstrings read out of batch instance i (seed 10000 + i)."""
+    return bitstrings(n, count, seed=10_000 + i)
 
 
 def grid_qubit(r: int, c: int, rows: int) -> int:
@@ -183,21 +200,49 @@ def grid_qubit(r: int, c: int, rows: int) -> int:
     return rows * c + r
 
 
+def _grid_pattern_edges(layer: int, rows: int, cols: int):
+    """CZ edges of layer ``layer``: pattern "ABCD"[layer mod 4] (A: horizontal
+    (r,c)-(r,c+1) with r+c even; B: horizontal, r+c odd; C: vertical
+    (r,c)-(r+1,c), r+c even; D: vertical, r+c odd), ordered by ascending
+    lower qubit."""
+    pat = "ABCD"[layer % 4]
+    edges = []
+    for r in range(rows):
+        for c in range(cols):
+            if pat in "AB" and c + 1 < cols and ((r + c) % 2 == (0 if pat == "A" else 1)):
+                edges.append((grid_qubit(r, c, rows), grid_qubit(r, c + 1, rows)))
+            if pat in "CD" and r + 1 < rows and ((r + c) % 2 == (0 if pat == "C" else 1)):
+                edges.append((grid_qubit(r, c, rows), grid_qubit(r + 1, c, rows)))
+    edges.sort(key=lambda e: (min(e), max(e)))
+    return edges
+
+
+def _grid_side(rows: int, cols: int) -> np.ndarray:
+    half = cols // 2
+    return np.array([0 if (q // rows) < half else 1 for q in range(rows * cols)], dtype=np.uint8)
+
+
+def _cz_records(edges) -> np.ndarray:
+    cz = empty_circuit(len(edges))
+    cz["op"] = OP_CZ
+    if edges:
+        cz["q0"] = [min(e) for e in edges]
+        cz["q1"] = [max(e) for e in edges]
+    return cz
+
+
 def grid_circuit(rows: int = 6, cols: int = 8, depth: int = 8, seed: int = 5,
                  max_cross: int | None = 10):
     """Grid circuit with Haar U(2) layers and CZ on four alternating edge
-    patterns.  A: horizontal (r,c)-(r,c+1) with r+c even; B: horizontal, r+c
-    odd; C: vertical (r,c)-(r+1,c), r+c even; D: vertical, r+c odd.  Layer l
-    applies Haar on all qubits then pattern "ABCD"[l mod 4]; CZs inside a
-    layer are ordered by ascending lower qubit.
+    patterns.  Layer l applies Haar on all qubits then the CZs of pattern
+    "ABCD"[l mod 4] (see _grid_pattern_edges).
 
     The cut separates columns [0, cols/2) from [cols/2, cols).  Only the first
     ``max_cross`` cut-crossing CZs (circuit order) are kept; later crossing
     CZs are dropped.  Returns (gates, side) with side[q] in {0, 1}."""
     rng = _rng(seed)
     n = rows * cols
-    half = cols // 2
-    side = np.array([0 if (q // rows) < half else 1 for q in range(n)], dtype=np.uint8)
+    side = _grid_side(rows, cols)
     out = []
     kept_cross = 0
     for layer in range(depth):
@@ -207,28 +252,43 @@ def grid_circuit(rows: int = 6, cols: int = 8, depth: int = 8, seed: int = 5,
         for q in range(n):
             g["u"][q] = _u_record(haar_u2(rng))
         out.append(g)
-        pat = "ABCD"[layer % 4]
-        edges = []
-        for r in range(rows):
-            for c in range(cols):
-                if pat in "AB" and c + 1 < cols and ((r + c) % 2 == (0 if pat == "A" else 1)):
-                    edges.append((grid_qubit(r, c, rows), grid_qubit(r, c + 1, rows)))
-                if pat in "CD" and r + 1 < rows and ((r + c) % 2 == (0 if pat == "C" else 1)):
-                    edges.append((grid_qubit(r, c, rows), grid_qubit(r + 1, c, rows)))
-        edges.sort(key=lambda e: (min(e), max(e)))
         keep = []
-        for a, b in edges:
+        for a, b in _grid_pattern_edges(layer, rows, cols):
             if side[a] != side[b]:
                 if max_cross is not None and kept_cross >= max_cross:
                     continue
                 kept_cross += 1
             keep.append((a, b))
-        cz = empty_circuit(len(keep))
-        cz["op"] = OP_CZ
-        if keep:
-            cz["q0"] = [min(e) for e in keep]
-            cz["q1"] = [max(e) for e in keep]
-        out.append(cz)
+        out.append(_cz_records(keep))
+    return concat(*out), side
+
+
+def grid_diag_circuit(rows: int = 6, cols: int = 8, depth: int = 8, seed: int = 5,
+                      max_cross: int | None = 10):
+    """The grid circuit's shape, cut and crossing rule with a closed form at
+    every bitstring: one Haar U(2) layer on all qubits, then per layer l a
+    T layer (l even) or S layer (l odd) on all qubits followed by the CZs of
+    pattern "ABCD"[l mod 4], keeping the first ``max_cross`` crossing CZs.
+    Everything after the Haar layer is diagonal, so
+    <z|C|0> = prod_q U_q[z_q, 0] * prod of the diagonal gates' phases at z.
+    Returns (gates, side)."""
+    n = rows * cols
+    side = _grid_side(rows, cols)
+    out = [haar_layer(n, seed)]
+    kept_cross = 0
+    for layer in range(depth):
+        ph = empty_circuit(n)
+        ph["op"] = OP_T if layer % 2 == 0 else OP_S
+        ph["q0"] = np.arange(n)
+        out.append(ph)
+        keep = []
+        for a, b in _grid_pattern_edges(layer, rows, cols):
+            if side[a] != side[b]:
+                if max_cross is not None and kept_cross >= max_cross:
+                    continue
+                kept_cross += 1
+            keep.append((a, b))
+        out.append(_cz_records(keep))
     return concat(*out), side
 
 

@@ -8,7 +8,13 @@ into a low and a high half, every CZ across the cut is split with Eq. (2),
 and <z|C|0> = 2^-S sum_s A_s(z_low) B_s(z_high) in FP64.  The decomposition
 is pinned against the full state vector in tests/test_oracle_pins.py.
 
-usage: python tests/golden/make_golden.py brick30 [brick28 brick34 brick36 grid48m2 grid42m3]
+The batch sample (batch4096s) takes a stratified sample of the 4096 batched
+circuits -- every qubit count 12..24, the shallowest circuit for n >= 21 and
+the first and the deepest for n <= 20 -- and stores 64 seeded amplitudes of
+each, from the oracle's full state vector.
+
+usage: python tests/golden/make_golden.py brick30 [brick28 brick34 brick36 grid48m2 grid42m3
+                                                   batch4096s]
 """
 import os
 import sys
@@ -37,6 +43,60 @@ SETS = {
 }
 
 
+BATCH_COUNT = 4096
+BATCH_AMPS = 64
+
+
+def batch_sample(count=BATCH_COUNT):
+    """Indices of the stored batch circuits: for every qubit count, the
+    shallowest instance when n >= 21 (the oracle's full state costs most
+    there), else the first and the deepest one."""
+    shapes = [W.batch_shape(i) for i in range(count)]
+    pick = []
+    for n in sorted({s[0] for s in shapes}):
+        idx = [i for i, s in enumerate(shapes) if s[0] == n]
+        deepest = max(idx, key=lambda i: (shapes[i][1], -i))
+        shallowest = min(idx, key=lambda i: (shapes[i][1], i))
+        pick += [shallowest] if n >= 21 else sorted({idx[0], deepest})
+    return sorted(pick)
+
+
+def make_batch(name):
+    from oracle import statevector as sv
+    sample = batch_sample()
+    t0 = time.time()
+    with open(path_for(name), "w") as f:
+        f.write(f"# {name}: batch_instance(i) of the {BATCH_COUNT}-circuit batch for a stratified "
+                f"sample of i; batch_bitstrings(i, n, {BATCH_AMPS})\n")
+        f.write("# amplitudes from the FP64 oracle's full state vector (statevector.run_circuit)\n")
+        f.write("# i z re im\n")
+        for i in sample:
+            n, circ = W.batch_instance(i)
+            z = W.batch_bitstrings(i, n, BATCH_AMPS)
+            t1 = time.time()
+            psi = sv.run_circuit(n, circ)
+            for zi in z:
+                a = psi[int(zi)]
+                f.write(f"{i} {int(zi)} {a.real:.17e} {a.imag:.17e}\n")
+            f.flush()
+            print(f"  circuit {i}: n={n} gates={len(circ)} {time.time() - t1:.1f}s", flush=True)
+    print(f"{name}: {len(sample)} circuits {time.time() - t0:.1f}s -> {path_for(name)}", flush=True)
+
+
+def load_batch(name="batch4096s"):
+    """{circuit index: (z uint64 array, complex128 amplitudes)}."""
+    out = {}
+    with open(path_for(name)) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            i, z, re, im = line.split()
+            zs, am = out.setdefault(int(i), ([], []))
+            zs.append(int(z))
+            am.append(float(re) + 1j * float(im))
+    return {i: (np.array(z, dtype=np.uint64), np.array(a)) for i, (z, a) in out.items()}
+
+
 def path_for(name):
     return os.path.join(HERE, f"{name}_amplitudes.txt")
 
@@ -62,6 +122,8 @@ def make_grid(name):
 
 
 def make(name):
+    if name == "batch4096s":
+        return make_batch(name)
     if name in GRID_SETS:
         return make_grid(name)
     n, layers, cseed, zseed, count = SETS[name]

@@ -63,9 +63,100 @@ def test_create_rejects_bad_buffers_before_any_device_call(J):
     assert lib.juqcs_state_create(ct.byref(h), 4, 0, 0, 16, 255, None, 0, None, 0, None) == J.ERR_SIZE
     # ENC2 without scales
     assert lib.juqcs_state_create(ct.byref(h), 8, 2, 0, 16, 512, None, 0, None, 0, None) == J.ERR_ARG
-    # workspace too small
-    assert lib.juqcs_state_create(ct.byref(h), 4, 0, 0, 16, 256, None, 0, 32, 16, None) == J.ERR_SIZE
+    # workspace: required (the library never allocates), 256-byte aligned, large enough
+    assert lib.juqcs_state_create(ct.byref(h), 4, 0, 0, 16, 256, None, 0, None, 0, None) == J.ERR_ARG
+    assert lib.juqcs_state_create(ct.byref(h), 4, 0, 0, 16, 256, None, 0, 32, 1 << 30, None) == J.ERR_ARG
+    assert lib.juqcs_state_create(ct.byref(h), 4, 0, 0, 16, 256, None, 0, 256, 16, None) == J.ERR_SIZE
     assert h.value is None
+
+
+def test_global_factor_rejects_bad_arguments(J):
+    lib = J._lib
+    g = (ct.c_double * 2)(1.0, 0.0)
+    assert lib.juqcs_set_global_factor(None, g) == J.ERR_ARG
+    assert lib.juqcs_mul_global_factor(None, g) == J.ERR_ARG
+    assert lib.juqcs_get_global_factor(None, g) == J.ERR_ARG
+    assert lib.juqcs_renormalize(None, None) == J.ERR_ARG
+
+
+def _batch_args(J, ns, soff):
+    import numpy as np
+    from paper_1912_03243_amd import workloads as W
+    circs = [W.layered_brick(n, 2, seed=n) for n in ns]
+    offs = np.zeros(len(ns) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(c) for c in circs])
+    g = np.ascontiguousarray(np.concatenate(circs))
+    nn = np.array(ns, dtype=np.int32)
+    so = np.array(soff, dtype=np.uint64)
+    keep = (g, nn, offs, so)
+    return keep, (len(ns), nn.ctypes.data_as(ct.POINTER(ct.c_int)), g.ctypes.data,
+                  offs.ctypes.data_as(ct.POINTER(ct.c_int64)))
+
+
+def test_batch_create_checks_the_state_buffer_on_the_host(J):
+    # states past the end of the buffer, overlapping regions and misaligned
+    # buffers are rejected before any device work (the pointer is never used)
+    lib = J._lib
+    h = ct.c_void_p()
+    keep, a = _batch_args(J, [4, 5], [0, 256])
+    so = keep[3].ctypes.data_as(ct.POINTER(ct.c_uint64))
+    need = 256 + (8 << 5)
+    assert lib.juqcs_batch_create(ct.byref(h), *a, 256, need - 1, so, None) == J.ERR_SIZE
+    assert lib.juqcs_batch_create(ct.byref(h), *a, 8, need, so, None) == J.ERR_ARG
+    keep2, a2 = _batch_args(J, [4, 5], [0, 64])      # 8 * 2^4 = 128 bytes: overlaps
+    so2 = keep2[3].ctypes.data_as(ct.POINTER(ct.c_uint64))
+    assert lib.juqcs_batch_create(ct.byref(h), *a2, 256, 1 << 20, so2, None) == J.ERR_ARG
+    assert h.value is None
+
+
+def test_batch_workspace_is_sized_and_required(J):
+    lib = J._lib
+    h = ct.c_void_p()
+    keep, a = _batch_args(J, [4, 5], [0, 256])
+    so = keep[3].ctypes.data_as(ct.POINTER(ct.c_uint64))
+    assert lib.juqcs_batch_create(ct.byref(h), *a, 256, 1 << 20, so, None) == J.OK
+    try:
+        b = ct.c_size_t()
+        assert lib.juqcs_batch_bytes(h, ct.byref(b)) == J.OK
+        assert b.value >= 4 << 20
+        # no workspace bound yet: nothing runs or reads
+        assert lib.juqcs_batch_run(h, None) == J.ERR_ARG
+        assert lib.juqcs_batch_norms(h, (ct.c_double * 2)(), None) == J.ERR_ARG
+        assert lib.juqcs_batch_autotune(h, None) == J.ERR_ARG
+        # too small, misaligned, null
+        assert lib.juqcs_batch_bind(h, 256, b.value - 1, None) == J.ERR_SIZE
+        assert lib.juqcs_batch_bind(h, 16, b.value, None) == J.ERR_ARG
+        assert lib.juqcs_batch_bind(h, None, b.value, None) == J.ERR_ARG
+    finally:
+        assert lib.juqcs_batch_destroy(h) == J.OK
+
+
+def test_branch_workspace_is_sized_and_required(J):
+    import numpy as np
+    from paper_1912_03243_amd import workloads as W
+    lib = J._lib
+    circ, side = W.grid_circuit(2, 4, 4, 3, max_cross=None)
+    n = 8
+    z = np.arange(16, dtype=np.uint64)
+    mn, full = J.juqcs_branch_bytes(n, circ, side, 1, z.size, 0, True)
+    assert 0 < mn <= full
+    mn1, g1 = J.juqcs_branch_bytes(n, circ, side, 1, z.size, 1, True)
+    assert mn1 == mn and g1 == mn
+    dmn, _ = J.juqcs_branch_bytes(n, circ, side, 1, z.size, 1, False)
+    assert dmn < mn                       # no staged bitstrings or result
+    out = np.zeros(2 * z.size)
+    sp = side.ctypes.data_as(ct.POINTER(ct.c_uint8))
+    zp = z.ctypes.data_as(ct.POINTER(ct.c_uint64))
+    args = (n, circ.ctypes.data, circ.size, sp, zp, z.size)
+    dp = out.ctypes.data_as(ct.POINTER(ct.c_double))
+    # null, misaligned, or too small for one branch / for the group size
+    assert lib.juqcs_branch_amplitudes(*args, 0, dp, None, 1 << 30, None) == J.ERR_ARG
+    assert lib.juqcs_branch_amplitudes(*args, 0, dp, 16, 1 << 30, None) == J.ERR_ARG
+    assert lib.juqcs_branch_amplitudes(*args, 0, dp, 256, mn - 1, None) == J.ERR_SIZE
+    assert lib.juqcs_branch_amplitudes(*args, 1 << 20, dp, 256, mn, None) == J.ERR_SIZE
+    # no bitstrings: nothing to do, no workspace needed
+    assert lib.juqcs_branch_amplitudes(n, circ.ctypes.data, circ.size, sp, zp, 0, 0, dp, None, 0,
+                                       None) == J.OK
 
 
 def test_null_handle_and_codec_errors(J):

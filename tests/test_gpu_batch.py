@@ -256,16 +256,19 @@ def test_branch_ghz48_closed_form(J, golden):
 
 
 @pytest.mark.parametrize("name", ["grid48m2", "grid42m3"])
-def test_branch_grid_against_stored_oracle_values(J, name):
-    # full-size halves (24 and 21 qubits) against the oracle's own branch sum
+@pytest.mark.parametrize("group", [0, 1, 2])
+def test_branch_grid_against_stored_oracle_values(J, name, group):
+    # full-size halves (24 and 21 qubits) against the oracle's own branch
+    # sum, with every branch in one group and in groups of one and two
     if not os.path.exists(path_for(name)):
         pytest.skip("stored amplitudes not generated")
     rows, cols, depth, seed, mcross, _, _ = GRID_SETS[name]
     z, want = load(name)
     circ, side = W.grid_circuit(rows, cols, depth, seed, max_cross=mcross)
-    announce(name)
-    got = J.juqcs_branch_amplitudes(rows * cols, circ, side, z)
+    announce(name, group)
+    got = J.juqcs_branch_amplitudes(rows * cols, circ, side, z, group_size=group)
     assert rel_l2(got, want) < 1e-5
+    assert np.max(np.abs(got - want)) / np.abs(want).max() < 1e-5
 
 
 def test_branch_rejects_other_crossings(J):

@@ -371,6 +371,56 @@ def test_permute_and_canonicalize(J, dtype):
         assert_dtype(dtype, amps, phi[z.astype(np.int64)])
 
 
+# ---- global factor -------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c128", "c64", "enc2"])
+def test_global_factor(J, dtype):
+    # an FP64 complex factor of the whole state: set by one call, carried by
+    # diagonal gates' first entries, applied by every read-out, used to
+    # renormalise; the stored amplitudes are never touched for it
+    n = 13
+    announce("global-factor", dtype)
+    circ = W.random_mixed(n, 90, seed=17)
+    g = 0.3 - 0.7j
+    rz = np.diag([np.exp(-0.45j), np.exp(0.45j)])      # diag(a, b): a goes into the factor
+    phi = g * sv.run_circuit(n, circ)
+    sv.apply_1q(phi, n, 4, rz)
+    sv.apply_1q(phi, n, 0, 1.5 * np.eye(2))              # a scalar: no pass at all
+    z = np.arange(0, 1 << n, 37, dtype=np.uint64)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        s.set_global_factor(g)
+        s.run(circ, mode="tile")
+        s.apply_1q(4, rz)
+        s.apply_1q(0, 1.5 * np.eye(2))
+        gf = s.global_factor()
+        amps = s.amplitudes(z)
+        full = s.state_vector()
+        nrm = s.norm()
+        ex = s.expectations()
+        before = s.renormalize()
+        nrm1 = s.norm()
+        amps1 = s.amplitudes(z)
+        s.init(0)
+        assert s.global_factor() == 1.0
+    assert abs(gf - g * np.exp(-0.45j) * 1.5) < 1e-15
+    want_n = sv.norm(phi)
+    want_q = observables.q_expectations(phi, n)
+    if dtype == "enc2":
+        tol = 0.05
+        assert rel_l2(full, phi) < tol and rel_l2(amps, phi[z.astype(np.int64)]) < tol
+        assert abs(nrm / want_n - 1) < tol and abs(before - nrm) < 1e-15 * nrm
+        assert abs(nrm1 - 1) < 1e-12
+        assert np.max(np.abs(ex - want_q)) < tol
+        return
+    assert_dtype(dtype, full, phi)
+    assert_dtype(dtype, amps, phi[z.astype(np.int64)])
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert abs(nrm - want_n) < tol * want_n and before == nrm
+    assert abs(nrm1 - 1.0) < tol
+    assert_dtype(dtype, amps1, phi[z.astype(np.int64)] / math.sqrt(want_n))
+    assert np.max(np.abs(ex - want_q)) < tol
+
+
 # ---- read-out ----------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_norm_expectations_scale(J, dtype):
