@@ -260,7 +260,9 @@ juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, 
   if (L > b) return fail(JUQCS_ERR_ARG, "low_bits > tile_bits");
   if (b - L > kMaxGather) return fail(JUQCS_ERR_ARG, "too many gathered tile bits");
   if (st->dt == JUQCS_ENC2 && L < st->B) L = st->B;
-  if (st->dt == JUQCS_ENC2 && b < L) b = L;
+  if (st->dt == JUQCS_ENC2 && b < L + 2) b = std::min(maxb, L + 2);  // room for two gathered qubits
+  if (st->n > b && b - L < 2)
+    return fail(JUQCS_ERR_ARG, "a tile needs at least two gathered bits (tile_bits >= low_bits + 2)");
   if (kin <= 0) kin = 3;
   if (kin > 4) return fail(JUQCS_ERR_ARG, "in-pass fusion width must be 1..4");
   if (pass_gates < -1) return fail(JUQCS_ERR_ARG, "pass_gates must be >= -1");
@@ -288,6 +290,8 @@ juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, 
       }
     }
   }
+  if (plan.gates != (int64_t)gates.size())
+    return fail(JUQCS_ERR_UNSUPPORTED, "a gate does not fit any tile of this geometry");
   if (passes) *passes = (int64_t)plan.passes.size();
   if (juqcs_status rc = run_tile_plan(st, plan)) return rc;
   if (rl)

@@ -84,6 +84,137 @@ __global__ __launch_bounds__(kThreads) void k_1q(cplx<T>* __restrict__ psi, uint
   }
 }
 
+// ---------------------------------------------------------------- runs ----
+// Per-gate passes in runs.  A run is 64 consecutive 16-byte words (one per
+// lane of a wave): 64 C128 or 128 C64 amplitudes, so every load and store a
+// wave issues covers 1 KiB of contiguous memory whatever the gate's qubits
+// (Eq. (1) pairs indices that differ in the target bit only; when that bit
+// is below the run width the partner sits in another lane of the same
+// wave).  Bits below the run width RB (6 for C128, 7 for C64) are "low",
+// the others "high":
+//   * low target   (RUN_LOW): the partner amplitude comes from lane l ^ 2^t
+//     (C64: l ^ 2^(t-1); t = 0 pairs the two amplitudes of one lane);
+//   * high target  (RUN_HIGH): run r is paired with run r + 2^(t - RB);
+//   * a high control or diagonal bit is set to 1 in the run index, so only
+//     the runs it selects are read; a low one is a per-amplitude predicate
+//     (amplitudes that fail it are written back unchanged).
+enum RunMode { RUN_LOW = 0, RUN_HIGH = 1, RUN_DIAG = 2 };
+
+template <typename T>
+struct RunT;
+template <>
+struct RunT<double> {
+  static constexpr int RB = 6;  // amplitudes per run: 64
+  typedef double W __attribute__((ext_vector_type(2)));
+};
+template <>
+struct RunT<float> {
+  static constexpr int RB = 7;  // amplitudes per run: 128
+  typedef float W __attribute__((ext_vector_type(4)));
+};
+
+struct RunArgs {
+  uint64_t nruns;   // runs (RUN_HIGH: run pairs) to process
+  int nins;         // run-index bits inserted (ascending positions ins[])
+  int ins[3];
+  uint64_t ones;    // inserted bits that are 1 (high controls and diagonal bits)
+  uint64_t tstride; // RUN_HIGH: run-index distance of the partner run
+  int t;            // RUN_LOW: the target bit
+  uint32_t lmask;   // low control / diagonal bits that must all be 1
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mat_row(cplx<T> m0, cplx<T> x, cplx<T> m1, cplx<T> y) {
+  return cmad(m1, y, cmul(m0, x));
+}
+
+template <typename T, int MODE, int U>
+__global__ __launch_bounds__(kThreads) void k_runs(cplx<T>* __restrict__ psi, RunArgs ra, Mat2<T> u,
+                                                   cplx<T> ph) {
+  using W = typename RunT<T>::W;
+  constexpr int RB = RunT<T>::RB;
+  constexpr int APL = sizeof(W) / sizeof(cplx<T>);  // amplitudes per lane: 1 or 2
+  W* g = reinterpret_cast<W*>(psi);
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  constexpr int NL = MODE == RUN_HIGH ? 2 * U : U;  // 16-byte words per lane
+  W v[NL];
+  uint64_t at[NL];
+  bool ok[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const uint64_t ri = wave * U + k;
+    ok[k] = ri < ra.nruns;
+    uint64_t r = ok[k] ? ri : 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j < ra.nins) r = insert_zero(r, ra.ins[j]);
+    r |= ra.ones;
+    at[k] = (r << (RB - (APL == 2 ? 1 : 0))) + lane;  // word index of this lane
+    if (MODE == RUN_HIGH) at[U + k] = at[k] + (ra.tstride << (RB - (APL == 2 ? 1 : 0)));
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k)
+    if (ok[k % U]) v[k] = ld_stream(&g[at[k]]);
+  // amplitude index bits of this lane's amplitudes within their run
+  const int a0 = APL == 2 ? 2 * lane : lane;
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    if (MODE == RUN_LOW) {
+      // partner values from the lane across the target bit
+      const int xl = APL == 2 ? (ra.t > 0 ? 1 << (ra.t - 1) : 0) : 1 << ra.t;
+      W w = v[k];
+#pragma unroll
+      for (int c = 0; c < (int)(sizeof(W) / sizeof(T)); ++c) w[c] = xl ? __shfl_xor(v[k][c], xl, 64) : v[k][c];
+#pragma unroll
+      for (int j = 0; j < APL; ++j) {
+        const int a = a0 + j;
+        const cplx<T> self = {v[k][2 * j], v[k][2 * j + 1]};
+        // C64 t = 0: the partner is the other amplitude of this lane
+        const int pj = (APL == 2 && ra.t == 0) ? 1 - j : j;
+        const cplx<T> other = (APL == 2 && ra.t == 0) ? cplx<T>{v[k][2 * pj], v[k][2 * pj + 1]}
+                                                       : cplx<T>{w[2 * j], w[2 * j + 1]};
+        const bool hi = (a >> ra.t) & 1;
+        cplx<T> r = hi ? mat_row(u.m[2], other, u.m[3], self) : mat_row(u.m[0], self, u.m[1], other);
+        if (((uint32_t)a & ra.lmask) != ra.lmask) r = self;
+        w[2 * j] = r.re;
+        w[2 * j + 1] = r.im;
+      }
+      if (ok[k]) st_stream(&g[at[k]], w);
+    } else if (MODE == RUN_HIGH) {
+      W wa = v[k], wb = v[U + k];
+#pragma unroll
+      for (int j = 0; j < APL; ++j) {
+        const int a = a0 + j;
+        const cplx<T> x = {v[k][2 * j], v[k][2 * j + 1]}, y = {v[U + k][2 * j], v[U + k][2 * j + 1]};
+        if (((uint32_t)a & ra.lmask) == ra.lmask) {
+          const cplx<T> r0 = mat_row(u.m[0], x, u.m[1], y), r1 = mat_row(u.m[2], x, u.m[3], y);
+          wa[2 * j] = r0.re;
+          wa[2 * j + 1] = r0.im;
+          wb[2 * j] = r1.re;
+          wb[2 * j + 1] = r1.im;
+        }
+      }
+      if (ok[k]) {
+        st_stream(&g[at[k]], wa);
+        st_stream(&g[at[U + k]], wb);
+      }
+    } else {
+      W w = v[k];
+#pragma unroll
+      for (int j = 0; j < APL; ++j) {
+        const int a = a0 + j;
+        if (((uint32_t)a & ra.lmask) == ra.lmask) {
+          const cplx<T> r = cmul(ph, cplx<T>{v[k][2 * j], v[k][2 * j + 1]});
+          w[2 * j] = r.re;
+          w[2 * j + 1] = r.im;
+        }
+      }
+      if (ok[k]) st_stream(&g[at[k]], w);
+    }
+  }
+}
+
 // --------------------------------------------------------------- diag ----
 // Multiplies the amplitudes whose bits in mask are all 1 by phase (the
 // nontrivial part of Z, S, T, CZ and controlled-phase); other amplitudes are
@@ -314,8 +445,60 @@ Mat4<T> to_mat4(const cplx<double> u[16]) {
   return m;
 }
 
+// Run geometry of a gate: high bits (>= RB) are inserted into the run index
+// (ones: set to 1), low ones go to the lane predicate.  Returns false when
+// the state is too small for runs.
+template <typename T>
+bool run_args(int n, int t_high, uint64_t set_mask, RunArgs* ra) {
+  constexpr int RB = RunT<T>::RB;
+  int hb[3], nh = 0;
+  ra->lmask = 0;
+  ra->ones = 0;
+  for (int q = 0; q < 64; ++q) {
+    if (!((set_mask >> q) & 1)) continue;
+    if (q < RB) {
+      ra->lmask |= 1u << q;
+    } else {
+      hb[nh++] = q - RB;
+      ra->ones |= uint64_t(1) << (q - RB);
+    }
+  }
+  if (t_high >= 0) hb[nh++] = t_high - RB;
+  if (n < RB + nh + 1) return false;
+  // ascending insertion positions
+  for (int i = 0; i < nh; ++i)
+    for (int j = i + 1; j < nh; ++j)
+      if (hb[j] < hb[i]) {
+        const int x = hb[i];
+        hb[i] = hb[j];
+        hb[j] = x;
+      }
+  ra->nins = nh;
+  for (int i = 0; i < 3; ++i) ra->ins[i] = i < nh ? hb[i] : 0;
+  ra->nruns = uint64_t(1) << (n - RB - nh);
+  ra->tstride = t_high >= 0 ? uint64_t(1) << (t_high - RB) : 0;
+  ra->t = 0;
+  return true;
+}
+
+template <typename T, int MODE, int U>
+hipError_t launch_runs(void* amps, const RunArgs& ra, const Mat2<T>& u, cplx<T> ph, hipStream_t s) {
+  const uint64_t waves = (ra.nruns + U - 1) / U;
+  hipLaunchKernelGGL((k_runs<T, MODE, U>), dim3(grid_for(waves, kThreads / 64)), dim3(kThreads), 0, s,
+                     (cplx<T>*)amps, ra, u, ph);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t do_1q(void* amps, int n, int t, int c, const cplx<double> u[4], hipStream_t s) {
+  constexpr int RB = RunT<T>::RB;
+  const uint64_t cm = c >= 0 ? uint64_t(1) << c : 0;
+  RunArgs ra;
+  if (run_args<T>(n, t >= RB ? t : -1, cm, &ra)) {
+    if (t >= RB) return launch_runs<T, RUN_HIGH, 2>(amps, ra, to_mat2<T>(u), cplx<T>{}, s);
+    ra.t = t;
+    return launch_runs<T, RUN_LOW, 4>(amps, ra, to_mat2<T>(u), cplx<T>{}, s);
+  }
   constexpr int U = 4;
   const uint64_t npairs = uint64_t(1) << (n - 1 - (c >= 0 ? 1 : 0));
   int z0 = t, z1 = -1;
@@ -332,6 +515,9 @@ hipError_t do_1q(void* amps, int n, int t, int c, const cplx<double> u[4], hipSt
 
 template <typename T>
 hipError_t do_diag(void* amps, int n, uint64_t mask, cplx<double> ph, hipStream_t s) {
+  RunArgs ra;
+  if (run_args<T>(n, -1, mask, &ra))
+    return launch_runs<T, RUN_DIAG, 4>(amps, ra, Mat2<T>{}, cplx<T>{(T)ph.re, (T)ph.im}, s);
   constexpr int U = 4;
   int z[2] = {-1, -1}, nb = 0;
   for (int q = 0; q < 64 && nb < 2; ++q)

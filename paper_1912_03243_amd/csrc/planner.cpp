@@ -378,6 +378,10 @@ void select_tiles(int n, int L, int b, int block_bits, const std::vector<Gate>& 
         for (int j = 0; j < g.nq; ++j) blocked[g.q[j]] = 1;
       }
     }
+    if (taken.empty()) {  // the front gate cannot fit any tile: give up
+      sched->gates -= (int64_t)rem.size();
+      return;
+    }
     TilePass pass{};
     pass.g.n = n;
     pass.g.L = L;
@@ -518,6 +522,10 @@ void select_tiles_relabel(int n, int L, int b, int block_bits, const std::vector
         keep.push_back(gi);
         for (int j = 0; j < g.nq; ++j) blocked[g.q[j]] = 1;
       }
+    }
+    if (taken.empty()) {  // the front gate cannot fit any tile: give up
+      sched->gates -= (int64_t)rem.size();
+      break;
     }
     TilePass pass{};
     pass.g.n = n;

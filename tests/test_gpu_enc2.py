@@ -3,7 +3,8 @@
 * A pass whose gates are exact in FP32 (X, Y, Z, S, CNOT, CZ: entries 0,
   +-1, +-i) only permutes and re-signs the decoded amplitudes, so the codes
   and scales it writes must equal the reference codec's encoding of those
-  values bit for bit.
+  values bit for bit (every pass re-encodes, so the reference re-encodes
+  after every pass too).
 * After passes with arbitrary gates every block must be a valid code: a zero
   block has scale 0 and zero codes; otherwise some component codes to +-127,
   and re-encoding the decoded block gives the same codes (and the decoded
@@ -51,23 +52,49 @@ def exact_circuit(n, count, seed):
     return W.concat(*recs)
 
 
-@pytest.mark.parametrize("n, B", [(14, 8), (16, 8), (15, 10)])
-def test_pass_reencode_is_the_reference_codec(J, n, B):
-    announce("enc2-exact-pass", n, B)
+def noisy_state(J, s, n):
+    """Fills the two-byte state s with spread amplitudes (a few brick layers)
+    and returns its decoded values as complex128 (exact)."""
+    s.init(0)
+    s.run(W.layered_brick(n, 3, seed=80 + n), mode="tile", relabel=-1)
+    codes, scales = s.raw_codes()
+    return oenc2.decode(codes, scales, s.block_bits).astype(np.complex128)
+
+
+@pytest.mark.parametrize("n, B", [(13, 8), (12, 5)])
+def test_one_pass_reencode_is_the_reference_codec(J, n, B):
+    # the whole state is one tile: all 40 exact gates in one pass, one re-encode
+    announce("enc2-exact-one-pass", n, B)
+    circ = exact_circuit(n, 40, seed=81 + n)
     with J.State(n, "enc2", block_bits=B) as s:
-        s.init(0)
-        s.run(W.layered_brick(n, 3, seed=80 + n), mode="tile", relabel=-1)
-        codes0, scales0 = s.raw_codes()
-        circ = exact_circuit(n, 60, seed=81 + n)
-        o = s.run(circ, mode="tile", relabel=-1)
+        x0 = noisy_state(J, s, n)
+        o = s.run(circ, mode="tile", relabel=-1, pass_gates=-1)
         codes1, scales1 = s.raw_codes()
-    assert o.passes >= 1
-    x0 = oenc2.decode(codes0, scales0, B).astype(np.complex128)
-    # exact in FP64, and representable in FP32: the values the pass encodes
+    assert o.passes == 1
+    # exact in FP64 and representable in FP32: the values the pass encodes
     phi = sv.run_circuit(n, circ, psi=x0).astype(np.complex64)
     want_codes, want_scales = oenc2.encode(phi, B)
     assert np.array_equal(scales1, want_scales)
     assert np.array_equal(codes1, want_codes)
+
+
+@pytest.mark.parametrize("n, B", [(16, 8), (15, 10)])
+def test_every_pass_reencode_is_the_reference_codec(J, n, B):
+    # one gate per run, so one pass (one decode, exact gate, re-encode) per
+    # gate; the reference re-encodes after every gate the same way
+    announce("enc2-exact-per-pass", n, B)
+    circ = exact_circuit(n, 30, seed=82 + n)
+    with J.State(n, "enc2", block_bits=B) as s:
+        x = noisy_state(J, s, n)
+        for k in range(len(circ)):
+            o = s.run(circ[k:k + 1], mode="tile", relabel=-1)
+            assert o.passes == 1
+            x = sv.run_circuit(n, circ[k:k + 1], psi=x)
+            codes, scales = oenc2.encode(x.astype(np.complex64), B)
+            x = oenc2.decode(codes, scales, B).astype(np.complex128)
+        codes1, scales1 = s.raw_codes()
+    assert np.array_equal(scales1, scales)
+    assert np.array_equal(codes1, codes)
 
 
 @pytest.mark.parametrize("n, B, relabel", [(16, 8, 0), (18, 6, 0), (17, 12, -1)])
