@@ -441,6 +441,26 @@ juqcs_status juqcs_branch_amplitudes_device(int n, const juqcs_gate* gates,
                                             void* d_work, size_t work_bytes,
                                             void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under graph capture
+ * set-up, tight serving loops, harnesses that forbid allocation): the same
+ * as juqcs_branch_amplitudes_device with no workspace argument.  The
+ * workspace is a static array of JUQCS_NOALLOC_SCRATCH_BYTES in the
+ * library's device code, one per GPU, held until the process ends; calls
+ * are serialised inside the process (they share the array, which keeps the
+ * last call's contents; everything a call needs zeroed it clears itself),
+ * and calls that overlapped on one GPU would race.  group_size 0 takes the
+ * largest group that fits the array.  Decompositions whose workspace for
+ * group_size (for groups of one branch when group_size is 0) exceeds it
+ * are rejected with JUQCS_ERR_SIZE before any device work.  Synchronises
+ * hip_stream.  Other arguments, results and errors as for
+ * juqcs_branch_amplitudes_device. */
+#define JUQCS_NOALLOC_SCRATCH_BYTES (32u << 20)
+juqcs_status juqcs_branch_amplitudes_noalloc(int n, const juqcs_gate* gates,
+                                             size_t gate_count, const uint8_t* side,
+                                             const uint64_t* d_z, int words, size_t count,
+                                             int group_size, double* d_out,
+                                             void* hip_stream);
+
 /* Device workspace of the decomposition calls above for these arguments:
  * *min_bytes for groups of one branch (the least any run needs), *bytes for
  * group_size (0: every branch in one group).  host_io = 1 for

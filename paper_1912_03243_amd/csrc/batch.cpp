@@ -1020,10 +1020,10 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   if (e == hipSuccess)
     e = hipMemcpyAsync(dsum, lds ? (const void*)t8.data() : (const void*)t32.data(), tbytes,
                        hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(dbad, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_zero(dbad, sizeof(int), s);
   if (e == hipSuccess)
     e = launch_branch_split(dev ? z : dz, words, (long long)count, P, n, dtab, zp, dbad, s);
-  if (e == hipSuccess) e = hipMemsetAsync(acc, 0, count * 2 * sizeof(double), s);
+  if (e == hipSuccess) e = launch_zero(acc, count * 2 * sizeof(double), s);
   int bad = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1111,6 +1111,65 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// The decomposition without a caller workspace: everything beyond the
+// caller's bitstrings and result lives in one file-scope device array of
+// JUQCS_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.  Host
+// code never passes the array's name to a kernel or a copy: it takes the
+// array's device address on each device from hipGetSymbolAddress (once per
+// device, with that device current) and passes that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[JUQCS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;           // one call at a time per process: calls share the array
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the scratch array on the current device.
+juqcs_status scratch_on_current_device(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices) return fail(JUQCS_ERR_UNSUPPORTED, "device index above 63");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return JUQCS_OK;
+}
+
+}  // namespace
+
+extern "C" juqcs_status juqcs_branch_amplitudes_noalloc(int n, const juqcs_gate* gates,
+                                                        size_t gate_count, const uint8_t* side,
+                                                        const uint64_t* d_z, int words, size_t count,
+                                                        int group_size, double* d_out,
+                                                        void* hip_stream) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  size_t need = 0;
+  if (count > 0) {
+    auto J = std::make_unique<BranchJob>();
+    if (juqcs_status rc = branch_prepare(n, gates, gate_count, side, words, count, false, J.get()))
+      return rc;
+    need = branch_layout(*J, group_size > 0 ? group_bits(J->m, group_size) : J->m).total;
+    if (need > (size_t)JUQCS_NOALLOC_SCRATCH_BYTES)
+      return fail(JUQCS_ERR_SIZE, "the decomposition needs " + std::to_string(need) +
+                                      " bytes of workspace; the static scratch holds " +
+                                      std::to_string((size_t)JUQCS_NOALLOC_SCRATCH_BYTES));
+  }
+  void* ws = nullptr;
+  if (count > 0)
+    if (juqcs_status rc = scratch_on_current_device(&ws)) return rc;
+  return branch_amplitudes(n, gates, gate_count, side, d_z, words, count, group_size, d_out, ws,
+                           count > 0 ? (size_t)JUQCS_NOALLOC_SCRATCH_BYTES : 0, (hipStream_t)hip_stream,
+                           true);
+}
 
 extern "C" juqcs_status juqcs_branch_bytes(int n, const juqcs_gate* gates, size_t gate_count,
                                            const uint8_t* side, int words, size_t count,

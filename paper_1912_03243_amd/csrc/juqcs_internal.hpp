@@ -165,6 +165,8 @@ hipError_t launch_gather(juqcs_dtype dt, const void* amps, const void* scales,
 hipError_t launch_scale(juqcs_dtype dt, void* amps, void* scales, int n,
                         int block_bits, double f, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Zeroes bytes (a multiple of 4, 4-byte aligned) with a kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 hipError_t launch_tile(juqcs_dtype dt, void* amps, void* scales,
                        const TileGeom& g, const TileOp* d_ops, int nops,

@@ -402,6 +402,14 @@ __global__ __launch_bounds__(kThreads) void k_scale_f32(float* __restrict__ x, u
     x[i] *= f;
 }
 
+// ---------------------------------------------------------------- fill ----
+// Zeroes count 32-bit words (used instead of a memset node where a caller
+// may capture the work into a graph).
+__global__ __launch_bounds__(kThreads) void k_zero(uint32_t* __restrict__ p, uint64_t count) {
+  const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < count; i += stride) p[i] = 0u;
+}
+
 // ---------------------------------------------------------------- copy ----
 // Reference streaming copy: each thread moves 4 x 16 bytes per iteration,
 // with the same non-temporal accesses as the state passes.
@@ -638,6 +646,13 @@ hipError_t launch_scale(juqcs_dtype dt, void* amps, void* scales, int n, int blo
     hipLaunchKernelGGL(k_scale_f32, dim3(stride_grid(nb)), dim3(kThreads), 0, s, (float*)scales,
                        nb, (float)f);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const uint64_t count = bytes / 4;
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(stride_grid(count)), dim3(kThreads), 0, s, (uint32_t*)p, count);
   return hipGetLastError();
 }
 

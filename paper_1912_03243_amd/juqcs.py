@@ -106,6 +106,7 @@ _SIGS = {
                                      _I, _DP, _P, _S, _P],
     "juqcs_branch_amplitudes_device": [_I, _P, _S, ct.POINTER(ct.c_uint8), _P, _I, _S, _I, _P,
                                        _P, _S, _P],
+    "juqcs_branch_amplitudes_noalloc": [_I, _P, _S, ct.POINTER(ct.c_uint8), _P, _I, _S, _I, _P, _P],
     "juqcs_branch_bytes": [_I, _P, _S, ct.POINTER(ct.c_uint8), _I, _S, _I, _I, ct.POINTER(_S),
                            ct.POINTER(_S)],
     "juqcs_copy": [_P, _P, _S, _P],
@@ -268,6 +269,28 @@ def juqcs_branch_amplitudes_device(n: int, gates, side, z, out, group_size: int 
                                                work.numel() if work is not None else 0,
                                                _stream_handle(stream)),
            "juqcs_branch_amplitudes_device")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # JUQCS_NOALLOC_SCRATCH_BYTES
+
+
+def juqcs_branch_amplitudes_noalloc(n: int, gates, side, z, out, group_size: int = 0, stream=None):
+    """juqcs_branch_amplitudes_device with the library's static scratch as
+    the workspace (no device allocation by anyone during the call): z an
+    int64 (count, words) device tensor, out a float64 device tensor of
+    2*count elements."""
+    g = _gates(gates)
+    side = np.ascontiguousarray(side, dtype=np.uint8)
+    if z.dim() != 2 or not z.is_contiguous() or z.dtype.itemsize != 8:
+        raise ValueError("z: contiguous (count, words) tensor of 64-bit words")
+    if out.numel() != 2 * z.shape[0] or not out.is_contiguous() or out.element_size() != 8:
+        raise ValueError("out: contiguous float64 tensor of 2*count elements")
+    _check(_lib.juqcs_branch_amplitudes_noalloc(n, g.ctypes.data, g.size,
+                                                side.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                                                z.data_ptr(), z.shape[1], z.shape[0], group_size,
+                                                out.data_ptr(), _stream_handle(stream)),
+           "juqcs_branch_amplitudes_noalloc")
     return out
 
 
