@@ -201,7 +201,13 @@ typedef struct {
   double kernel_ms;    /* profile: summed device durations of the passes  */
   double bytes;        /* algorithmic HBM bytes of the passes: read + write
                           of every amplitude (and ENC2 scale) a pass must
-                          touch                                            */
+                          touch (a 16-byte word counts whole)              */
+  double flops;        /* algorithmic flops of the gates consumed, per
+                          gate and state amplitude: dense 2x2 14, diagonal
+                          3 (first entry 1) or 6, controlled 7, controlled
+                          diagonal 1.5 (sign flip 0.5), CNOT 0, dense 4x4 30 */
+  double mma_flops;    /* FUSED: flops of the dense blocks launched,
+                          8 * 2^k per block and state amplitude            */
 } juqcs_plan_opts;
 
 /* Applies count gate records in order (gates commuting on disjoint qubits
@@ -461,6 +467,26 @@ juqcs_status juqcs_branch_amplitudes_noalloc(int n, const juqcs_gate* gates,
                                              int group_size, double* d_out,
                                              void* hip_stream);
 
+/* What the calling thread's last completed decomposition call did (zeros
+ * before any): the branch groups and the part-state trees it simulated,
+ * with the algorithmic flops and HBM bytes of their tile passes (gate
+ * flops as juqcs_plan_opts.flops counts them; C64 read + write of every
+ * part state per pass), and the FP64 flops of the Eq. (3) sums,
+ * 2^m (6 (P - 1) + 2) per coefficient. */
+typedef struct {
+  int32_t crossings;    /* m                                               */
+  int32_t group_bits;   /* L: 2^L groups of 2^(m - L) branches             */
+  int64_t groups;
+  int64_t tree_states;  /* part-state tree nodes simulated, all groups     */
+  int64_t tile_passes;  /* tile passes over them                           */
+  double pass_bytes;
+  double gate_flops;
+  double sum_flops;
+  int32_t lds_sum;      /* 1: the sums ran from LDS                        */
+  int32_t pad;
+} juqcs_branch_stats;
+juqcs_status juqcs_branch_last_stats(juqcs_branch_stats* out);
+
 /* Device workspace of the decomposition calls above for these arguments:
  * *min_bytes for groups of one branch (the least any run needs), *bytes for
  * group_size (0: every branch in one group).  host_io = 1 for
@@ -477,8 +503,11 @@ juqcs_status juqcs_branch_bytes(int n, const juqcs_gate* gates, size_t gate_coun
  * ---------------------------------------------------------------------- */
 
 /* Device-to-device streaming copy of bytes (multiple of 16, 16-byte aligned
- * pointers) with the library's own copy kernel: the practical HBM ceiling
- * that gate passes are compared with.  Asynchronous. */
+ * pointers) with the library's own copy kernel.  With d_dst == d_src it is
+ * an in-place stream (every word read and written back, in the access
+ * pattern of the per-gate passes): the practical HBM ceiling of an in-place
+ * pass, which gate passes are compared with.  Other overlaps are
+ * undefined.  Asynchronous. */
 juqcs_status juqcs_copy(void* d_dst, const void* d_src, size_t bytes,
                         void* hip_stream);
 

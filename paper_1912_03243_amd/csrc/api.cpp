@@ -71,7 +71,8 @@ struct juqcs_state {
   // per-pass timing of juqcs_run_circuit when profiling (else empty)
   bool profiling = false;
   std::vector<hipEvent_t> ev;
-  double bytes = 0.0;  // algorithmic bytes of the passes launched by the call
+  double bytes = 0.0;      // algorithmic bytes of the passes launched by the call
+  double mma_flops = 0.0;  // flops of the fused blocks launched by the call
 };
 
 namespace {
@@ -310,6 +311,17 @@ Gate make_gate1(int t, const C u[4]) {
   return g;
 }
 
+// Fraction of the state a per-gate pass reads and writes when the given
+// physical bits must be 1: the per-gate kernels move whole runs of 1 KiB,
+// so only bits at or above a run (64 C128 / 128 C64 amplitudes) select.
+double touched(const juqcs_state* st, uint64_t mask) {
+  const int rb = st->dt == JUQCS_C128 ? 6 : 7;
+  double f = 1.0;
+  for (int q = rb; q < 64; ++q)
+    if ((mask >> q) & 1) f *= 0.5;
+  return f;
+}
+
 juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g0) {
   hipError_t e = hipSuccess;
   Gate g = g0;
@@ -338,7 +350,7 @@ juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g0) {
         return JUQCS_OK;  // identity (up to the global factor)
       }
       e = launch_diag(st->dt, st->amps, st->n, uint64_t(1) << g.q[0], d1, st->stream);
-      st->bytes += 0.5 * full;
+      st->bytes += touched(st, uint64_t(1) << g.q[0]) * full;
     } else {
       e = launch_1q(st->dt, st->amps, st->n, g.q[0], -1, u, st->stream);
       st->bytes += full;
@@ -362,12 +374,12 @@ juqcs_status apply_gate_plain(juqcs_state* st, const Gate& g0) {
           prof_end(st);
           return JUQCS_OK;
         }
-        e = launch_diag(st->dt, st->amps, st->n, (uint64_t(1) << g.q[0]) | (uint64_t(1) << g.q[1]),
-                        u[3], st->stream);
-        st->bytes += 0.25 * full;
+        const uint64_t mask = (uint64_t(1) << g.q[0]) | (uint64_t(1) << g.q[1]);
+        e = launch_diag(st->dt, st->amps, st->n, mask, u[3], st->stream);
+        st->bytes += touched(st, mask) * full;
       } else {
         e = launch_1q(st->dt, st->amps, st->n, g.q[1], g.q[0], u, st->stream);
-        st->bytes += 0.5 * full;
+        st->bytes += touched(st, uint64_t(1) << g.q[0]) * full;
       }
     } else {
       e = launch_2q(st->dt, st->amps, st->n, g.q[0], g.q[1], m, st->stream);
@@ -420,6 +432,7 @@ juqcs_status apply_fused_phys(juqcs_state* st, int k, const int* targets, const 
   prof_end(st);
   if (e != hipSuccess) return hip_fail(e, "fused launch");
   st->bytes += full_pass_bytes(st);
+  st->mma_flops += 8.0 * (double)K * std::ldexp(1.0, st->n);
   return JUQCS_OK;
 }
 
@@ -647,12 +660,16 @@ juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates, size_t 
   o->gates = (int64_t)count;
   o->passes = 0;
   o->kernel_ms = 0.0;
+  o->flops = 0.0;
+  for (const Gate& x : g) o->flops += gate_flops(x) * std::ldexp(1.0, st->n);
   st->bytes = 0.0;
+  st->mma_flops = 0.0;
   st->profiling = o->profile != 0;
   juqcs_status rc = run_planned(st, g, mode, o);
   if (st->profiling) o->kernel_ms = prof_collect(st);
   st->profiling = false;
   o->bytes = st->bytes;
+  o->mma_flops = st->mma_flops;
   return rc;
 }
 

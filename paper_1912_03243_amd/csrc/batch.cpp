@@ -902,6 +902,8 @@ BranchLayout branch_layout(const BranchJob& J, int L) {
   return B;
 }
 
+thread_local juqcs_branch_stats g_branch_stats{};
+
 // L for a group size (rounded down to a power of two; 0 = every branch).
 int group_bits(int m, int group_size) {
   if (group_size <= 0) return 0;
@@ -952,6 +954,12 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
   const int L = lay.L;
   const long long gsize = lay.gsize, ngroups = lay.ngroups;
   for (int p = 0; p < P; ++p) set_free(&parts[p], L);
+  juqcs_branch_stats stats{};
+  stats.crossings = m;
+  stats.group_bits = L;
+  stats.groups = ngroups;
+  stats.lds_sum = lay.lds ? 1 : 0;
+  stats.sum_flops = (double)count * std::ldexp(1.0, m) * (6.0 * (P - 1) + 2.0);
   char* W = (char*)d_work;
   // split table: each part's qubits and their physical bits at the leaves
   std::vector<int32_t> tab(kBranchTabInts, 0);
@@ -1049,6 +1057,15 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
           for (long long c = 0; c < (1ll << sg.nfree); ++c) {
             const long long parent = a << (R - done), leaf = parent + (c << after);
             plans.push_back(node_plan(bp, sg, gi, L, c));
+            {
+              double f = 0.0;
+              for (const Gate& x : sg.gates) f += gate_flops(x);
+              stats.gate_flops += f * std::ldexp(1.0, bp.nloc);
+              stats.pass_bytes += (double)std::max<size_t>(1, plans.back().passes.size()) * 16.0 *
+                                  std::ldexp(1.0, bp.nloc);
+              stats.tile_passes += (int64_t)std::max<size_t>(1, plans.back().passes.size());
+              ++stats.tree_states;
+            }
             B.n.push_back(bp.nloc);
             B.state_off.push_back(lay.base[p] + (size_t)leaf * bp.sbytes);
             B.keep.push_back(r > 0 ? 1 : 0);
@@ -1107,6 +1124,7 @@ juqcs_status branch_amplitudes(int n, const juqcs_gate* gates, size_t gate_count
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "branch result copy");
   }
+  if (rc == JUQCS_OK) g_branch_stats = stats;
   return rc;
 }
 
@@ -1169,6 +1187,12 @@ extern "C" juqcs_status juqcs_branch_amplitudes_noalloc(int n, const juqcs_gate*
   return branch_amplitudes(n, gates, gate_count, side, d_z, words, count, group_size, d_out, ws,
                            count > 0 ? (size_t)JUQCS_NOALLOC_SCRATCH_BYTES : 0, (hipStream_t)hip_stream,
                            true);
+}
+
+extern "C" juqcs_status juqcs_branch_last_stats(juqcs_branch_stats* out) {
+  if (!out) return fail(JUQCS_ERR_ARG, "null output");
+  *out = g_branch_stats;
+  return JUQCS_OK;
 }
 
 extern "C" juqcs_status juqcs_branch_bytes(int n, const juqcs_gate* gates, size_t gate_count,

@@ -282,6 +282,8 @@ struct Gate {  // decoded gate: matrix on 1 or 2 qubits (physical positions)
 };
 
 bool decode_gate(const juqcs_gate& g, int n, Gate* out, std::string* err);
+// Algorithmic flops per state amplitude of a gate (planner.cpp).
+double gate_flops(const Gate& g);
 
 struct TilePlan {
   std::vector<TilePass> passes;

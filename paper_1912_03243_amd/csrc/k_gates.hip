@@ -434,6 +434,28 @@ __global__ __launch_bounds__(kThreads) void k_copy(uint4* __restrict__ dst,
   }
 }
 
+// In-place stream: every 16-byte word read and written back, in the access
+// pattern of the per-gate run kernels (each wave moves U consecutive runs of
+// 64 words, loads before stores): the HBM ceiling of an in-place pass.
+template <int U>
+__global__ __launch_bounds__(kThreads) void k_stream(uint4* __restrict__ p, uint64_t count) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  v4u* q = reinterpret_cast<v4u*>(p);
+  const uint64_t wave = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  v4u v[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const uint64_t i = (wave * U + k) * 64 + lane;
+    if (i < count) v[k] = ld_stream(&q[i]);
+  }
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const uint64_t i = (wave * U + k) * 64 + lane;
+    if (i < count) st_stream(&q[i], v[k]);
+  }
+}
+
 inline unsigned stride_grid(uint64_t count) {
   // grid-stride kernels: enough blocks to fill 256 CUs many times over
   const uint64_t want = (count + kThreads - 1) / kThreads;
@@ -658,6 +680,13 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const uint64_t count = bytes / 16;
+  if (dst == src) {
+    constexpr int U = 4;
+    const uint64_t waves = (count + 64 * U - 1) / (64 * U);
+    hipLaunchKernelGGL((k_stream<U>), dim3(grid_for(waves, kThreads / 64)), dim3(kThreads), 0, s,
+                       (uint4*)dst, count);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_copy, dim3(grid_for(count, kThreads * 4)), dim3(kThreads), 0, s,
                      (uint4*)dst, (const uint4*)src, count);
   return hipGetLastError();

@@ -215,6 +215,30 @@ bool decode_gate(const juqcs_gate& g, int n, Gate* out, std::string* err) {
   return true;
 }
 
+// Algorithmic flops per state amplitude of a gate, counted on the matrix
+// as given: a dense 2x2 is two complex products and a sum per amplitude
+// (14); a diagonal touches a half (3 when its first entry is 1) or every
+// amplitude (6); controlled forms touch a half (7) or, when diagonal, a
+// quarter (1.5; 0.5 for a sign flip); a controlled X only moves data; a
+// dense 4x4 is four complex products and three sums (30).
+double gate_flops(const Gate& g) {
+  const auto eq = [](C a, double re, double im) { return a.re == re && a.im == im; };
+  if (g.nq == 1) {
+    if (!g.diag) return 14.0;
+    return eq(g.m[0], 1.0, 0.0) ? 3.0 : 6.0;
+  }
+  // controlled form (index b_q0 + 2 b_q1): rows and columns with b_q0 = 0 identity
+  bool ctrl = true;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      if (((r & 1) == 0 || (c & 1) == 0) && !eq(g.m[4 * r + c], r == c ? 1.0 : 0.0, 0.0)) ctrl = false;
+  if (!ctrl) return 30.0;
+  const C u00 = g.m[5], u01 = g.m[7], u10 = g.m[13], u11 = g.m[15];
+  if (eq(u00, 0, 0) && eq(u11, 0, 0) && eq(u01, 1, 0) && eq(u10, 1, 0)) return 0.0;  // CNOT
+  if (eq(u01, 0, 0) && eq(u10, 0, 0) && eq(u00, 1, 0)) return eq(u11, -1, 0) ? 0.5 : 1.5;
+  return 7.0;
+}
+
 // ---------------------------------------------------------------------------
 // Tile planning
 // ---------------------------------------------------------------------------

@@ -43,7 +43,15 @@ class PlanOpts(ct.Structure):
                 ("autotune", ct.c_int32), ("pass_gates", ct.c_int32), ("relabel", ct.c_int32),
                 ("passes", ct.c_int64),
                 ("gates", ct.c_int64),
-                ("kernel_ms", ct.c_double), ("bytes", ct.c_double)]
+                ("kernel_ms", ct.c_double), ("bytes", ct.c_double), ("flops", ct.c_double),
+                ("mma_flops", ct.c_double)]
+
+
+class BranchStats(ct.Structure):
+    _fields_ = [("crossings", ct.c_int32), ("group_bits", ct.c_int32), ("groups", ct.c_int64),
+                ("tree_states", ct.c_int64), ("tile_passes", ct.c_int64), ("pass_bytes", ct.c_double),
+                ("gate_flops", ct.c_double), ("sum_flops", ct.c_double), ("lds_sum", ct.c_int32),
+                ("pad", ct.c_int32)]
 
 
 class JuqcsError(RuntimeError):
@@ -107,6 +115,7 @@ _SIGS = {
     "juqcs_branch_amplitudes_device": [_I, _P, _S, ct.POINTER(ct.c_uint8), _P, _I, _S, _I, _P,
                                        _P, _S, _P],
     "juqcs_branch_amplitudes_noalloc": [_I, _P, _S, ct.POINTER(ct.c_uint8), _P, _I, _S, _I, _P, _P],
+    "juqcs_branch_last_stats": [ct.POINTER(BranchStats)],
     "juqcs_branch_bytes": [_I, _P, _S, ct.POINTER(ct.c_uint8), _I, _S, _I, _I, ct.POINTER(_S),
                            ct.POINTER(_S)],
     "juqcs_copy": [_P, _P, _S, _P],
@@ -270,6 +279,13 @@ def juqcs_branch_amplitudes_device(n: int, gates, side, z, out, group_size: int 
                                                _stream_handle(stream)),
            "juqcs_branch_amplitudes_device")
     return out
+
+
+def juqcs_branch_last_stats() -> dict:
+    """Statistics of this thread's last completed decomposition call."""
+    st = BranchStats()
+    _check(_lib.juqcs_branch_last_stats(ct.byref(st)), "juqcs_branch_last_stats")
+    return {name: getattr(st, name) for name, _ in BranchStats._fields_ if name != "pad"}
 
 
 NOALLOC_SCRATCH_BYTES = 32 << 20  # JUQCS_NOALLOC_SCRATCH_BYTES
