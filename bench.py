@@ -157,7 +157,9 @@ def main():
                     help="grid42: crossing CZs kept (S of the decomposition, 2^S branches)")
     ap.add_argument("--group", type=int, default=0,
                     help="grid48, ghz128: branches resident at a time (0 = automatic)")
-    ap.add_argument("--autotune", type=int, default=0, help="batch4096: timed-trial autotuner")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="brick30: pick the planner options by timed trials first (then mode auto); "
+                         "batch4096: timed-trial in-pass fusion width, compared with the cost model")
     ap.add_argument("--tile-fuse", type=int, default=0, help="in-pass fusion width (0 = default)")
     ap.add_argument("--tile-bits", type=int, default=0, help="tile bits (0 = default)")
     ap.add_argument("--low-bits", type=int, default=0, help="contiguous low tile bits (0 = default)")
@@ -200,10 +202,20 @@ def main():
     log(f"workload: n={n}, {len(gates)} gates, {z.size} bitstrings, mode={args.mode}")
 
     st = juqcs.State(n, "c128", device=dev, stream=stream)
+    tune = None
+    run_mode = args.mode
+    if args.autotune and args.mode == "tile":
+        t0 = time.perf_counter()
+        tune = st.autotune(gates)
+        tune["wall_s"] = time.perf_counter() - t0
+        run_mode = "auto"
+        log(f"autotune: {tune}")
 
     def step(mode, profile):
         st.init(0)
-        if mode == "tile":
+        if mode == "auto":
+            o = st.run(gates, mode="auto", profile=profile)
+        elif mode == "tile":
             o = st.run(gates, mode=mode, profile=profile, fuse_k=args.tile_fuse,
                        tile_bits=args.tile_bits, low_bits=args.low_bits,
                        pass_gates=args.pass_gates, relabel=args.relabel)
@@ -214,7 +226,7 @@ def main():
         return o, nrm
 
     for i in range(args.warmup):
-        step(args.mode, True)
+        step(run_mode, True)
         log(f"warmup step {i} done")
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -224,11 +236,13 @@ def main():
     torch.cuda.synchronize()
     start.record(stream)
     t0 = time.perf_counter()
+    mma_flops = 0.0
     for i in range(args.steps):
-        o, nrm = step(args.mode, True)
+        o, nrm = step(run_mode, True)
         kernel_ms += o.kernel_ms
         kbytes += o.bytes
         passes += o.passes
+        mma_flops += o.mma_flops
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -257,7 +271,8 @@ def main():
     per_launch = kbytes / max(passes, 1)
     hbm = {"achieved_GBps": achieved, "peak_GBps": HBM_PEAK_GBPS, "frac": achieved / HBM_PEAK_GBPS,
            "bytes_per_launch": per_launch}
-    if args.mode == "tile":
+    chosen = tune["mode"] if tune else args.mode
+    if chosen == "tile":
         # A tile pass absorbs ~64 gates here: far past the FP64 ridge (about
         # 22 gates per pass), so the pass is bound by arithmetic on chip.
         # achieved = the absorbed gates' algorithmic flops per launch / the
@@ -266,11 +281,18 @@ def main():
         tflops = flops_launch / (pass_ms / 1e3) / 1e12
         roofline = {"bound": "alu", "achieved": tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": tflops / FP64_VECTOR_PEAK_TFLOPS,
-                    "traffic": traffic_for(TILE_SOURCES), "kernel": "k_tile_fixed<double,13,1024>",
+                    "traffic": traffic_for(TILE_SOURCES),
+                    "kernel": ("k_tile_fixed<double,12,512>" if tune and tune["tile_bits"] == 12
+                               else "k_tile_fixed<double,13,1024>"),
                     "flops_per_launch": flops_launch, "avg_launch_ms": pass_ms, "hbm": hbm}
+    elif chosen == "fused":
+        tf = mma_flops / max(passes, 1) / (pass_ms / 1e3) / 1e12
+        roofline = {"bound": "mfma", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_fused<F64>",
+                    "flops_per_launch": mma_flops / max(passes, 1), "avg_launch_ms": pass_ms, "hbm": hbm}
     else:
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": args.mode,
+                    "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": chosen,
                     "bytes_per_launch": per_launch, "avg_launch_ms": pass_ms}
     result = {
         "metric": METRIC,
@@ -288,7 +310,8 @@ def main():
         "config": {"workload": "brick30: n=30 complex128 state (16 GiB), 20 layers of Haar U(2) "
                                "on every qubit + brick CZ (890 gates, seed 2); init, all gates, "
                                "4096 amplitudes (seed 1002) and the norm per step",
-                   "n": n, "gates": ngates, "bitstrings": int(z.size), "mode": args.mode,
+                   "n": n, "gates": ngates, "bitstrings": int(z.size), "mode": chosen,
+                   "autotune": tune,
                    "tile_fuse": args.tile_fuse, "tile_bits": args.tile_bits,
                    "pass_gates": args.pass_gates, "relabel": args.relabel,
                    "passes_per_step": passes // args.steps},
@@ -311,12 +334,12 @@ def main():
     stream_gbps = 3 * 2 * nb / (e0.elapsed_time(e1) / 1e3) / 1e9
     result["stream_inplace_GBps"] = stream_gbps
     hbm["frac_of_stream"] = achieved / stream_gbps
-    if args.mode != "tile":
+    if chosen == "plain":
         result["roofline"]["frac_of_stream"] = achieved / stream_gbps
 
     if args.compare:
         for mode in ("plain", "fused"):
-            if mode == args.mode:
+            if mode == chosen:
                 continue
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -436,6 +459,18 @@ def other_workload(args, juqcs, W, dev, stream):
             idx = np.stack([W.batch_bitstrings(i, n) for i, (n, _) in enumerate(inst)])
             amps = b.amplitudes(idx, s)
             norms = b.norms(s)
+        cost_model_ms = None
+        if args.autotune:
+            # the same batch planned by the cost model alone, on the same states
+            t0 = time.perf_counter()
+            b0 = juqcs.Batch(inst, device=dev, states=b.states, relabel=args.relabel, stream=s)
+            t_plan0 = time.perf_counter() - t0
+            with torch.cuda.stream(s):
+                cost_model_ms = _timed(lambda: b0.run(s), args.steps, args.warmup, s)
+                b0.wait()
+            b0.close()
+            # the autotuned batch wrote the states last for the read-outs above
+            log(f"cost-model plan: {cost_model_ms:.1f} ms (planning {t_plan0:.1f}s) vs autotuned {ms:.1f} ms")
         gates = sum(len(g) for _, g in inst)
         amp_updates = sum(len(g) * float(1 << n) for n, g in inst)
         flops = sum(gate_flops_per_amp(g, W) * float(1 << n) for n, g in inst)
@@ -458,6 +493,7 @@ def other_workload(args, juqcs, W, dev, stream):
                        "autotune": bool(args.autotune), "relabel": args.relabel},
             "amp_updates_per_s": amp_updates / (ms / 1e3),
             "planning_s": t_plan,
+            "cost_model_ms_per_step": cost_model_ms,
             # the graph is one persistent tile kernel per pass round: its
             # time is the step; in-tile ops run on FP32 matrix cores and VALU
             "roofline": {"bound": "alu", "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS,

@@ -166,7 +166,8 @@ typedef enum {
                            HBM read+write per pass                        */
   JUQCS_PLAN_FUSED = 2, /* greedy fusion into dense k-qubit blocks applied
                            with juqcs_apply_fused_k's kernels             */
-  JUQCS_PLAN_AUTO = 3   /* TILE (the fastest on this hardware)             */
+  JUQCS_PLAN_AUTO = 3   /* the options juqcs_autotune stored for a circuit
+                           of this structure, else TILE with its defaults */
 } juqcs_plan_mode;
 
 typedef struct {
@@ -215,6 +216,42 @@ typedef struct {
  * NULL (AUTO).  Errors: ARG, QUBIT, NUMERIC, UNSUPPORTED. */
 juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates,
                                size_t count, juqcs_plan_opts* opts);
+
+/* ------------------------------------------------------------------------
+ * Autotuner
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  juqcs_plan_opts opts;  /* chosen planner options (mode, fuse_k, mma,
+                            tile_bits, low_bits, pass_gates, relabel)       */
+  double ms;             /* one run with them (HIP events on the stream,
+                            planning and upload included)                  */
+  double default_ms;     /* one run with the defaults (TILE, all 0)        */
+  int32_t trials;        /* runs timed                                     */
+  int32_t pad;
+  uint64_t key;          /* circuit structure key (see juqcs_autotune)     */
+} juqcs_tune_result;
+
+/* Picks planner options for this circuit on this state by timed trials:
+ * from the defaults, one parameter at a time (tile low bits, tile bits,
+ * in-pass fusion width, gates per pass, relabeling), keeping the fastest
+ * value of each, then dense fused blocks of k = 3..6 (FP64 for C128, FP32
+ * for C64), and one pass per gate for small states.  Every trial starts
+ * from |0...0> on st's buffers (the state is left as the last trial made
+ * it).  The fastest options are stored in the library's tuning table under
+ * the circuit's structure key (n, amplitude type, ENC2 block bits, every
+ * gate's op and qubits; matrices and angles do not enter), where
+ * juqcs_run_circuit with mode JUQCS_PLAN_AUTO finds them.  Synchronises.
+ * Errors: as for juqcs_run_circuit. */
+juqcs_status juqcs_autotune(juqcs_state* st, const juqcs_gate* gates, size_t count,
+                            juqcs_tune_result* out);
+
+/* The tuning table as JSON (one object per entry), and back: load adds or
+ * replaces entries.  clear empties the table.  Errors: ARG (null path,
+ * unreadable or malformed file). */
+juqcs_status juqcs_tune_save(const char* path);
+juqcs_status juqcs_tune_load(const char* path);
+juqcs_status juqcs_tune_clear(void);
 
 /* ------------------------------------------------------------------------
  * Read-out

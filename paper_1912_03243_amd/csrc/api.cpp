@@ -5,7 +5,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -496,6 +499,50 @@ juqcs_status move_layout(juqcs_state* st, const int* target) {
 juqcs_status run_planned(juqcs_state* st, const std::vector<Gate>& g, int mode,
                          juqcs_plan_opts* o);
 
+// ---------------------------------------------------------------- tuning --
+// Circuit structure key: FNV-1a over n, the amplitude type, the ENC2 block
+// bits and every gate's op and qubits.
+uint64_t structure_key(const juqcs_state* st, const juqcs_gate* gates, size_t count) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(st->n);
+  mix(st->dt);
+  mix(st->B);
+  for (size_t i = 0; i < count; ++i) {
+    mix(gates[i].op);
+    mix(gates[i].q0);
+    mix(gates[i].q1);
+  }
+  return h;
+}
+
+struct TuneEntry {
+  juqcs_tune_result r;
+  int n = 0, dtype = 0;
+};
+std::mutex g_tune_mu;
+std::map<uint64_t, TuneEntry> g_tune;
+
+bool tuned_options(uint64_t key, juqcs_plan_opts* o) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  const juqcs_plan_opts& t = it->second.r.opts;
+  o->mode = t.mode;
+  o->fuse_k = t.fuse_k;
+  o->mma = t.mma;
+  o->tile_bits = t.tile_bits;
+  o->low_bits = t.low_bits;
+  o->pass_gates = t.pass_gates;
+  o->relabel = t.relabel;
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -655,6 +702,18 @@ juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates, size_t 
     return fail(JUQCS_ERR_ARG, "bad plan mode");
   std::vector<Gate> g;
   if (juqcs_status rc = decode_all(st, gates, count, &g)) return rc;
+  juqcs_plan_opts tuned = *o;
+  if (o->mode == JUQCS_PLAN_AUTO && tuned_options(structure_key(st, gates, count), &tuned)) {
+    tuned.profile = o->profile;
+    juqcs_status rc = juqcs_run_circuit(st, gates, count, &tuned);
+    o->passes = tuned.passes;
+    o->gates = tuned.gates;
+    o->kernel_ms = tuned.kernel_ms;
+    o->bytes = tuned.bytes;
+    o->flops = tuned.flops;
+    o->mma_flops = tuned.mma_flops;
+    return rc;
+  }
   int mode = o->mode == JUQCS_PLAN_AUTO ? JUQCS_PLAN_TILE : o->mode;
   if (st->dt == JUQCS_ENC2) mode = JUQCS_PLAN_TILE;
   o->gates = (int64_t)count;
@@ -671,6 +730,201 @@ juqcs_status juqcs_run_circuit(juqcs_state* st, const juqcs_gate* gates, size_t 
   o->bytes = st->bytes;
   o->mma_flops = st->mma_flops;
   return rc;
+}
+
+juqcs_status juqcs_autotune(juqcs_state* st, const juqcs_gate* gates, size_t count,
+                            juqcs_tune_result* out) {
+  if (check_state(st)) return JUQCS_ERR_ARG;
+  if (!out) return fail(JUQCS_ERR_ARG, "null output");
+  if (count > 0 && !gates) return fail(JUQCS_ERR_ARG, "null gate array");
+  *out = juqcs_tune_result{};
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  juqcs_status err = JUQCS_OK;
+  int trials = 0;
+  // one timed run from |0...0>; infinite if the options are rejected
+  auto time_run = [&](juqcs_plan_opts o) {
+    o.profile = 0;
+    if (juqcs_state_init(st, 0) != JUQCS_OK) return 1e300;
+    if (hipEventRecord(a, st->stream) != hipSuccess) return 1e300;
+    const juqcs_status rc = juqcs_run_circuit(st, gates, count, &o);
+    (void)hipEventRecord(b, st->stream);
+    (void)hipEventSynchronize(b);
+    if (rc == JUQCS_ERR_HIP) err = rc;
+    float ms = 0.0f;
+    if (rc != JUQCS_OK || hipEventElapsedTime(&ms, a, b) != hipSuccess) return 1e300;
+    ++trials;
+    return (double)ms;
+  };
+  // the better of two runs (the first run of a kernel also pays for loading it)
+  auto measure = [&](const juqcs_plan_opts& o, double best) {
+    double t = time_run(o);
+    if (t < 2.0 * best) t = std::min(t, time_run(o));
+    return t;
+  };
+  juqcs_plan_opts cur{};
+  cur.mode = JUQCS_PLAN_TILE;
+  const double t_default = measure(cur, 1e300);
+  double best = t_default;
+  juqcs_plan_opts bo = cur;
+  auto consider = [&](juqcs_plan_opts o) {
+    const double t = measure(o, best);
+    if (t < best) {
+      best = t;
+      bo = o;
+    }
+  };
+  const bool c128 = st->dt == JUQCS_C128, enc2 = st->dt == JUQCS_ENC2;
+  const std::vector<int> low_v = c128 ? std::vector<int>{4, 5, 6} : std::vector<int>{5, 6, 7, 8};
+  const std::vector<int> tb_v = c128 ? std::vector<int>{12, 13} : std::vector<int>{12, 13, 14};
+  const std::vector<int> cap_v = c128 ? std::vector<int>{-1, 60, 40, 25} : std::vector<int>{-1, 90, 60, 40};
+  // coordinate descent over the tile options, each from the best so far
+  if (!enc2)
+    for (int v : low_v) {
+      juqcs_plan_opts o = bo;
+      o.low_bits = v;
+      consider(o);
+    }
+  for (int v : tb_v) {
+    juqcs_plan_opts o = bo;
+    o.tile_bits = v;
+    if (o.low_bits == 0 && !enc2) o.low_bits = c128 ? 5 : 7;
+    consider(o);
+  }
+  for (int v : {2, 4}) {
+    juqcs_plan_opts o = bo;
+    o.fuse_k = v;
+    consider(o);
+  }
+  for (int v : cap_v) {
+    juqcs_plan_opts o = bo;
+    o.pass_gates = v;
+    consider(o);
+  }
+  {
+    juqcs_plan_opts o = bo;
+    o.relabel = -1;
+    consider(o);
+  }
+  // dense fused blocks on the matrix cores (full precision of the state)
+  if (!enc2)
+    for (int k = 3; k <= 6 && k <= st->n; ++k) {
+      juqcs_plan_opts o{};
+      o.mode = JUQCS_PLAN_FUSED;
+      o.fuse_k = k;
+      o.mma = JUQCS_MMA_AUTO;
+      consider(o);
+    }
+  // one pass per gate: only where that cannot take long
+  if (!enc2 && (st->n <= 24 || count <= 32)) {
+    juqcs_plan_opts o{};
+    o.mode = JUQCS_PLAN_PLAIN;
+    consider(o);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (err != JUQCS_OK) return err;
+  if (!(best < 1e299)) return fail(JUQCS_ERR_UNSUPPORTED, "no planner option ran this circuit");
+  out->opts = bo;
+  out->opts.profile = 0;
+  out->ms = best;
+  out->default_ms = t_default;
+  out->trials = trials;
+  out->key = structure_key(st, gates, count);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  TuneEntry& te = g_tune[out->key];
+  te.r = *out;
+  te.n = st->n;
+  te.dtype = st->dt;
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_tune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_tune_save(const char* path) {
+  if (!path) return fail(JUQCS_ERR_ARG, "null path");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(JUQCS_ERR_ARG, std::string("cannot write ") + path);
+  std::fprintf(f, "{\"juqcs_tune\": 1, \"entries\": [\n");
+  size_t i = 0;
+  for (const auto& kv : g_tune) {
+    const juqcs_tune_result& r = kv.second.r;
+    std::fprintf(f,
+                 " {\"key\": \"%016llx\", \"n\": %d, \"dtype\": %d, \"mode\": %d, \"fuse_k\": %d, "
+                 "\"mma\": %d, \"tile_bits\": %d, \"low_bits\": %d, \"pass_gates\": %d, "
+                 "\"relabel\": %d, \"ms\": %.6f, \"default_ms\": %.6f, \"trials\": %d}%s\n",
+                 (unsigned long long)kv.first, kv.second.n, kv.second.dtype, r.opts.mode, r.opts.fuse_k,
+                 r.opts.mma, r.opts.tile_bits, r.opts.low_bits, r.opts.pass_gates, r.opts.relabel, r.ms,
+                 r.default_ms, r.trials, ++i < g_tune.size() ? "," : "");
+  }
+  std::fprintf(f, "]}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok) return fail(JUQCS_ERR_ARG, std::string("cannot write ") + path);
+  return JUQCS_OK;
+}
+
+juqcs_status juqcs_tune_load(const char* path) {
+  if (!path) return fail(JUQCS_ERR_ARG, "null path");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(JUQCS_ERR_ARG, std::string("cannot read ") + path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  if (text.find("\"juqcs_tune\"") == std::string::npos) return fail(JUQCS_ERR_ARG, "not a tuning table");
+  // every object after "entries": numbers by name, the key as hex text
+  auto number = [](const std::string& obj, const char* name, double* v) {
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t at = obj.find(pat);
+    if (at == std::string::npos) return false;
+    char* end = nullptr;
+    *v = std::strtod(obj.c_str() + at + pat.size(), &end);
+    return end != obj.c_str() + at + pat.size();
+  };
+  std::map<uint64_t, TuneEntry> add;
+  size_t p = text.find("\"entries\"");
+  if (p == std::string::npos) return fail(JUQCS_ERR_ARG, "tuning table without entries");
+  while ((p = text.find('{', p)) != std::string::npos) {
+    const size_t q = text.find('}', p);
+    if (q == std::string::npos) return fail(JUQCS_ERR_ARG, "malformed tuning table");
+    const std::string obj = text.substr(p, q - p + 1);
+    p = q + 1;
+    const size_t kat = obj.find("\"key\": \"");
+    if (kat == std::string::npos) return fail(JUQCS_ERR_ARG, "tuning entry without key");
+    const uint64_t key = std::strtoull(obj.c_str() + kat + 8, nullptr, 16);
+    double v[12];
+    const char* names[12] = {"n", "dtype", "mode", "fuse_k", "mma", "tile_bits", "low_bits",
+                             "pass_gates", "relabel", "ms", "default_ms", "trials"};
+    for (int i = 0; i < 12; ++i)
+      if (!number(obj, names[i], &v[i])) return fail(JUQCS_ERR_ARG, std::string("tuning entry without ") + names[i]);
+    if (v[2] < JUQCS_PLAN_PLAIN || v[2] > JUQCS_PLAN_FUSED) return fail(JUQCS_ERR_ARG, "tuning entry with a bad mode");
+    TuneEntry te;
+    te.n = (int)v[0];
+    te.dtype = (int)v[1];
+    te.r.opts.mode = (int32_t)v[2];
+    te.r.opts.fuse_k = (int32_t)v[3];
+    te.r.opts.mma = (int32_t)v[4];
+    te.r.opts.tile_bits = (int32_t)v[5];
+    te.r.opts.low_bits = (int32_t)v[6];
+    te.r.opts.pass_gates = (int32_t)v[7];
+    te.r.opts.relabel = (int32_t)v[8];
+    te.r.ms = v[9];
+    te.r.default_ms = v[10];
+    te.r.trials = (int32_t)v[11];
+    te.r.key = key;
+    add[key] = te;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (auto& kv : add) g_tune[kv.first] = kv.second;
+  return JUQCS_OK;
 }
 
 }  // extern "C"

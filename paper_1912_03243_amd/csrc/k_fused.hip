@@ -27,12 +27,16 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kCols = 64;  // columns per workgroup, 16 per wave
+constexpr int kLdw = kCols + 1;  // LDS row stride of a panel: rows fall in different banks
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline v8bf as_bf(v8s x) { return __builtin_bit_cast(v8bf, x); }
 
 // FP32 -> BF16 with round to nearest even (finite inputs).
 __device__ inline short bf16_rne(float x) {
@@ -63,41 +67,77 @@ struct PrecTraits<P_BF16X3> {
   using T = float;
 };
 
+// Panel geometry of a fused block.  A panel is the KD x NC sub-matrix of
+// amplitudes (rows: the k target bits, columns: the NC = 2^cb lowest
+// non-target bits) for one setting of every other bit.  In address order it
+// is 2^khi contiguous chunks of 2^S amplitudes (S: the lowest S bits hold
+// the low targets and the cb column bits; the khi high targets select the
+// chunk), so loads and stores walk whole chunks of at least NC amplitudes.
+struct FusedGeom {
+  int32_t k, S, khi, cb;
+  int32_t tbits[6];   // targets in matrix order (physical bits)
+  int32_t hts[6];     // high targets (>= S), ascending: inserted into the panel index
+};
+
 // KD: K = 2^k amplitudes per column; R = padded real rows (multiple of 16).
-// Persistent: every workgroup loads the matrix once and then walks column
-// panels (gridDim.x apart), prefetching the next panel into registers while
-// the current one is multiplied.
+// Persistent: every workgroup loads the matrix once, builds the panel map
+// (element -> row, column) in LDS, and then walks panels (gridDim.x apart),
+// prefetching the next panel into registers while the current one is
+// multiplied.
 template <int P, int KD>
 __global__ __launch_bounds__(kThreads) void k_fused(
-    cplx<typename PrecTraits<P>::T>* __restrict__ psi, uint64_t ncols, TileGeom tg,
+    cplx<typename PrecTraits<P>::T>* __restrict__ psi, uint64_t npanels, FusedGeom fg,
     const typename PrecTraits<P>::T* __restrict__ At /* R x R, transposed: At[col*R+row] */) {
   using T = typename PrecTraits<P>::T;
   constexpr int R0 = 2 * KD;
   constexpr int R = R0 < 16 ? 16 : R0;
   constexpr bool kALds = (R * R * sizeof(T)) <= 64 * 1024;
-  constexpr int PER = (KD * kCols + kThreads - 1) / kThreads;  // panel amplitudes per thread
+  constexpr int E = KD * kCols;                           // panel elements (at most)
+  constexpr int PER = (E + kThreads - 1) / kThreads;      // panel amplitudes per thread
   // register prefetch only where it fits beside the accumulators
   constexpr bool kPrefetch = PER * sizeof(cplx<T>) <= 8 * sizeof(cplx<double>);
   constexpr int PV = kPrefetch ? PER : 1;
-  __shared__ T sB[R * kCols];
+  __shared__ T sB[R * kLdw];
   __shared__ T sA[kALds ? R * R : 1];
-  __shared__ uint64_t off[KD];
-  __shared__ int hs[6];
-
-  // tg.hbits[0..k) hold the targets in matrix order; tg.hbits[k..2k) sorted.
-  const int k = tg.H;
-  if (threadIdx.x < KD) {
-    uint64_t o = 0;
-    for (int j = 0; j < k; ++j) o |= (uint64_t)((threadIdx.x >> j) & 1) << tg.hbits[j];
-    off[threadIdx.x] = o;
+  __shared__ uint16_t map[E];        // row << 6 | column of panel element e
+  __shared__ uint64_t offhi[KD];     // address offset of chunk h
+  const int k = fg.k, S = fg.S, khi = fg.khi;
+  const int ncols = 1 << fg.cb, ne = KD << fg.cb;
+  const uint64_t omask = (uint64_t(1) << S) - 1;
+  for (int e = threadIdx.x; e < ne; e += kThreads) {
+    const int h = e >> S;
+    const uint64_t o = (uint64_t)e & omask;
+    int r = 0, c = 0, nc = 0, nh = 0;
+    for (int j = 0; j < k; ++j) {
+      const int t = fg.tbits[j];
+      if (t < S) r |= (int)((o >> t) & 1) << j;
+    }
+    for (int b = 0; b < S; ++b) {
+      bool tgt = false;
+      for (int j = 0; j < k; ++j) tgt |= fg.tbits[j] == b;
+      if (!tgt) c |= (int)((o >> b) & 1) << nc++;
+    }
+    // high target j is bit i of h, i = its rank among the high targets
+    for (int j = 0; j < k; ++j) {
+      if (fg.tbits[j] < S) continue;
+      int i = 0;
+      for (int jj = 0; jj < khi; ++jj) i += fg.hts[jj] < fg.tbits[j] ? 1 : 0;
+      r |= ((h >> i) & 1) << j;
+    }
+    (void)nh;
+    map[e] = (uint16_t)((r << 6) | c);
   }
-  if (threadIdx.x < 6) hs[threadIdx.x] = (int)threadIdx.x < k ? tg.hbits[k + threadIdx.x] : 0;
+  if (threadIdx.x < (1 << khi)) {
+    uint64_t o = 0;
+    for (int i = 0; i < khi; ++i) o |= (uint64_t)((threadIdx.x >> i) & 1) << fg.hts[i];
+    offhi[threadIdx.x] = o;
+  }
   if (kALds) {
     for (int i = threadIdx.x; i < R * R; i += kThreads) sA[i] = At[i];
   }
   // padded rows of B stay zero
   if (R > R0) {
-    for (int i = R0 * kCols + threadIdx.x; i < R * kCols; i += kThreads) sB[i] = T(0);
+    for (int i = R0 * kLdw + threadIdx.x; i < R * kLdw; i += kThreads) sB[i] = T(0);
   }
   __syncthreads();
   const T* A = kALds ? sA : At;
@@ -105,50 +145,44 @@ __global__ __launch_bounds__(kThreads) void k_fused(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lhi = lane >> 4;
 
-  // element e = r * kCols + col of a panel: amplitude r of column col
-  auto col_base = [&](uint64_t c) {
-    uint64_t base = c;
-    for (int j = 0; j < k; ++j) base = insert_zero(base, hs[j]);
+  auto panel_base = [&](uint64_t pi) {
+    uint64_t base = pi << S;
+    for (int i = 0; i < khi; ++i) base = insert_zero(base, fg.hts[i]);
     return base;
   };
+  auto addr = [&](uint64_t base, int e) { return base + offhi[e >> S] + ((uint64_t)e & omask); };
+  auto to_lds = [&](int e, cplx<T> w) {
+    const int m = map[e], r = m >> 6, c = m & 63;
+    sB[(2 * r) * kLdw + c] = w.re;
+    sB[(2 * r + 1) * kLdw + c] = w.im;
+  };
   cplx<T> v[PV];
-  auto fetch = [&](uint64_t cb) {
+  auto fetch = [&](uint64_t pi) {
+    const uint64_t base = panel_base(pi);
 #pragma unroll
     for (int q = 0; q < PV; ++q) {
       const int e = q * kThreads + threadIdx.x;
-      const int col = e % kCols, r = e / kCols;
-      const uint64_t c = cb + col;
       v[q] = cplx<T>{T(0), T(0)};
-      if (e < KD * kCols && c < ncols) v[q] = ld_amp(&psi[col_base(c) | off[r]]);
+      if (e < ne) v[q] = ld_amp(&psi[addr(base, e)]);
     }
   };
-  uint64_t cb = (uint64_t)blockIdx.x * kCols;
-  const uint64_t stride = (uint64_t)gridDim.x * kCols;
-  if (kPrefetch && cb < ncols) fetch(cb);
-  for (; cb < ncols; cb += stride) {
-    // ---- the 2K x 64 panel into LDS (prefetched, or loaded here)
+  uint64_t pi = blockIdx.x;
+  const uint64_t stride = gridDim.x;
+  if (kPrefetch && pi < npanels) fetch(pi);
+  for (; pi < npanels; pi += stride) {
+    const uint64_t base = panel_base(pi);
+    // ---- the panel into LDS as 2K rows x NC columns (prefetched, or loaded here)
     if constexpr (kPrefetch) {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int e = q * kThreads + threadIdx.x;
-        if (e < KD * kCols) {
-          const int col = e % kCols, r = e / kCols;
-          sB[(2 * r) * kCols + col] = v[q].re;
-          sB[(2 * r + 1) * kCols + col] = v[q].im;
-        }
+        if (e < ne) to_lds(e, v[q]);
       }
     } else {
-      for (int e = threadIdx.x; e < KD * kCols; e += kThreads) {
-        const int col = e % kCols, r = e / kCols;
-        const uint64_t c = cb + col;
-        cplx<T> w = {T(0), T(0)};
-        if (c < ncols) w = ld_amp(&psi[col_base(c) | off[r]]);
-        sB[(2 * r) * kCols + col] = w.re;
-        sB[(2 * r + 1) * kCols + col] = w.im;
-      }
+      for (int e = threadIdx.x; e < ne; e += kThreads) to_lds(e, ld_amp(&psi[addr(base, e)]));
     }
     __syncthreads();
-    if (kPrefetch && cb + stride < ncols) fetch(cb + stride);
+    if (kPrefetch && pi + stride < npanels) fetch(pi + stride);
 
     // ---- per wave: out(R x 16) = A(R x R) * B(R x 16)
     const int cw = wave * 16;
@@ -157,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(
 #pragma unroll
       for (int t = 0; t < R / 16; ++t) acc[t] = v4d{0, 0, 0, 0};
       for (int kk = 0; kk < R; kk += 4) {
-        const double bv = sB[(kk + lhi) * kCols + cw + l16];
+        const double bv = sB[(kk + lhi) * kLdw + cw + l16];
 #pragma unroll
         for (int t = 0; t < R / 16; ++t) {
           const double av = A[(kk + lhi) * R + t * 16 + l16];
@@ -168,13 +202,13 @@ __global__ __launch_bounds__(kThreads) void k_fused(
 #pragma unroll
       for (int t = 0; t < R / 16; ++t)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) sB[(t * 16 + 4 * g + lhi) * kCols + cw + l16] = acc[t][g];
+        for (int g = 0; g < 4; ++g) sB[(t * 16 + 4 * g + lhi) * kLdw + cw + l16] = acc[t][g];
     } else if constexpr (P == P_F32) {
       v4f acc[R / 16];
 #pragma unroll
       for (int t = 0; t < R / 16; ++t) acc[t] = v4f{0, 0, 0, 0};
       for (int kk = 0; kk < R; kk += 4) {
-        const float bv = sB[(kk + lhi) * kCols + cw + l16];
+        const float bv = sB[(kk + lhi) * kLdw + cw + l16];
 #pragma unroll
         for (int t = 0; t < R / 16; ++t) {
           const float av = A[(kk + lhi) * R + t * 16 + l16];
@@ -184,65 +218,67 @@ __global__ __launch_bounds__(kThreads) void k_fused(
 #pragma unroll
       for (int t = 0; t < R / 16; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sB[(t * 16 + 4 * lhi + i) * kCols + cw + l16] = acc[t][i];
+        for (int i = 0; i < 4; ++i) sB[(t * 16 + 4 * lhi + i) * kLdw + cw + l16] = acc[t][i];
     } else {
+      // BF16 operands on the gfx950 double-rate shape 16x16x32: lane
+      // 16 q + c holds K slots 8 q .. 8 q + 7 (K padded to 32 with zeros)
       v4f acc[R / 16];
 #pragma unroll
       for (int t = 0; t < R / 16; ++t) acc[t] = v4f{0, 0, 0, 0};
-      for (int kk = 0; kk < R; kk += 16) {
-        v4s bh, bl;
+      for (int kk = 0; kk < R; kk += 32) {
+        v8s bh, bl;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float x = sB[(kk + 4 * lhi + i) * kCols + cw + l16];
+        for (int i = 0; i < 8; ++i) {
+          const int kr = kk + 8 * lhi + i;
+          const float x = kr < R ? sB[kr * kLdw + cw + l16] : 0.0f;
           const short h = bf16_rne(x);
           bh[i] = h;
           bl[i] = bf16_rne(x - bf16_to_f32(h));
         }
 #pragma unroll
         for (int t = 0; t < R / 16; ++t) {
-          v4s ah, al;
+          v8s ah, al;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float x = A[(kk + 4 * lhi + i) * R + t * 16 + l16];
+          for (int i = 0; i < 8; ++i) {
+            const int kr = kk + 8 * lhi + i;
+            const float x = kr < R ? A[kr * R + t * 16 + l16] : 0.0f;
             const short h = bf16_rne(x);
             ah[i] = h;
             al[i] = bf16_rne(x - bf16_to_f32(h));
           }
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bh), acc[t], 0, 0, 0);
           if constexpr (P == P_BF16X3) {
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bl), acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(al), as_bf(bh), acc[t], 0, 0, 0);
           }
         }
       }
 #pragma unroll
       for (int t = 0; t < R / 16; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sB[(t * 16 + 4 * lhi + i) * kCols + cw + l16] = acc[t][i];
+        for (int i = 0; i < 4; ++i) sB[(t * 16 + 4 * lhi + i) * kLdw + cw + l16] = acc[t][i];
     }
     __syncthreads();
 
-    // ---- store (coalesced over columns)
-    for (int e = threadIdx.x; e < KD * kCols; e += kThreads) {
-      const int col = e % kCols, r = e / kCols;
-      const uint64_t c = cb + col;
-      if (c < ncols) {
-        cplx<T> w;
-        w.re = sB[(2 * r) * kCols + col];
-        w.im = sB[(2 * r + 1) * kCols + col];
-        st_amp(&psi[col_base(c) | off[r]], w);
-      }
+    // ---- store in address order (whole chunks)
+    for (int e = threadIdx.x; e < ne; e += kThreads) {
+      const int m = map[e], r = m >> 6, c = m & 63;
+      cplx<T> w;
+      w.re = sB[(2 * r) * kLdw + c];
+      w.im = sB[(2 * r + 1) * kLdw + c];
+      st_amp(&psi[addr(base, e)], w);
     }
+    (void)ncols;
     __syncthreads();
   }
 }
 
 template <int P>
-hipError_t dispatch_k(void* amps, int n, int k, const TileGeom& tg, const void* d_mat,
+hipError_t dispatch_k(void* amps, int n, int k, const FusedGeom& tg, const void* d_mat,
                       hipStream_t s) {
   using T = typename PrecTraits<P>::T;
-  const uint64_t ncols = uint64_t(1) << (n - k);
-  uint64_t g = (ncols + kCols - 1) / kCols;
+  const uint64_t npanels = uint64_t(1) << (n - k - tg.cb);
+  uint64_t g = npanels;
   // persistent grid: the resident workgroups of the kernel
   static std::mutex mu;
   static std::map<const void*, uint64_t> slots;
@@ -273,12 +309,12 @@ hipError_t dispatch_k(void* amps, int n, int k, const TileGeom& tg, const void* 
   auto* p = (cplx<T>*)amps;
   const T* A = (const T*)d_mat;
   switch (k) {
-    case 1: hipLaunchKernelGGL((k_fused<P, 2>), grid, block, 0, s, p, ncols, tg, A); break;
-    case 2: hipLaunchKernelGGL((k_fused<P, 4>), grid, block, 0, s, p, ncols, tg, A); break;
-    case 3: hipLaunchKernelGGL((k_fused<P, 8>), grid, block, 0, s, p, ncols, tg, A); break;
-    case 4: hipLaunchKernelGGL((k_fused<P, 16>), grid, block, 0, s, p, ncols, tg, A); break;
-    case 5: hipLaunchKernelGGL((k_fused<P, 32>), grid, block, 0, s, p, ncols, tg, A); break;
-    case 6: hipLaunchKernelGGL((k_fused<P, 64>), grid, block, 0, s, p, ncols, tg, A); break;
+    case 1: hipLaunchKernelGGL((k_fused<P, 2>), grid, block, 0, s, p, npanels, tg, A); break;
+    case 2: hipLaunchKernelGGL((k_fused<P, 4>), grid, block, 0, s, p, npanels, tg, A); break;
+    case 3: hipLaunchKernelGGL((k_fused<P, 8>), grid, block, 0, s, p, npanels, tg, A); break;
+    case 4: hipLaunchKernelGGL((k_fused<P, 16>), grid, block, 0, s, p, npanels, tg, A); break;
+    case 5: hipLaunchKernelGGL((k_fused<P, 32>), grid, block, 0, s, p, npanels, tg, A); break;
+    case 6: hipLaunchKernelGGL((k_fused<P, 64>), grid, block, 0, s, p, npanels, tg, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -290,23 +326,27 @@ hipError_t dispatch_k(void* amps, int n, int k, const TileGeom& tg, const void* 
 // in the precision of the mode (double for FP64, float otherwise).
 hipError_t launch_fused(juqcs_dtype dt, void* amps, int n, int k, const int* targets,
                         const void* d_mat, juqcs_mma mode, hipStream_t s) {
-  TileGeom tg{};
-  tg.n = n;
-  tg.H = k;
-  int sorted[6];
+  if (k < 1 || k > 6 || k > n) return hipErrorInvalidValue;
+  FusedGeom tg{};
+  tg.k = k;
+  uint64_t tmask = 0;
   for (int j = 0; j < k; ++j) {
-    tg.hbits[j] = targets[j];
-    sorted[j] = targets[j];
+    if (targets[j] < 0 || targets[j] >= n) return hipErrorInvalidValue;
+    tg.tbits[j] = targets[j];
+    tmask |= uint64_t(1) << targets[j];
   }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j + 1 < k - i; ++j)
-      if (sorted[j] > sorted[j + 1]) {
-        const int t = sorted[j];
-        sorted[j] = sorted[j + 1];
-        sorted[j + 1] = t;
-      }
-  if (2 * k > kHbitsCap) return hipErrorInvalidValue;
-  for (int j = 0; j < k; ++j) tg.hbits[k + j] = sorted[j];
+  // column bits: the lowest min(6, n - k) non-target bits; S: the span that
+  // holds them and the targets below them
+  tg.cb = n - k < 6 ? n - k : 6;
+  int S = 0, nc = 0;
+  while (nc < tg.cb) {
+    if (!((tmask >> S) & 1)) ++nc;
+    ++S;
+  }
+  tg.S = S;
+  tg.khi = 0;
+  for (int b = S; b < n; ++b)
+    if ((tmask >> b) & 1) tg.hts[tg.khi++] = b;
   if (dt == JUQCS_C128) {
     if (mode != JUQCS_MMA_FP64) return hipErrorInvalidValue;
     return dispatch_k<P_F64>(amps, n, k, tg, d_mat, s);

@@ -47,6 +47,11 @@ class PlanOpts(ct.Structure):
                 ("mma_flops", ct.c_double)]
 
 
+class TuneResult(ct.Structure):
+    _fields_ = [("opts", PlanOpts), ("ms", ct.c_double), ("default_ms", ct.c_double),
+                ("trials", ct.c_int32), ("pad", ct.c_int32), ("key", ct.c_uint64)]
+
+
 class BranchStats(ct.Structure):
     _fields_ = [("crossings", ct.c_int32), ("group_bits", ct.c_int32), ("groups", ct.c_int64),
                 ("tree_states", ct.c_int64), ("tile_passes", ct.c_int64), ("pass_bytes", ct.c_double),
@@ -78,6 +83,10 @@ _SIGS = {
     "juqcs_apply_2q": [_P, _I, _I, _DP],
     "juqcs_apply_fused_k": [_P, _I, ct.POINTER(_I), _DP, _I],
     "juqcs_run_circuit": [_P, _P, _S, ct.POINTER(PlanOpts)],
+    "juqcs_autotune": [_P, _P, _S, ct.POINTER(TuneResult)],
+    "juqcs_tune_save": [ct.c_char_p],
+    "juqcs_tune_load": [ct.c_char_p],
+    "juqcs_tune_clear": [],
     "juqcs_amplitudes": [_P, ct.POINTER(_U64), _S, _DP],
     "juqcs_amplitudes_device": [_P, _P, _S, _P],
     "juqcs_norm": [_P, _DP],
@@ -174,6 +183,21 @@ def juqcs_state_bytes(n: int, dtype: int, block_bits: int = 0):
     _check(_lib.juqcs_state_bytes(n, dtype, block_bits, ct.byref(a), ct.byref(s), ct.byref(w)),
            "juqcs_state_bytes")
     return a.value, s.value, w.value
+
+
+def juqcs_tune_save(path: str):
+    _check(_lib.juqcs_tune_save(os.fsencode(path)), "juqcs_tune_save")
+
+
+def juqcs_tune_load(path: str):
+    _check(_lib.juqcs_tune_load(os.fsencode(path)), "juqcs_tune_load")
+
+
+def juqcs_tune_clear():
+    _check(_lib.juqcs_tune_clear(), "juqcs_tune_clear")
+
+
+MODE_NAMES = {v: k for k, v in PLANS.items()}
 
 
 def juqcs_encode2(src, src_dtype: int, count: int, block_bits: int, codes, scales, stream=None):
@@ -383,6 +407,18 @@ class State:
         _check(_lib.juqcs_run_circuit(self.h, g.ctypes.data, g.size, ct.byref(o)),
                "juqcs_run_circuit")
         return o
+
+    def autotune(self, gates) -> dict:
+        """Timed trials of planner options for this circuit (juqcs_autotune);
+        later run(mode="auto") calls on circuits of the same structure use
+        the winner."""
+        g = _gates(gates)
+        r = TuneResult()
+        _check(_lib.juqcs_autotune(self.h, g.ctypes.data, g.size, ct.byref(r)), "juqcs_autotune")
+        o = r.opts
+        return {"mode": MODE_NAMES[o.mode], "fuse_k": o.fuse_k, "mma": o.mma, "tile_bits": o.tile_bits,
+                "low_bits": o.low_bits, "pass_gates": o.pass_gates, "relabel": o.relabel,
+                "ms": r.ms, "default_ms": r.default_ms, "trials": r.trials, "key": f"{r.key:016x}"}
 
     # read-out
     def amplitudes(self, idx) -> np.ndarray:

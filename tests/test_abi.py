@@ -171,3 +171,33 @@ def test_null_handle_and_codec_errors(J):
     assert lib.juqcs_decode2(16, 16, 8, 8, 16, 2, None) == J.ERR_DTYPE
     assert lib.juqcs_copy(16, 16, 15, None) == J.ERR_ARG
     assert lib.juqcs_copy(None, 16, 16, None) == J.ERR_ARG
+
+
+def test_tuning_table_round_trip(J, tmp_path):
+    # an empty table saves and loads; a written table is read back entry by
+    # entry; malformed files are rejected
+    J.juqcs_tune_clear()
+    p = tmp_path / "tune.json"
+    J.juqcs_tune_save(str(p))
+    J.juqcs_tune_load(str(p))
+    p.write_text('{"juqcs_tune": 1, "entries": [\n'
+                 ' {"key": "00000000000000ab", "n": 30, "dtype": 0, "mode": 2, "fuse_k": 5, "mma": 4, '
+                 '"tile_bits": 0, "low_bits": 0, "pass_gates": 0, "relabel": 0, "ms": 500.5, '
+                 '"default_ms": 600.25, "trials": 17}]}\n')
+    J.juqcs_tune_load(str(p))
+    q = tmp_path / "tune2.json"
+    J.juqcs_tune_save(str(q))
+    text = q.read_text()
+    assert '"key": "00000000000000ab"' in text and '"mode": 2' in text and '"fuse_k": 5' in text
+    assert '"ms": 500.500000' in text and '"trials": 17' in text
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": []}')
+    with pytest.raises(J.JuqcsError) as e:
+        J.juqcs_tune_load(str(bad))
+    assert e.value.status == J.ERR_ARG
+    bad.write_text('{"juqcs_tune": 1, "entries": [{"key": "1", "n": 3}]}')
+    with pytest.raises(J.JuqcsError):
+        J.juqcs_tune_load(str(bad))
+    with pytest.raises(J.JuqcsError):
+        J.juqcs_tune_load(str(tmp_path / "missing.json"))
+    J.juqcs_tune_clear()

@@ -371,6 +371,37 @@ def test_permute_and_canonicalize(J, dtype):
         assert_dtype(dtype, amps, phi[z.astype(np.int64)])
 
 
+# ---- autotuner ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c128", "c64", "enc2"])
+def test_autotune_picks_and_auto_mode_uses_it(J, dtype, tmp_path):
+    n = 16
+    announce("autotune", dtype)
+    circ = W.layered_brick(n, 8, seed=31)
+    other = W.layered_brick(n, 8, seed=32)          # same structure, other matrices
+    J.juqcs_tune_clear()
+    with J.State(n, dtype) as s:
+        t = s.autotune(circ)
+        assert t["mode"] in ("tile", "fused", "plain") and t["trials"] >= 8
+        assert t["ms"] <= t["default_ms"]
+        s.init(0)
+        s.run(other, mode="auto")
+        got = s.state_vector()
+        path = tmp_path / "tune.json"
+        J.juqcs_tune_save(str(path))
+        J.juqcs_tune_clear()
+        J.juqcs_tune_load(str(path))
+        s.init(0)
+        s.run(other, mode="auto")
+        got2 = s.state_vector()
+    J.juqcs_tune_clear()
+    phi = sv.run_circuit(n, other)
+    if dtype == "enc2":
+        assert rel_l2(got, phi) < 0.05 and rel_l2(got2, phi) < 0.05
+    else:
+        assert_dtype(dtype, got, phi)
+        assert np.array_equal(got, got2)
+
+
 # ---- global factor -------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64", "enc2"])
 def test_global_factor(J, dtype):
