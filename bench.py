@@ -109,6 +109,7 @@ def cpu_baseline(n, gates, budget_s):
 
 
 TILE_SOURCES = ("k_tile.hip", "tile_ops.hpp", "juqcs_internal.hpp")
+TUNING_RECORD = os.path.join(ROOT, "paper_1912_03243_amd", "tuning_mi355x.json")
 
 
 def sources_sha256(names):
@@ -157,9 +158,11 @@ def main():
                     help="grid42: crossing CZs kept (S of the decomposition, 2^S branches)")
     ap.add_argument("--group", type=int, default=0,
                     help="grid48, ghz128: branches resident at a time (0 = automatic)")
-    ap.add_argument("--autotune", type=int, default=1,
-                    help="brick30: pick the planner options by timed trials first (then mode auto); "
-                         "batch4096: timed-trial in-pass fusion width, compared with the cost model")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="brick30: pick the planner options by timed trials first (then mode auto; "
+                         "without it the stored tuning record is used); batch4096: timed-trial "
+                         "in-pass fusion width, compared with the cost model")
+    ap.add_argument("--tune-out", default=None, help="brick30 --autotune 1: save the tuning table here")
     ap.add_argument("--tile-fuse", type=int, default=0, help="in-pass fusion width (0 = default)")
     ap.add_argument("--tile-bits", type=int, default=0, help="tile bits (0 = default)")
     ap.add_argument("--low-bits", type=int, default=0, help="contiguous low tile bits (0 = default)")
@@ -204,11 +207,22 @@ def main():
     st = juqcs.State(n, "c128", device=dev, stream=stream)
     tune = None
     run_mode = args.mode
-    if args.autotune and args.mode == "tile":
-        t0 = time.perf_counter()
-        tune = st.autotune(gates)
-        tune["wall_s"] = time.perf_counter() - t0
-        run_mode = "auto"
+    if args.mode == "tile":
+        if args.autotune:
+            t0 = time.perf_counter()
+            tune = st.autotune(gates)
+            tune["wall_s"] = time.perf_counter() - t0
+            tune["source"] = "timed trials in this run"
+            if args.tune_out:
+                juqcs.juqcs_tune_save(args.tune_out)
+        elif os.path.exists(TUNING_RECORD):
+            # the record written by an earlier --autotune 1 run on MI355X
+            juqcs.juqcs_tune_load(TUNING_RECORD)
+            tune = st.tuned(gates)
+            if tune is not None:
+                tune["source"] = os.path.relpath(TUNING_RECORD, ROOT)
+        if tune is not None:
+            run_mode = "auto"
         log(f"autotune: {tune}")
 
     def step(mode, profile):

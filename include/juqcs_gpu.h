@@ -234,9 +234,11 @@ typedef struct {
 
 /* Picks planner options for this circuit on this state by timed trials:
  * from the defaults, one parameter at a time (tile low bits, tile bits,
- * in-pass fusion width, gates per pass, relabeling), keeping the fastest
- * value of each, then dense fused blocks of k = 3..6 (FP64 for C128, FP32
- * for C64), and one pass per gate for small states.  Every trial starts
+ * in-pass fusion width, gates per pass, relabeling), keeping a value when
+ * it is more than 2% faster than the best so far, then dense fused blocks
+ * of k = 3..6 (FP64 for C128, FP32 for C64), and one pass per gate for
+ * small states; a choice other than the defaults is kept only if the
+ * median of three runs beats theirs by 1%.  Every trial starts
  * from |0...0> on st's buffers (the state is left as the last trial made
  * it).  The fastest options are stored in the library's tuning table under
  * the circuit's structure key (n, amplitude type, ENC2 block bits, every
@@ -250,6 +252,10 @@ juqcs_status juqcs_autotune(juqcs_state* st, const juqcs_gate* gates, size_t cou
  * replaces entries.  clear empties the table.  Errors: ARG (null path,
  * unreadable or malformed file). */
 juqcs_status juqcs_tune_save(const char* path);
+/* The stored entry for this circuit's structure on st (JUQCS_ERR_ARG if
+ * there is none). */
+juqcs_status juqcs_tune_lookup(const juqcs_state* st, const juqcs_gate* gates, size_t count,
+                               juqcs_tune_result* out);
 juqcs_status juqcs_tune_load(const char* path);
 juqcs_status juqcs_tune_clear(void);
 

@@ -87,6 +87,7 @@ _SIGS = {
     "juqcs_tune_save": [ct.c_char_p],
     "juqcs_tune_load": [ct.c_char_p],
     "juqcs_tune_clear": [],
+    "juqcs_tune_lookup": [_P, _P, _S, ct.POINTER(TuneResult)],
     "juqcs_amplitudes": [_P, ct.POINTER(_U64), _S, _DP],
     "juqcs_amplitudes_device": [_P, _P, _S, _P],
     "juqcs_norm": [_P, _DP],
@@ -415,6 +416,18 @@ class State:
         g = _gates(gates)
         r = TuneResult()
         _check(_lib.juqcs_autotune(self.h, g.ctypes.data, g.size, ct.byref(r)), "juqcs_autotune")
+        return self._tune_dict(r)
+
+    def tuned(self, gates):
+        """The tuning table's entry for this circuit's structure, or None."""
+        g = _gates(gates)
+        r = TuneResult()
+        if _lib.juqcs_tune_lookup(self.h, g.ctypes.data, g.size, ct.byref(r)) != OK:
+            return None
+        return self._tune_dict(r)
+
+    @staticmethod
+    def _tune_dict(r):
         o = r.opts
         return {"mode": MODE_NAMES[o.mode], "fuse_k": o.fuse_k, "mma": o.mma, "tile_bits": o.tile_bits,
                 "low_bits": o.low_bits, "pass_gates": o.pass_gates, "relabel": o.relabel,

@@ -64,24 +64,27 @@ def test_plain_random_circuit(J, dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_every_target_and_control_bit(J, dtype):
-    n = 12
+@pytest.mark.parametrize("n", [12, 22])
+def test_every_target_and_control_bit(J, dtype, n):
+    # every target bit with a control below and above the run width of the
+    # per-gate kernels (64 C128 / 128 C64 amplitudes) at n = 22, whose runs
+    # split into low bits (partners across lanes) and high bits (pairs of runs)
     rng = np.random.default_rng(7)
     prefix = W.layered_brick(n, 1, seed=3)
+    base = sv.run_circuit(n, prefix, basis_index=3)
     for t in range(n):
         other = int((t + 1 + rng.integers(0, n - 1)) % n)
-        recs = [prefix,
-                W.gate(W.OP_U, t, u=random_unitary(1, t)),
+        recs = [W.gate(W.OP_U, t, u=random_unitary(1, t)),
                 W.gate(W.OP_CNOT, t, other), W.gate(W.OP_CNOT, other, t),
                 W.gate(W.OP_CZ, t, other), W.gate(W.OP_CP, other, t, theta=0.3 + t),
                 W.gate(W.OP_T, t), W.gate(W.OP_Y, t), W.gate(W.OP_H, t)]
         circ = W.concat(*recs)
-        announce("target", dtype, t, other)
+        announce("target", dtype, n, t, other)
         with J.State(n, dtype) as s:
             s.init(3)
-            s.run(circ, mode="plain")
+            s.run(W.concat(prefix, circ), mode="plain")
             got = s.state_vector()
-        assert_dtype(dtype, got, sv.run_circuit(n, circ, basis_index=3))
+        assert_dtype(dtype, got, sv.run_circuit(n, circ, psi=base.copy()))
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
