@@ -525,9 +525,9 @@ hipError_t do_1q(void* amps, int n, int t, int c, const cplx<double> u[4], hipSt
   const uint64_t cm = c >= 0 ? uint64_t(1) << c : 0;
   RunArgs ra;
   if (run_args<T>(n, t >= RB ? t : -1, cm, &ra)) {
-    if (t >= RB) return launch_runs<T, RUN_HIGH, 2>(amps, ra, to_mat2<T>(u), cplx<T>{}, s);
+    if (t >= RB) return launch_runs<T, RUN_HIGH, 1>(amps, ra, to_mat2<T>(u), cplx<T>{}, s);
     ra.t = t;
-    return launch_runs<T, RUN_LOW, 4>(amps, ra, to_mat2<T>(u), cplx<T>{}, s);
+    return launch_runs<T, RUN_LOW, 2>(amps, ra, to_mat2<T>(u), cplx<T>{}, s);
   }
   constexpr int U = 4;
   const uint64_t npairs = uint64_t(1) << (n - 1 - (c >= 0 ? 1 : 0));
@@ -547,7 +547,7 @@ template <typename T>
 hipError_t do_diag(void* amps, int n, uint64_t mask, cplx<double> ph, hipStream_t s) {
   RunArgs ra;
   if (run_args<T>(n, -1, mask, &ra))
-    return launch_runs<T, RUN_DIAG, 4>(amps, ra, Mat2<T>{}, cplx<T>{(T)ph.re, (T)ph.im}, s);
+    return launch_runs<T, RUN_DIAG, 2>(amps, ra, Mat2<T>{}, cplx<T>{(T)ph.re, (T)ph.im}, s);
   constexpr int U = 4;
   int z[2] = {-1, -1}, nb = 0;
   for (int q = 0; q < 64 && nb < 2; ++q)
@@ -681,7 +681,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const uint64_t count = bytes / 16;
   if (dst == src) {
-    constexpr int U = 4;
+    constexpr int U = 2;
     const uint64_t waves = (count + 64 * U - 1) / (64 * U);
     hipLaunchKernelGGL((k_stream<U>), dim3(grid_for(waves, kThreads / 64)), dim3(kThreads), 0, s,
                        (uint4*)dst, count);
