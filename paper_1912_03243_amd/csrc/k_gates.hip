@@ -136,8 +136,11 @@ __global__ __launch_bounds__(kThreads) void k_runs(cplx<T>* __restrict__ psi, Ru
   constexpr int APL = sizeof(W) / sizeof(cplx<T>);  // amplitudes per lane: 1 or 2
   W* g = reinterpret_cast<W*>(psi);
   const int lane = threadIdx.x & 63;
-  const uint64_t wave = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   constexpr int NL = MODE == RUN_HIGH ? 2 * U : U;  // 16-byte words per lane
+  const uint64_t nwaves = (ra.nruns + U - 1) / U;
+  // grid-stride over waves: a launch stays below 2^32 work-items at any n
+  for (uint64_t wave = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); wave < nwaves;
+       wave += (uint64_t)gridDim.x * (kThreads / 64)) {
   W v[NL];
   uint64_t at[NL];
   bool ok[U];
@@ -213,6 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_runs(cplx<T>* __restrict__ psi, Ru
       if (ok[k]) st_stream(&g[at[k]], w);
     }
   }
+  }
 }
 
 // --------------------------------------------------------------- diag ----
@@ -246,22 +250,24 @@ template <typename T, int U>
 __global__ __launch_bounds__(kThreads) void k_2q(cplx<T>* __restrict__ psi, uint64_t nquads,
                                                  int z0, int z1, uint64_t b0, uint64_t b1,
                                                  Mat4<T> m) {
-  const uint64_t base = (uint64_t)blockIdx.x * (kThreads * U) + threadIdx.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * (kThreads * U) + threadIdx.x; base < nquads;
+       base += (uint64_t)gridDim.x * (kThreads * U)) {
 #pragma unroll
-  for (int k = 0; k < U; ++k) {
-    const uint64_t p = base + (uint64_t)k * kThreads;
-    if (p >= nquads) continue;
-    const uint64_t i = insert_zero(insert_zero(p, z0), z1);
-    const uint64_t idx[4] = {i, i | b0, i | b1, i | b0 | b1};
-    cplx<T> v[4];
+    for (int k = 0; k < U; ++k) {
+      const uint64_t p = base + (uint64_t)k * kThreads;
+      if (p >= nquads) continue;
+      const uint64_t i = insert_zero(insert_zero(p, z0), z1);
+      const uint64_t idx[4] = {i, i | b0, i | b1, i | b0 | b1};
+      cplx<T> v[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = ld_amp(&psi[idx[r]]);
+      for (int r = 0; r < 4; ++r) v[r] = ld_amp(&psi[idx[r]]);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      cplx<T> acc = cmul(m.m[4 * r], v[0]);
+      for (int r = 0; r < 4; ++r) {
+        cplx<T> acc = cmul(m.m[4 * r], v[0]);
 #pragma unroll
-      for (int c = 1; c < 4; ++c) acc = cmad(m.m[4 * r + c], v[c], acc);
-      st_amp(&psi[idx[r]], acc);
+        for (int c = 1; c < 4; ++c) acc = cmad(m.m[4 * r + c], v[c], acc);
+        st_amp(&psi[idx[r]], acc);
+      }
     }
   }
 }
@@ -352,15 +358,16 @@ __global__ __launch_bounds__(kThreads) void k_gather(const cplx<T>* __restrict__
                                                      const uint64_t* __restrict__ idx,
                                                      uint64_t count, PhysMap pm, cplx<double> g,
                                                      double* __restrict__ out) {
-  const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (k >= count) return;
-  const uint64_t z = idx[k];
-  if ((z >> n) != 0) {  // index outside the state: NaN, no access
-    out[2 * k] = out[2 * k + 1] = __builtin_nan("");
-    return;
+  for (uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x; k < count;
+       k += (uint64_t)gridDim.x * kThreads) {
+    const uint64_t z = idx[k];
+    if ((z >> n) != 0) {  // index outside the state: NaN, no access
+      out[2 * k] = out[2 * k + 1] = __builtin_nan("");
+      continue;
+    }
+    const cplx<T> v = psi[to_phys(z, n, pm)];
+    put_amp(out, k, (double)v.re, (double)v.im, g);
   }
-  const cplx<T> v = psi[to_phys(z, n, pm)];
-  put_amp(out, k, (double)v.re, (double)v.im, g);
 }
 
 __global__ __launch_bounds__(kThreads) void k_gather_enc2(const char2* __restrict__ codes,
@@ -370,16 +377,17 @@ __global__ __launch_bounds__(kThreads) void k_gather_enc2(const char2* __restric
                                                           uint64_t count, PhysMap pm,
                                                           cplx<double> g,
                                                           double* __restrict__ out) {
-  const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (k >= count) return;
-  if ((idx[k] >> n) != 0) {
-    out[2 * k] = out[2 * k + 1] = __builtin_nan("");
-    return;
+  for (uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x; k < count;
+       k += (uint64_t)gridDim.x * kThreads) {
+    if ((idx[k] >> n) != 0) {
+      out[2 * k] = out[2 * k + 1] = __builtin_nan("");
+      continue;
+    }
+    const uint64_t i = to_phys(idx[k], n, pm);
+    const char2 q = codes[i];
+    const float d = scales[i >> block_bits] / 127.0f;
+    put_amp(out, k, (double)((float)q.x * d), (double)((float)q.y * d), g);
   }
-  const uint64_t i = to_phys(idx[k], n, pm);
-  const char2 q = codes[i];
-  const float d = scales[i >> block_bits] / 127.0f;
-  put_amp(out, k, (double)((float)q.x * d), (double)((float)q.y * d), g);
 }
 
 // --------------------------------------------------------------- scale ----
@@ -418,19 +426,21 @@ __global__ __launch_bounds__(kThreads) void k_copy(uint4* __restrict__ dst,
                                                    uint64_t count) {
   typedef uint32_t v4u __attribute__((ext_vector_type(4)));
   constexpr int U = 4;
-  const uint64_t base = (uint64_t)blockIdx.x * (kThreads * U) + threadIdx.x;
   const v4u* s4 = reinterpret_cast<const v4u*>(src);
   v4u* d4 = reinterpret_cast<v4u*>(dst);
-  v4u v[U];
+  for (uint64_t base = (uint64_t)blockIdx.x * (kThreads * U) + threadIdx.x; base < count;
+       base += (uint64_t)gridDim.x * (kThreads * U)) {
+    v4u v[U];
 #pragma unroll
-  for (int k = 0; k < U; ++k) {
-    const uint64_t i = base + (uint64_t)k * kThreads;
-    if (i < count) v[k] = ld_stream(&s4[i]);
-  }
+    for (int k = 0; k < U; ++k) {
+      const uint64_t i = base + (uint64_t)k * kThreads;
+      if (i < count) v[k] = ld_stream(&s4[i]);
+    }
 #pragma unroll
-  for (int k = 0; k < U; ++k) {
-    const uint64_t i = base + (uint64_t)k * kThreads;
-    if (i < count) st_stream(&d4[i], v[k]);
+    for (int k = 0; k < U; ++k) {
+      const uint64_t i = base + (uint64_t)k * kThreads;
+      if (i < count) st_stream(&d4[i], v[k]);
+    }
   }
 }
 
@@ -441,18 +451,21 @@ template <int U>
 __global__ __launch_bounds__(kThreads) void k_stream(uint4* __restrict__ p, uint64_t count) {
   typedef uint32_t v4u __attribute__((ext_vector_type(4)));
   v4u* q = reinterpret_cast<v4u*>(p);
-  const uint64_t wave = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  v4u v[U];
+  const uint64_t nwaves = (count + 64 * U - 1) / (64 * U);
+  for (uint64_t wave = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); wave < nwaves;
+       wave += (uint64_t)gridDim.x * (kThreads / 64)) {
+    v4u v[U];
 #pragma unroll
-  for (int k = 0; k < U; ++k) {
-    const uint64_t i = (wave * U + k) * 64 + lane;
-    if (i < count) v[k] = ld_stream(&q[i]);
-  }
+    for (int k = 0; k < U; ++k) {
+      const uint64_t i = (wave * U + k) * 64 + lane;
+      if (i < count) v[k] = ld_stream(&q[i]);
+    }
 #pragma unroll
-  for (int k = 0; k < U; ++k) {
-    const uint64_t i = (wave * U + k) * 64 + lane;
-    if (i < count) st_stream(&q[i], v[k]);
+    for (int k = 0; k < U; ++k) {
+      const uint64_t i = (wave * U + k) * 64 + lane;
+      if (i < count) st_stream(&q[i], v[k]);
+    }
   }
 }
 
@@ -511,10 +524,18 @@ bool run_args(int n, int t_high, uint64_t set_mask, RunArgs* ra) {
   return true;
 }
 
+// Blocks of a grid-stride launch: every block of the work, at most
+// kMaxBlocks (2^24 work-items, far beyond the resident blocks of 256 CUs).
+constexpr uint64_t kMaxBlocks = uint64_t(1) << 16;
+inline unsigned capped_grid(uint64_t work, uint64_t per_block) {
+  const uint64_t g = grid_for(work, per_block);
+  return (unsigned)(g < kMaxBlocks ? g : kMaxBlocks);
+}
+
 template <typename T, int MODE, int U>
 hipError_t launch_runs(void* amps, const RunArgs& ra, const Mat2<T>& u, cplx<T> ph, hipStream_t s) {
   const uint64_t waves = (ra.nruns + U - 1) / U;
-  hipLaunchKernelGGL((k_runs<T, MODE, U>), dim3(grid_for(waves, kThreads / 64)), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL((k_runs<T, MODE, U>), dim3(capped_grid(waves, kThreads / 64)), dim3(kThreads), 0, s,
                      (cplx<T>*)amps, ra, u, ph);
   return hipGetLastError();
 }
@@ -564,7 +585,7 @@ hipError_t do_2q(void* amps, int n, int q0, int q1, const cplx<double> m[16], hi
   constexpr int U = 2;
   const uint64_t nq = uint64_t(1) << (n - 2);
   const int z0 = q0 < q1 ? q0 : q1, z1 = q0 < q1 ? q1 : q0;
-  hipLaunchKernelGGL((k_2q<T, U>), dim3(grid_for(nq, kThreads * U)), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL((k_2q<T, U>), dim3(capped_grid(nq, kThreads * U)), dim3(kThreads), 0, s,
                      (cplx<T>*)amps, nq, z0, z1, uint64_t(1) << q0, uint64_t(1) << q1,
                      to_mat4<T>(m));
   return hipGetLastError();
@@ -641,7 +662,7 @@ hipError_t launch_gather(juqcs_dtype dt, const void* amps, const void* scales, i
   for (int q = 0; q < 64; ++q) pm.p[q] = (int8_t)(q < n ? phys[q] : q);
   for (int q = 0; q < n; ++q)
     if (phys[q] != q) pm.identity = 0;
-  const dim3 grid(grid_for(count, kThreads));
+  const dim3 grid(capped_grid(count, kThreads));
   if (dt == JUQCS_C128)
     hipLaunchKernelGGL(k_gather<double>, grid, dim3(kThreads), 0, s, (const cplx<double>*)amps, n,
                        idx, count, pm, g, out);
@@ -683,11 +704,11 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
   if (dst == src) {
     constexpr int U = 2;
     const uint64_t waves = (count + 64 * U - 1) / (64 * U);
-    hipLaunchKernelGGL((k_stream<U>), dim3(grid_for(waves, kThreads / 64)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_stream<U>), dim3(capped_grid(waves, kThreads / 64)), dim3(kThreads), 0, s,
                        (uint4*)dst, count);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_copy, dim3(grid_for(count, kThreads * 4)), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL(k_copy, dim3(capped_grid(count, kThreads * 4)), dim3(kThreads), 0, s,
                      (uint4*)dst, (const uint4*)src, count);
   return hipGetLastError();
 }

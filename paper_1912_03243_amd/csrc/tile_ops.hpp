@@ -186,15 +186,14 @@ struct Var {
 
 // Per-lane tables of one FP32 matrix-core 8x8 op on a tile of 16 NBLK groups:
 // what the op's lanes would otherwise recompute from the op's bits for every
-// tile (sorting, bit spreading, swizzling, operand selection).  Built once
-// per pass; all offsets are tile-local and fit 16 bits (tiles of at most
-// 2^14 amplitudes).
+// tile (sorting, bit spreading, lane swaps, swizzling, operand selection).
+// Built once per pass; all offsets are tile-local and fit 16 bits (tiles of
+// at most 2^14 amplitudes).
 template <int NBLK>
 struct alignas(16) MmaTab {
-  float a[64][4];      // A operand of lane l for the steps j = 0..3
-  uint16_t rd[64][4];  // real-part index 2 lds(e) + p of the lane's reads (block part excluded)
-  uint16_t wr[64][2];  // lds slots of the lane's two written amplitudes (block part excluded)
-  uint16_t ub[NBLK];   // lds slot of each 16-group block's first group
+  float a[64][4];       // A operand of lane l for the steps j = 0..3
+  uint16_t off[64][2];  // lds slots of the lane's two amplitudes (block part excluded)
+  uint16_t ub[NBLK];    // block part of the slots of each block of 16 groups
 };
 
 // Uniform parameters of one in-tile op of a pass, built once per launch (the
@@ -518,67 +517,76 @@ struct Fixed {
   }
 
   // 8x8 on three local bits, on the matrix cores (FP32).  The complex product
-  // is the real 16x16 product y = R x over rows and columns 2r + p (p = 0:
-  // real, p = 1: imaginary part of amplitude r of a group), with
-  //   R[2r][2s] = R[2r+1][2s+1] = Re m_rs,  R[2r][2s+1] = -Im m_rs,
-  //   R[2r+1][2s] = Im m_rs.
-  // A wave takes 16 groups at a time as the 16 columns of x; lane 16 q + c
-  // feeds column c.  Four 16x16x4 steps j cover the rows 4j..4j+3 of x: the
-  // lane supplies R[c][4j + q] (A) and x[4j + q][c] (B), i.e. part q & 1 of
-  // amplitude 2j + (q >> 1), and receives rows 4q..4q+3 (amplitudes 2q and
-  // 2q+1 whole).  Groups are disjoint across waves and a wave reads all of
-  // a block before it writes it, so no barrier is needed inside the op.
-  __device__ static void dense3_mma(cplx<T>* sh, const int32_t* bits, const cplx<T>* m, int tid) {
+  // is a real 16x16 product over the 16 components (Re, Im of the 8
+  // amplitudes) of a group; a wave takes 16 groups at a time as the 16
+  // columns.  Lane 16 q + c (c: column) reads amplitudes q and q + 4 of its
+  // group (8 bytes each) and feeds, in the four 16x16x4 steps j, Re a_q,
+  // Im a_q, Re a_(q+4), Im a_(q+4) as K slot q.  The output rows are ordered
+  // so that the lane receives exactly what it read: rows 4 q .. 4 q + 3 hold
+  // Re a_q, Im a_q, Re a_(q+4), Im a_(q+4), written back in place (groups
+  // are disjoint across waves and a wave reads a block before it writes it:
+  // no barrier inside the op).  A (row rho, K slot q of step j) is the
+  // real-embedding entry of output component (amplitude rho/4 + 4 (rho%4 >= 2),
+  // part rho%2) and input component (amplitude q + 4 (j >= 2), part j%2).
+  // The 16 columns of block b are the groups lane_swap(16 b + c): the op's
+  // lane swaps put the 16 lanes of an 8-byte LDS access phase on distinct
+  // bank slots.
+  __device__ static T mma_a(const cplx<T>* m, int lane, int j) {
+    const int c = lane & 15, q = lane >> 4;
+    const int r = (c >> 2) + 4 * ((c & 3) >> 1), p = c & 1;
+    const int sc = q + 4 * (j >> 1), pp = j & 1;
+    const cplx<T> z = m[8 * r + sc];
+    return p == pp ? z.re : (p ? z.im : -z.im);
+  }
+
+  __device__ static void dense3_mma(cplx<T>* sh, const OpPre& q, const cplx<T>* m, int tid) {
     static_assert(sizeof(T) == 4, "FP32 matrix-core op");
     constexpr int ITEMS = NA / 8, NBLK = ITEMS / 16, W = NT / 64, CB = (int)sizeof(cplx<T>);
     static_assert(ITEMS % 16 == 0 && NBLK % W == 0, "whole 16-group blocks per wave");
-    int bt[3], sorted[3];
-    sort_bits<3>(bits, bt, sorted);
-    const int lane = tid & 63, c = lane & 15, q = lane >> 4, h = q >> 1, pp = q & 1;
+    int pos[3];
+    unpack<3>(q.pos, pos);
+    const int lane = tid & 63, c = lane & 15, qq = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int r = c >> 1, p = c & 1;
     T a[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const cplx<T> z = m[8 * r + 2 * j + h];
-      a[j] = p == pp ? z.re : (p ? z.im : -z.im);
-    }
-    // per-lane byte offsets: reads (part pp of amplitude 2j + h of group c)
-    // and writes (amplitudes 2q, 2q + 1 of group c)
-    const int lc = spread<3>(c, sorted);
-    int rd[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) rd[j] = lds<T>(lc | row_offset<3>(2 * j + h, bt)) * CB + pp * (int)sizeof(T);
-    const int w0 = lds<T>(lc | row_offset<3>(2 * q, bt)) * CB;
-    const int w1 = lds<T>(lc | row_offset<3>(2 * q + 1, bt)) * CB;
+    for (int j = 0; j < 4; ++j) a[j] = mma_a(m, lane, j);
+    const int lc = lds<T>(spread<3>(lane_swap(c, q.lsw), pos)) * CB;
+    const int o0 = lc ^ q.row[qq], o1 = lc ^ q.row[qq + 4];
     char* base = reinterpret_cast<char*>(sh);
-    // two blocks per step: all reads, then two independent MFMA chains, then
-    // all writes (measured faster than four per step)
     constexpr int NB = NBLK / W >= 2 ? 2 : 1;
 #pragma unroll
     for (int i0 = 0; i0 < NBLK / W; i0 += NB) {
       int ub[NB];  // block parts (wave-uniform)
-      T x[NB][4];
+      cplx<T> x0[NB], x1[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        ub[u] = lds<T>(spread<3>(((i0 + u) * W + wave) * 16, sorted)) * CB;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[u][j] = *reinterpret_cast<const T*>(base + (ub[u] ^ rd[j]));
+        ub[u] = lds<T>(spread<3>(lane_swap(((i0 + u) * W + wave) * 16, q.lsw), pos)) * CB;
+        x0[u] = *reinterpret_cast<const cplx<T>*>(base + (ub[u] ^ o0));
+        x1[u] = *reinterpret_cast<const cplx<T>*>(base + (ub[u] ^ o1));
       }
-      typedef float v4f __attribute__((ext_vector_type(4)));
-      v4f acc[NB];
+      mma_block<NB>(a, x0, x1, base, ub, o0, o1);
+    }
+  }
+
+  // Four 16x16x4 steps for NB blocks, then the write-back in place.
+  template <int NB>
+  __device__ static void mma_block(const T* a, const cplx<T>* x0, const cplx<T>* x1, char* base,
+                                   const int* ub, int o0, int o1) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f acc[NB];
 #pragma unroll
-      for (int u = 0; u < NB; ++u) acc[u] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int u = 0; u < NB; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], x0[u].re, v4f{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+    for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], x0[u].im, acc[u], 0, 0, 0);
 #pragma unroll
-        for (int u = 0; u < NB; ++u)
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[u][j], acc[u], 0, 0, 0);
+    for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], x1[u].re, acc[u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < NB; ++u) {
-        *reinterpret_cast<cplx<T>*>(base + (ub[u] ^ w0)) = cplx<T>{acc[u][0], acc[u][1]};
-        *reinterpret_cast<cplx<T>*>(base + (ub[u] ^ w1)) = cplx<T>{acc[u][2], acc[u][3]};
-      }
+    for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], x1[u].im, acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      *reinterpret_cast<cplx<T>*>(base + (ub[u] ^ o0)) = cplx<T>{acc[u][0], acc[u][1]};
+      *reinterpret_cast<cplx<T>*>(base + (ub[u] ^ o1)) = cplx<T>{acc[u][2], acc[u][3]};
     }
   }
 
@@ -596,21 +604,18 @@ struct Fixed {
       Tab& t = tabs[k++];
       int bt[3], sorted[3];
       sort_bits<3>(op.bits, bt, sorted);
+      const int lsw = lane_swaps(3, sorted[0], sorted[1], sorted[2]);
       const cplx<T>* m = mats + op.moff;
       for (int i = threadIdx.x; i < 64 + kBlocks; i += NT) {
         if (i < 64) {
-          const int c = i & 15, q = i >> 4, h = q >> 1, pp = q & 1, r = c >> 1, p = c & 1;
-          const int lc = spread<3>(c, sorted);
+          const int c = i & 15, q = i >> 4;
+          const int lc = lds<T>(spread<3>(lane_swap(c, lsw), sorted));
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const cplx<T> z = m[8 * r + 2 * j + h];
-            t.a[i][j] = p == pp ? z.re : (p ? z.im : -z.im);
-            t.rd[i][j] = (uint16_t)(2 * lds<T>(lc | row_offset<3>(2 * j + h, bt)) + pp);
-          }
-          t.wr[i][0] = (uint16_t)lds<T>(lc | row_offset<3>(2 * q, bt));
-          t.wr[i][1] = (uint16_t)lds<T>(lc | row_offset<3>(2 * q + 1, bt));
+          for (int j = 0; j < 4; ++j) t.a[i][j] = mma_a(m, i, j);
+          t.off[i][0] = (uint16_t)(lc ^ lds<T>(row_offset<3>(q, bt)));
+          t.off[i][1] = (uint16_t)(lc ^ lds<T>(row_offset<3>(q + 4, bt)));
         } else {
-          t.ub[i - 64] = (uint16_t)lds<T>(spread<3>((i - 64) * 16, sorted));
+          t.ub[i - 64] = (uint16_t)lds<T>(spread<3>(lane_swap((i - 64) * 16, lsw), sorted));
         }
       }
     }
@@ -619,41 +624,27 @@ struct Fixed {
   // The 8x8 matrix-core op from its tables (same data layout as dense3_mma).
   __device__ static void dense3_tab(cplx<T>* sh, const Tab& t, int tid) {
     static_assert(sizeof(T) == 4, "FP32 matrix-core op");
-    constexpr int W = NT / 64, PER_W = kBlocks / W;
+    constexpr int W = NT / 64, PER_W = kBlocks / W, CB = (int)sizeof(cplx<T>);
     static_assert(kBlocks % W == 0, "whole 16-group blocks per wave");
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     typedef float v4f __attribute__((ext_vector_type(4)));
-    const v4f a = *reinterpret_cast<const v4f*>(t.a[lane]);
-    int rd[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) rd[j] = t.rd[lane][j];
-    const int w0 = t.wr[lane][0], w1 = t.wr[lane][1];
-    float* f = reinterpret_cast<float*>(sh);
+    const v4f av = *reinterpret_cast<const v4f*>(t.a[lane]);
+    const T a[4] = {av[0], av[1], av[2], av[3]};
+    const int o0 = t.off[lane][0] * CB, o1 = t.off[lane][1] * CB;
+    char* base = reinterpret_cast<char*>(sh);
     constexpr int NB = PER_W >= 2 ? 2 : 1;
 #pragma unroll
     for (int i0 = 0; i0 < PER_W; i0 += NB) {
       int ub[NB];
-      float x[NB][4];
+      cplx<T> x0[NB], x1[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        ub[u] = t.ub[(i0 + u) * W + wave];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[u][j] = f[(2 * ub[u]) ^ rd[j]];
+        ub[u] = t.ub[(i0 + u) * W + wave] * CB;
+        x0[u] = *reinterpret_cast<const cplx<T>*>(base + (ub[u] ^ o0));
+        x1[u] = *reinterpret_cast<const cplx<T>*>(base + (ub[u] ^ o1));
       }
-      v4f acc[NB];
-#pragma unroll
-      for (int u = 0; u < NB; ++u) acc[u] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int u = 0; u < NB; ++u)
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[u][j], acc[u], 0, 0, 0);
-#pragma unroll
-      for (int u = 0; u < NB; ++u) {
-        sh[ub[u] ^ w0] = cplx<T>{acc[u][0], acc[u][1]};
-        sh[ub[u] ^ w1] = cplx<T>{acc[u][2], acc[u][3]};
-      }
+      mma_block<NB>(a, x0, x1, base, ub, o0, o1);
     }
   }
 
@@ -690,7 +681,7 @@ struct Fixed {
       } else {  // 8x8 (callers route passes with 4-qubit ops elsewhere)
         if constexpr (MODE == D3_VALU) dense3_valu(sh, q, m, tid);
         else if constexpr (MODE == D3_TAB) dense3_tab(sh, reinterpret_cast<const Tab*>(aux)[k3++], tid);
-        else dense3_mma(sh, op.bits, reinterpret_cast<const cplx<T>*>(aux) + (op.moff - mbase), tid);
+        else dense3_mma(sh, q, reinterpret_cast<const cplx<T>*>(aux) + (op.moff - mbase), tid);
       }
       __syncthreads();
     }

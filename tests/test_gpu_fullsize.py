@@ -92,6 +92,47 @@ def test_ghz30_closed_form(J):
     assert np.max(np.abs(q - 0.5)) < 1e-15
 
 
+def test_plain_passes_beyond_2_32_work_items(J):
+    # n = 33 complex128 (128 GiB): per-gate passes, a general 4x4 and the
+    # in-place stream launch more than 2^32 work-items' worth of runs, so
+    # their grids stride; GHZ and a 4x4 on qubits (0, 32) have closed forms
+    n = 33
+    announce("plain n=33 c128")
+    rng = np.random.default_rng(33)
+    z = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    m4, _ = np.linalg.qr(z)
+    with J.State(n, "c128") as s:
+        s.init(0)
+        s.run(W.ghz(n), mode="plain")
+        J.juqcs_copy(s.amps, s.amps, s.amps.numel())     # in place: unchanged
+        s.apply_2q(0, 32, m4)
+        ones = (1 << n) - 1
+        idx = [0, 1, 1 << 32, 1 | (1 << 32), ones ^ 1 ^ (1 << 32), ones ^ (1 << 32), ones ^ 1, ones, 2, 12345 << 3]
+        a = s.amplitudes(np.array(idx, dtype=np.uint64))
+    r = 1.0 / math.sqrt(2.0)
+    # index r4 = b_0 + 2 b_32 of the 4x4; the middle bits are all 0 or all 1
+    want = [r * m4[k, 0] for k in range(4)] + [r * m4[k, 3] for k in range(4)] + [0, 0]
+    assert np.max(np.abs(a - np.array(want))) < 1e-14
+
+
+def test_amplitudes_device_many_indices(J):
+    # more indices than one grid covers (2^24 per launch): the gather strides
+    import torch
+    n = 25
+    announce("gather 2^25")
+    circ = W.layered_brick(n, 2, seed=41)
+    with J.State(n, "c64") as s:
+        s.init(0)
+        s.run(circ, mode="tile")
+        full = s.state_vector()                        # chunks of 2^22
+        idx = torch.arange(1 << n, dtype=torch.int64, device="cuda").flip(0).contiguous()
+        out = torch.empty(2 << n, dtype=torch.float64, device="cuda")
+        s.amplitudes_device(idx, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.complex128)
+    assert np.array_equal(got, full[::-1])
+
+
 @pytest.mark.parametrize("n, dtype", [(33, "c128"), (36, "enc2")])
 def test_ghz_tile_closed_form(J, n, dtype):
     # the paper's benchmark circuit at its largest one-GPU sizes: exact in
