@@ -13,6 +13,7 @@ import sys
 import numpy as np
 import pytest
 
+from _closed_forms import diag_closed_form
 from _parity import assert_c128, assert_c64, rel_l2
 from oracle import decomposition as odec
 from oracle import statevector as sv
@@ -103,32 +104,6 @@ def test_qasm_qft_of_basis_state(J, n, x, mode):
 
 
 # ---- Eq. (3) at the 48-qubit grid's own shape, cut and m = 10 -----------------------------
-def diag_closed_form(gates, n, zs):
-    """<z|C|0> for a Haar layer followed by diagonal gates only (T, S, CZ):
-    prod_q U_q[z_q, 0] times the phases of the diagonal gates at z."""
-    z = np.asarray(zs, dtype=np.uint64)
-    bits = ((z[:, None] >> np.arange(n, dtype=np.uint64)[None, :]) & np.uint64(1)).astype(np.int64)
-    haar = gates[gates["op"] == W.OP_U]
-    assert np.array_equal(haar["q0"], np.arange(n))
-    u = haar["u"].reshape(n, 2, 2, 2)
-    u = u[..., 0] + 1j * u[..., 1]
-    amp = np.prod(u[np.arange(n)[None, :], bits, 0], axis=1)
-    rest = gates[len(haar):]
-    assert not np.any(rest["op"] == W.OP_U)
-    eighths = np.zeros(len(z), dtype=np.int64)  # phase in units of pi/4
-    for rec in rest:
-        op, a, b = int(rec["op"]), int(rec["q0"]), int(rec["q1"])
-        if op == W.OP_T:
-            eighths += bits[:, a]
-        elif op == W.OP_S:
-            eighths += 2 * bits[:, a]
-        elif op == W.OP_CZ:
-            eighths += 4 * bits[:, a] * bits[:, b]
-        else:
-            raise AssertionError(f"unexpected op {op}")
-    return amp * np.exp(0.25j * np.pi * (eighths % 8))
-
-
 def test_grid48_m10_closed_form_all_sum_paths(J):
     # 1024 branch pairs of 24-qubit halves; 2^16 + 4 coefficients, so the sum
     # from global memory runs in chunks.  group 16: 32 leaves, summed from

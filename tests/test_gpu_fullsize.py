@@ -168,7 +168,10 @@ def test_brick28_precision_forms(J, dtype, mode, mma):
         got = s.amplitudes(z)
         nrm = s.norm()
     err = rel_l2(got, want)
-    print(f"brick28 {dtype} {mode} {mma}: passes={o.passes} relL2={err:.3e} norm-1={nrm - 1:.3e}")
+    mx = float(np.abs(got - want).max() / np.abs(want).max())
+    fid = abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real)
+    print(f"brick28 {dtype} {mode} {mma}: passes={o.passes} relL2={err:.3e} "
+          f"max/max={mx:.3e} 1-fidelity(sampled)={1 - fid:.3e} norm-1={nrm - 1:.3e}")
     if dtype == "enc2":
         assert err <= enc2_bound(o.passes)
     elif mma == "bf16":

@@ -77,3 +77,31 @@ def test_grid42_cut():
     circ, side = W.grid_circuit(7, 6, 12, seed=7, max_cross=12)
     assert np.array_equal(np.bincount(side), [21, 21])
     assert len(dec.crossing_gates(circ, side)) == 12
+
+
+def test_grid_diag_closed_form_is_the_oracle_state():
+    # the closed form the 48-qubit decomposition test relies on, pinned on a
+    # 3x4 grid against the oracle's full state vector and its Eq. (3) sum
+    from _closed_forms import diag_closed_form
+    from oracle import decomposition as odec
+    from oracle import statevector as sv
+    circ, side = W.grid_diag_circuit(3, 4, 6, seed=9, max_cross=4)
+    n = 12
+    assert len(odec.crossing_gates(circ, side)) == 4
+    full = sv.run_circuit(n, circ)
+    z = np.arange(1 << n, dtype=np.uint64)
+    assert np.max(np.abs(diag_closed_form(circ, n, z) - full)) < 1e-14
+    zs = [0, 5, 777, (1 << n) - 1]
+    ob = odec.branch_amplitudes(n, circ, side, zs)
+    assert np.max(np.abs(ob - full[zs])) < 1e-14
+
+
+def test_grid_diag_circuit_shape():
+    # the 48-qubit grid's cut: the same crossing rule as grid_circuit
+    circ, side = W.grid_diag_circuit()
+    from oracle import decomposition as odec
+    assert len(odec.crossing_gates(circ, side)) == 10
+    assert np.sum(circ["op"] == W.OP_U) == 48
+    assert set(np.unique(circ["op"])) == {W.OP_U, W.OP_T, W.OP_S, W.OP_CZ}
+    full_cz = W.grid_circuit(6, 8, 8, seed=5, max_cross=10)[0]
+    assert np.array_equal(circ[circ["op"] == W.OP_CZ][["q0", "q1"]], full_cz[full_cz["op"] == W.OP_CZ][["q0", "q1"]])
