@@ -205,25 +205,7 @@ def main():
     log(f"workload: n={n}, {len(gates)} gates, {z.size} bitstrings, mode={args.mode}")
 
     st = juqcs.State(n, "c128", device=dev, stream=stream)
-    tune = None
-    run_mode = args.mode
-    if args.mode == "tile":
-        if args.autotune:
-            t0 = time.perf_counter()
-            tune = st.autotune(gates)
-            tune["wall_s"] = time.perf_counter() - t0
-            tune["source"] = "timed trials in this run"
-            if args.tune_out:
-                juqcs.juqcs_tune_save(args.tune_out)
-        elif os.path.exists(TUNING_RECORD):
-            # the record written by an earlier --autotune 1 run on MI355X
-            juqcs.juqcs_tune_load(TUNING_RECORD)
-            tune = st.tuned(gates)
-            if tune is not None:
-                tune["source"] = os.path.relpath(TUNING_RECORD, ROOT)
-        if tune is not None:
-            run_mode = "auto"
-        log(f"autotune: {tune}")
+    tune, run_mode = tuned_mode(args, juqcs, st, gates)
 
     def step(mode, profile):
         st.init(0)
@@ -428,6 +410,31 @@ def tree_roofline(bst, ms):
                     "bytes_per_step": bst["pass_bytes"],
                     "note": "24-qubit part states (128 MiB) are cache-resident: effective"},
             "note": "over the whole step"}
+
+
+def tuned_mode(args, juqcs, st, gates):
+    """Planner options for the tile mode: the stored tuning record's entry
+    for this circuit (written by an earlier --autotune 1 run on MI355X), or
+    fresh timed trials with --autotune 1 (saved with --tune-out, together
+    with the record's other entries).  Returns (entry or None, run mode)."""
+    if args.mode != "tile":
+        return None, args.mode
+    if os.path.exists(TUNING_RECORD):
+        juqcs.juqcs_tune_load(TUNING_RECORD)
+    if args.autotune:
+        os.environ["JUQCS_TUNE_VERBOSE"] = "1"    # one stderr line per timed trial
+        t0 = time.perf_counter()
+        tune = st.autotune(gates)
+        tune["wall_s"] = time.perf_counter() - t0
+        tune["source"] = "timed trials in this run"
+        if args.tune_out:
+            juqcs.juqcs_tune_save(args.tune_out)
+    else:
+        tune = st.tuned(gates)
+        if tune is not None:
+            tune["source"] = os.path.relpath(TUNING_RECORD, ROOT)
+    log(f"autotune: {tune}")
+    return tune, ("auto" if tune is not None else "tile")
 
 
 def _timed(fn, steps, warmup, stream):
@@ -686,12 +693,17 @@ def other_workload(args, juqcs, W, dev, stream):
         circ = W.layered_brick(n, 16, seed=3)
         st = juqcs.State(n, dtype, device=dev, stream=stream)
         info = {}
+        explicit = args.tile_bits or args.low_bits or args.tile_fuse or args.pass_gates or args.relabel
+        tune, run_mode = (None, "tile") if explicit else tuned_mode(args, juqcs, st, circ)
 
         def run():
             st.init(0)
-            o = st.run(circ, mode="tile", profile=True, fuse_k=args.tile_fuse,
-                       tile_bits=args.tile_bits, low_bits=args.low_bits,
-                       pass_gates=args.pass_gates, relabel=args.relabel)
+            if run_mode == "auto":
+                o = st.run(circ, mode="auto", profile=True)
+            else:
+                o = st.run(circ, mode="tile", profile=True, fuse_k=args.tile_fuse,
+                           tile_bits=args.tile_bits, low_bits=args.low_bits,
+                           pass_gates=args.pass_gates, relabel=args.relabel)
             info["o"] = (o.passes, o.kernel_ms, o.bytes, o.flops)
 
         ms = _timed(run, args.steps, args.warmup, stream)
@@ -714,7 +726,7 @@ def other_workload(args, juqcs, W, dev, stream):
             "dtype": "f32" if dtype == "c64" else "enc2",
             "config": {"workload": f"{args.workload}: n={n} {dtype}, 16 brick layers ({len(circ)} gates, "
                                    "seed 3), tile passes", "n": n, "passes_per_step": passes,
-                       "relabel": args.relabel},
+                       "relabel": args.relabel, "autotune": tune},
             # passes absorb far more gates than one HBM pass pays for: bound
             # by on-chip arithmetic (FP32 matrix cores for the 8x8 ops, VALU
             # for the rest and for the two-byte codec)
@@ -722,7 +734,9 @@ def other_workload(args, juqcs, W, dev, stream):
                          "unit": "TFLOP/s", "frac": tf / FP32_MFMA_PEAK_TFLOPS,
                          "frac_of_fp32_valu": tf / FP64_VECTOR_PEAK_TFLOPS,
                          "flops_per_launch": fl / passes, "avg_launch_ms": kms / passes,
-                         "kernel": "k_tile_fixed<float,13,1024>" if dtype == "c64" else "k_tile_enc2_fixed<13>",
+                         "kernel": (("k_tile_fixed<float,12,512>" if tune and tune["tile_bits"] == 12
+                                     else "k_tile_fixed<float,13,1024>") if dtype == "c64"
+                                    else "k_tile_enc2_fixed<13>"),
                          "hbm": {"achieved_GBps": achieved, "peak_GBps": HBM_PEAK_GBPS,
                                  "frac": achieved / HBM_PEAK_GBPS, "bytes_per_launch": kb / passes}},
             "amp_updates_per_s": len(circ) * float(1 << n) / (ms / 1e3),

@@ -244,7 +244,8 @@ typedef struct {
  * the circuit's structure key (n, amplitude type, ENC2 block bits, every
  * gate's op and qubits; matrices and angles do not enter), where
  * juqcs_run_circuit with mode JUQCS_PLAN_AUTO finds them.  Synchronises.
- * Errors: as for juqcs_run_circuit. */
+ * With the environment variable JUQCS_TUNE_VERBOSE=1 every timed run is
+ * reported on stderr.  Errors: as for juqcs_run_circuit. */
 juqcs_status juqcs_autotune(juqcs_state* st, const juqcs_gate* gates, size_t count,
                             juqcs_tune_result* out);
 

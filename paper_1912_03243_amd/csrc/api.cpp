@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -259,7 +260,12 @@ double tile_plan_ms(const TilePlan& p, juqcs_dtype dt, int n) {
 juqcs_status tile_gates(juqcs_state* st, const std::vector<Gate>& gates, int L, int b,
                         int64_t* passes, int kin = 0, int pass_gates = -1, int relabel = -1) {
   const int maxb = tile_max_bits(st->dt);
-  if (b <= 0 || L <= 0) default_tile_bits(st->dt, st->B, &L, &b);
+  {  // each of the two defaults on its own
+    int dL = 0, db = 0;
+    default_tile_bits(st->dt, st->B, &dL, &db);
+    if (b <= 0) b = db;
+    if (L <= 0) L = std::min(dL, b);
+  }
   if (b > maxb) return fail(JUQCS_ERR_ARG, "tile_bits above the LDS limit");
   if (L > b) return fail(JUQCS_ERR_ARG, "low_bits > tile_bits");
   if (b - L > kMaxGather) return fail(JUQCS_ERR_ARG, "too many gathered tile bits");
@@ -744,6 +750,8 @@ juqcs_status juqcs_autotune(juqcs_state* st, const juqcs_gate* gates, size_t cou
   if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   juqcs_status err = JUQCS_OK;
   int trials = 0;
+  const char* verbose = std::getenv("JUQCS_TUNE_VERBOSE");
+  const bool say = verbose && verbose[0] == '1';
   // one timed run from |0...0>; infinite if the options are rejected
   auto time_run = [&](juqcs_plan_opts o) {
     o.profile = 0;
@@ -756,6 +764,10 @@ juqcs_status juqcs_autotune(juqcs_state* st, const juqcs_gate* gates, size_t cou
     float ms = 0.0f;
     if (rc != JUQCS_OK || hipEventElapsedTime(&ms, a, b) != hipSuccess) return 1e300;
     ++trials;
+    if (say)
+      std::fprintf(stderr, "juqcs_autotune: mode %d fuse_k %d tile_bits %d low_bits %d pass_gates %d "
+                   "relabel %d: %.3f ms\n", o.mode, o.fuse_k, o.tile_bits, o.low_bits, o.pass_gates,
+                   o.relabel, ms);
     return (double)ms;
   };
   // the better of two runs (the first run of a kernel also pays for loading it)
