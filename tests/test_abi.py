@@ -201,3 +201,21 @@ def test_tuning_table_round_trip(J, tmp_path):
     with pytest.raises(J.JuqcsError):
         J.juqcs_tune_load(str(tmp_path / "missing.json"))
     J.juqcs_tune_clear()
+
+
+def test_noalloc_rejects_beyond_the_scratch_before_any_device_call(J):
+    # two 24-qubit halves: one part state alone is 128 MiB, beyond the static
+    # 32 MiB scratch; the pointers are never used
+    import numpy as np
+    from paper_1912_03243_amd import workloads as W
+    lib = J._lib
+    circ, side = W.grid_circuit(6, 8, 2, 5, max_cross=2)
+    rc = lib.juqcs_branch_amplitudes_noalloc(48, circ.ctypes.data, circ.size,
+                                             side.ctypes.data_as(ct.POINTER(ct.c_uint8)), 256, 1, 4, 0,
+                                             256, None)
+    assert rc == J.ERR_SIZE
+    assert "scratch" in J.juqcs_last_error()
+    # no bitstrings: nothing to do
+    assert lib.juqcs_branch_amplitudes_noalloc(48, circ.ctypes.data, circ.size,
+                                               side.ctypes.data_as(ct.POINTER(ct.c_uint8)), 256, 1, 0, 0,
+                                               256, None) == J.OK
