@@ -163,6 +163,9 @@ def main():
                          "without it the stored tuning record is used); batch4096: timed-trial "
                          "in-pass fusion width, compared with the cost model")
     ap.add_argument("--tune-out", default=None, help="brick30 --autotune 1: save the tuning table here")
+    ap.add_argument("--secondary", type=int, default=1,
+                    help="brick30: also run the other configurations once (configs 3-5 and the "
+                         "paper's Sec. 3/4 circuits) and attach their lines under \"configs\"")
     ap.add_argument("--tile-fuse", type=int, default=0, help="in-pass fusion width (0 = default)")
     ap.add_argument("--tile-bits", type=int, default=0, help="tile bits (0 = default)")
     ap.add_argument("--low-bits", type=int, default=0, help="contiguous low tile bits (0 = default)")
@@ -358,10 +361,52 @@ def main():
             log(f"{mode}: {el * 1e3:.1f} ms for one step, {o.passes} passes")
 
     st.close()
+    del st
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if args.secondary:
+        result["configs"] = secondary_configs(args, juqcs, W, dev, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_budget)
     print(json.dumps(result), flush=True)
+
+
+# The other configurations, each run once after the headline (steps, warmup):
+# the 128 GiB complex64 and two-byte states, the 4096-circuit batch (with the
+# batch autotuner, the cost model timed beside it), the 48-qubit grid
+# decomposition, and the paper's Sec. 3 and Sec. 4 GHZ circuits.
+SECONDARY = (("large34", 2, 1), ("large36", 1, 0), ("batch4096", 2, 1), ("grid48", 2, 1),
+             ("ghz128", 2, 1), ("ghz33", 2, 1))
+SECONDARY_KEYS = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "roofline", "check",
+                  "amp_updates_per_s", "ms_per_gate", "coefficients_per_s", "cost_model_ms_per_step",
+                  "expectations_ms", "tile", "plain", "branch_stats")
+
+
+def secondary_configs(args, juqcs, W, dev, stream):
+    import argparse as _ap
+    import torch
+    out = {}
+    for name, steps, warmup in SECONDARY:
+        a = _ap.Namespace(**vars(args))
+        a.workload, a.steps, a.warmup = name, steps, warmup
+        a.autotune = 1 if name == "batch4096" else 0
+        a.tile_fuse = a.tile_bits = a.low_bits = a.pass_gates = a.relabel = 0
+        t0 = time.perf_counter()
+        try:
+            res = other_workload(a, juqcs, W, dev, stream, emit=False)
+            line = {k: res[k] for k in SECONDARY_KEYS if k in res}
+            line["workload"] = res["config"]["workload"]
+            for k in ("passes_per_step", "autotune", "fusion_width_counts", "circuits", "gates", "n"):
+                if k in res["config"]:
+                    line[k] = res["config"][k]
+        except Exception as e:  # a failed configuration is reported, the headline still stands
+            line = {"error": f"{type(e).__name__}: {e}"}
+        line["wall_s"] = time.perf_counter() - t0
+        out[name] = line
+        log(f"{name}: {line.get('ms_per_step', line.get('error'))}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
 
 
 def sample_errors(got, want):
@@ -451,7 +496,7 @@ def _timed(fn, steps, warmup, stream):
     return a.elapsed_time(b) / steps
 
 
-def other_workload(args, juqcs, W, dev, stream):
+def other_workload(args, juqcs, W, dev, stream, emit=True):
     """Secondary configurations (not the headline line): many small circuits
     in one graph launch, the entangling-gate decomposition, and the
     largest single states in complex64 and two-byte form."""
@@ -743,7 +788,9 @@ def other_workload(args, juqcs, W, dev, stream):
             "check": check,
         })
         st.close()
-    print(json.dumps(res), flush=True)
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 if __name__ == "__main__":
