@@ -661,6 +661,8 @@ class Batch:
         n = int(self.n[i])
         count = len(self.n)
         m = 1 << n
+        if count * m > (1 << 28):
+            raise ValueError("state_vector reads every circuit's m indices: use amplitudes() on large batches")
         idx = torch.zeros((count, m), dtype=torch.int64, device=self.device)
         idx[i] = torch.arange(m, dtype=torch.int64, device=self.device)
         out = torch.empty(2 * count * m, dtype=torch.float64, device=self.device)
