@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--secondary", type=int, default=1,
                     help="brick30: also run the other configurations once (configs 3-5 and the "
                          "paper's Sec. 3/4 circuits) and attach their lines under \"configs\"")
+    ap.add_argument("--block-bits", type=int, default=0,
+                    help="large36, ghz36: two-byte block bits B (0 = the library default, 8)")
     ap.add_argument("--tile-fuse", type=int, default=0, help="in-pass fusion width (0 = default)")
     ap.add_argument("--tile-bits", type=int, default=0, help="tile bits (0 = default)")
     ap.add_argument("--low-bits", type=int, default=0, help="contiguous low tile bits (0 = default)")
@@ -696,7 +698,8 @@ def other_workload(args, juqcs, W, dev, stream, emit=True):
         # reports the elapsed time per gate
         n, dtype = (33, "c128") if args.workload == "ghz33" else (36, "enc2")
         circ = W.ghz(n)
-        st = juqcs.State(n, dtype, device=dev, stream=stream)
+        st = juqcs.State(n, dtype, device=dev, stream=stream,
+                         block_bits=args.block_bits if dtype == "enc2" else 0)
         q = {}
         modes = {}
         for mode in ("tile", "plain"):
@@ -736,7 +739,8 @@ def other_workload(args, juqcs, W, dev, stream, emit=True):
     else:
         n, dtype = (34, "c64") if args.workload == "large34" else (36, "enc2")
         circ = W.layered_brick(n, 16, seed=3)
-        st = juqcs.State(n, dtype, device=dev, stream=stream)
+        st = juqcs.State(n, dtype, device=dev, stream=stream,
+                         block_bits=args.block_bits if dtype == "enc2" else 0)
         info = {}
         explicit = args.tile_bits or args.low_bits or args.tile_fuse or args.pass_gates or args.relabel
         tune, run_mode = (None, "tile") if explicit else tuned_mode(args, juqcs, st, circ)

@@ -219,3 +219,13 @@ def test_noalloc_rejects_beyond_the_scratch_before_any_device_call(J):
     assert lib.juqcs_branch_amplitudes_noalloc(48, circ.ctypes.data, circ.size,
                                                side.ctypes.data_as(ct.POINTER(ct.c_uint8)), 256, 1, 0, 0,
                                                256, None) == J.OK
+
+
+def test_library_sources_never_allocate_device_memory():
+    # every device buffer is the caller's: no allocation or release calls in
+    # the library's sources (host vectors and the static scratch array aside)
+    import glob
+    calls = re.compile(r"\bhip(Malloc|MallocAsync|MallocManaged|ExtMallocWithFlags|Free|FreeAsync|HostMalloc)\s*\(")
+    for path in glob.glob(os.path.join(ROOT, "paper_1912_03243_amd", "csrc", "*")):
+        text = open(path).read()
+        assert not calls.search(text), f"{os.path.basename(path)} allocates device memory"
