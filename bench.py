@@ -238,16 +238,20 @@ def main():
     start.record(stream)
     t0 = time.perf_counter()
     mma_flops = 0.0
+    marks = []
     for i in range(args.steps):
         o, nrm = step(run_mode, True)
         kernel_ms += o.kernel_ms
         kbytes += o.bytes
         passes += o.passes
         mma_flops += o.mma_flops
+        marks.append(torch.cuda.Event(enable_timing=True))
+        marks[-1].record(stream)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop) / args.steps
+    per_step = [start.elapsed_time(marks[0])] + [marks[i - 1].elapsed_time(marks[i]) for i in range(1, len(marks))]
     log(f"timed {args.steps} steps: {ms:.2f} ms/step (host wall {1e3 * wall / args.steps:.2f})")
 
     amps = outd.cpu().numpy()
@@ -303,6 +307,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": float(np.median(per_step)),
+        "ms_per_step_min": float(np.min(per_step)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

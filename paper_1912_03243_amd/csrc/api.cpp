@@ -755,6 +755,7 @@ juqcs_status juqcs_autotune(juqcs_state* st, const juqcs_gate* gates, size_t cou
   // one timed run from |0...0>; infinite if the options are rejected
   auto time_run = [&](juqcs_plan_opts o) {
     o.profile = 0;
+    if (err != JUQCS_OK) return 1e300;  // no more device work after a device error
     if (juqcs_state_init(st, 0) != JUQCS_OK) return 1e300;
     if (hipEventRecord(a, st->stream) != hipSuccess) return 1e300;
     const juqcs_status rc = juqcs_run_circuit(st, gates, count, &o);
