@@ -149,7 +149,7 @@ def main():
                     help="run only the reference copy kernel (counter calibration)")
     ap.add_argument("--workload", default="brick30",
                     choices=["brick30", "batch4096", "grid48", "grid42", "ghz128", "large34", "large36",
-                             "ghz33", "ghz36"],
+                             "ghz33", "ghz36", "targets"],
                     help="brick30 is the headline configuration; the others are the batched, "
                          "decomposition and large-state configurations")
     ap.add_argument("--count", type=int, default=4096, help="batch4096: number of circuits")
@@ -697,6 +697,33 @@ def other_workload(args, juqcs, W, dev, stream, emit=True):
             "branch_stats": bst,
             "check": {"amp_all_zero": float(a[0].real), "amp_all_one": float(a[1].real),
                       "nonzero_random": int(np.count_nonzero(a[2:]))},
+        })
+    elif args.workload == "targets":
+        # one per-gate pass per target bit: a dense 2x2 on every bit below the
+        # run width and a few above it, c128 at n = 30 and c64 at n = 31 (16
+        # GiB each); achieved GB/s = 2 x state bytes / pass time (HIP events)
+        u = np.array([[0.6, 0.8j], [0.8j, 0.6]])
+        lines = {}
+        for dtype, n in (("c128", 30), ("c64", 31)):
+            st = juqcs.State(n, dtype, device=dev, stream=stream)
+            st.init(0)
+            full = 2.0 * (16 if dtype == "c128" else 8) * (1 << n)
+            nb = st.amps.numel()
+            stream_ms = _timed(lambda: juqcs.juqcs_copy(st.amps, st.amps, nb), max(args.steps, 4), 1, stream)
+            per = {"stream": {"ms": stream_ms, "GBps": full / stream_ms / 1e6}}
+            for t in list(range(9)) + [n // 2, n - 1]:
+                ms = _timed(lambda: st.apply_1q(t, u), max(args.steps, 4), 1, stream)
+                per[str(t)] = {"ms": ms, "GBps": full / ms / 1e6, "frac_of_stream": stream_ms / ms}
+            lines[f"{dtype} n={n}"] = per
+            st.close()
+            del st
+            torch.cuda.empty_cache()
+        worst = min(v["GBps"] for per in lines.values() for k, v in per.items() if k != "stream")
+        res.update({
+            "value": worst, "unit": "GB/s (slowest target bit)", "ms_per_step": None, "dtype": "f64/f32",
+            "config": {"workload": "targets: one dense 2x2 per-gate pass per target bit (0..8, n/2, n-1), "
+                                   "c128 n=30 and c64 n=31"},
+            "targets": lines,
         })
     elif args.workload in ("ghz33", "ghz36"):
         # the paper's benchmark circuit (Section 3): H on qubit 0, CNOT(i, i+1)
