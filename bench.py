@@ -210,7 +210,8 @@ def main():
     log(f"workload: n={n}, {len(gates)} gates, {z.size} bitstrings, mode={args.mode}")
 
     st = juqcs.State(n, "c128", device=dev, stream=stream)
-    tune, run_mode = tuned_mode(args, juqcs, st, gates)
+    explicit = args.tile_bits or args.low_bits or args.tile_fuse or args.pass_gates or args.relabel
+    tune, run_mode = (None, args.mode) if explicit else tuned_mode(args, juqcs, st, gates)
 
     def step(mode, profile):
         st.init(0)
