@@ -804,6 +804,17 @@ def other_workload(args, juqcs, W, dev, stream, emit=True):
             check.update(sample_errors(got, want))
         except OSError as e:
             log(f"no stored oracle amplitudes: {e}")
+        # norm drift after each layer (outside the timed steps): the circuit
+        # again, one layer per run, the FP64 norm read after each
+        bounds = [0]
+        for layer in range(16):
+            bounds.append(bounds[-1] + n + len(range(layer % 2, n - 1, 2)))
+        st.init(0)
+        drift = []
+        for layer in range(16):
+            st.run(circ[bounds[layer]:bounds[layer + 1]], mode="tile")
+            drift.append(st.norm() - 1.0)
+        check["norm_drift_per_layer"] = drift
         res.update({
             "value": len(circ) / (ms / 1e3), "ms_per_step": ms,
             "dtype": "f32" if dtype == "c64" else "enc2",
