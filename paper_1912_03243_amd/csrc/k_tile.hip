@@ -314,10 +314,26 @@ __device__ inline void store_enc2_t(const cplx<float>* sh, uint32_t* bmax, int t
                                     int8_t* codes, float* scales, const int* swp, int nswap,
                                     const int* lsj) {
   const int ngroups = tile_amps >> 3;
+  // Consecutive lanes hold consecutive groups of 8 amplitudes: when whole
+  // waves take part, the lanes of a block reduce its maximum by shuffles
+  // first, and one lane per block and wave does the LDS atomic (instead of
+  // every lane hitting the block's one address).
+  const int G = 1 << (B - 3);                    // groups per block
+  const int span = G < 64 ? G : 64;              // lanes that reduce together
+  const bool whole = (ngroups & 63) == 0;        // every wave fully active
   for (int gq = threadIdx.x; gq < ngroups; gq += NT) {
     const int e = gq << 3;
     const int ls = SW ? lds<float>(swap_staged(e, swp, nswap)) : 0;
-    atomicMax(&bmax[e >> B], __float_as_uint(max8<SW>(sh, e, ls, lsj)));
+    uint32_t mx = __float_as_uint(max8<SW>(sh, e, ls, lsj));
+    if (whole) {
+      for (int d = 1; d < span; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)mx, d, 64);
+        mx = o > mx ? o : mx;
+      }
+      if ((threadIdx.x & (span - 1)) == 0) atomicMax(&bmax[e >> B], mx);
+    } else {
+      atomicMax(&bmax[e >> B], mx);
+    }
   }
   __syncthreads();
   for (int gq = threadIdx.x; gq < ngroups; gq += NT) {
