@@ -229,3 +229,18 @@ def test_library_sources_never_allocate_device_memory():
     for path in glob.glob(os.path.join(ROOT, "paper_1912_03243_amd", "csrc", "*")):
         text = open(path).read()
         assert not calls.search(text), f"{os.path.basename(path)} allocates device memory"
+
+
+def test_committed_tuning_record_loads(J):
+    # the record bench.py reads: every entry well formed, choices that the
+    # planner accepts (a tile or fused mode), times not worse than defaults
+    import json
+    path = os.path.join(ROOT, "paper_1912_03243_amd", "tuning_mi355x.json")
+    rec = json.load(open(path))
+    assert rec["juqcs_tune"] == 1 and rec["entries"]
+    for e in rec["entries"]:
+        assert e["mode"] in (J.PLAN_PLAIN, J.PLAN_TILE, J.PLAN_FUSED)
+        assert e["ms"] <= e["default_ms"] and e["trials"] > 0
+    J.juqcs_tune_clear()
+    J.juqcs_tune_load(path)
+    J.juqcs_tune_clear()

@@ -202,3 +202,24 @@ def test_largest_states(J, name, dtype):
         assert err <= enc2_bound(o.passes)
     else:
         assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n, dtype, layers, tol", [(30, "c128", 20, 1e-12), (34, "c64", 8, 2e-5)])
+def test_inverse_round_trip_at_full_size(J, n, dtype, layers, tol):
+    # the brick circuit followed by its inverse (reversed, each gate's
+    # adjoint) is the identity: |0...0> comes back, whatever planner runs it
+    circ = W.layered_brick(n, layers, seed=2)
+    inv = W.inverse_circuit_records(circ)
+    announce("round trip", n, dtype)
+    with J.State(n, dtype) as s:
+        s.init(0)
+        s.run(circ, mode="tile")
+        s.run(inv, mode="tile")
+        a = s.amplitudes([0, 1, 1 << (n - 1), 123456789])
+        nrm = s.norm()
+    import torch
+    del s
+    torch.cuda.empty_cache()
+    print(f"round trip n={n} {dtype}: |a0 - 1| = {abs(a[0] - 1):.3e}, others {np.abs(a[1:]).max():.3e}")
+    assert abs(a[0] - 1.0) < tol and np.abs(a[1:]).max() < tol
+    assert abs(nrm - 1.0) < tol
