@@ -736,14 +736,17 @@ def other_workload(args, juqcs, W, dev, stream, emit=True):
                          block_bits=args.block_bits if dtype == "enc2" else 0)
         q = {}
         modes = {}
+        tune, tile_mode = tuned_mode(args, juqcs, st, circ)
         for mode in ("tile", "plain"):
-            def run(mode=mode):
+            run_as = tile_mode if mode == "tile" else mode
+
+            def run(run_as=run_as):
                 st.init(0)
-                st.run(circ, mode=mode)
+                st.run(circ, mode=run_as)
             steps = args.steps if mode == "tile" else 1
             ms = _timed(run, steps, args.warmup if mode == "tile" else 0, stream)
             st.init(0)
-            o = st.run(circ, mode=mode, profile=True)
+            o = st.run(circ, mode=run_as, profile=True)
             modes[mode] = {"ms_per_circuit": ms, "ms_per_gate": ms / len(circ), "passes": o.passes,
                            "avg_pass_ms": o.kernel_ms / max(o.passes, 1),
                            "achieved_GBps": o.bytes / (o.kernel_ms / 1e3) / 1e9}
@@ -760,7 +763,8 @@ def other_workload(args, juqcs, W, dev, stream, emit=True):
             "ms_per_step": t["ms_per_circuit"] + ms_q, "dtype": "f64" if dtype == "c128" else "enc2",
             "config": {"workload": f"{args.workload}: n={n} {dtype} GHZ circuit (H(0) + {n - 1} "
                                    "CNOT(i,i+1)) + expectation values of all qubits; init, gates "
-                                   "and expectations per step", "n": n, "gates": len(circ)},
+                                   "and expectations per step", "n": n, "gates": len(circ),
+                       "autotune": tune},
             "tile": t, "plain": modes["plain"],
             "expectations_ms": ms_q,
             "amp_updates_per_s": len(circ) * float(1 << n) / (t["ms_per_circuit"] / 1e3),
