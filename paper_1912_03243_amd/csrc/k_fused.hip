@@ -91,7 +91,12 @@ __global__ __launch_bounds__(kThreads) void k_fused(
   using T = typename PrecTraits<P>::T;
   constexpr int R0 = 2 * KD;
   constexpr int R = R0 < 16 ? 16 : R0;
-  constexpr bool kALds = (R * R * sizeof(T)) <= 64 * 1024;
+  // FP64 / FP32 blocks of up to 4 qubits keep their matrix operands in
+  // registers (R/16 x R/4 values per lane): no LDS copy of the matrix, so
+  // more workgroups fit a CU
+  constexpr bool kAReg = (P == P_F64 || P == P_F32) && R <= 32;
+  constexpr int NAR = kAReg ? (R / 16) * (R / 4) : 1;
+  constexpr bool kALds = !kAReg && (R * R * sizeof(T)) <= 64 * 1024;
   constexpr int E = KD * kCols;                           // panel elements (at most)
   constexpr int PER = (E + kThreads - 1) / kThreads;      // panel amplitudes per thread
   // register prefetch only where it fits beside the accumulators
@@ -144,6 +149,13 @@ __global__ __launch_bounds__(kThreads) void k_fused(
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, lhi = lane >> 4;
+  T areg[NAR];
+  if constexpr (kAReg) {
+#pragma unroll
+    for (int t = 0; t < R / 16; ++t)
+#pragma unroll
+      for (int kq = 0; kq < R / 4; ++kq) areg[t * (R / 4) + kq] = At[(4 * kq + lhi) * R + t * 16 + l16];
+  }
 
   auto panel_base = [&](uint64_t pi) {
     uint64_t base = pi << S;
@@ -190,11 +202,12 @@ __global__ __launch_bounds__(kThreads) void k_fused(
       v4d acc[R / 16];
 #pragma unroll
       for (int t = 0; t < R / 16; ++t) acc[t] = v4d{0, 0, 0, 0};
+#pragma unroll
       for (int kk = 0; kk < R; kk += 4) {
         const double bv = sB[(kk + lhi) * kLdw + cw + l16];
 #pragma unroll
         for (int t = 0; t < R / 16; ++t) {
-          const double av = A[(kk + lhi) * R + t * 16 + l16];
+          const double av = kAReg ? areg[t * (R / 4) + kk / 4] : A[(kk + lhi) * R + t * 16 + l16];
           acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
         }
       }
@@ -207,11 +220,12 @@ __global__ __launch_bounds__(kThreads) void k_fused(
       v4f acc[R / 16];
 #pragma unroll
       for (int t = 0; t < R / 16; ++t) acc[t] = v4f{0, 0, 0, 0};
+#pragma unroll
       for (int kk = 0; kk < R; kk += 4) {
         const float bv = sB[(kk + lhi) * kLdw + cw + l16];
 #pragma unroll
         for (int t = 0; t < R / 16; ++t) {
-          const float av = A[(kk + lhi) * R + t * 16 + l16];
+          const float av = kAReg ? areg[t * (R / 4) + kk / 4] : A[(kk + lhi) * R + t * 16 + l16];
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
         }
       }
