@@ -353,7 +353,7 @@ typedef struct juqcs_batch juqcs_batch; /* opaque */
  * state_offset[i] (each 8 * 2^n[i] bytes, 16-byte aligned, inside the buffer
  * and disjoint: JUQCS_ERR_SIZE / JUQCS_ERR_ARG otherwise, checked before any
  * device work); every circuit starts from |0...0>.  Each circuit is planned
- * on the host into on-chip tile passes (tiles of up to 2^13 amplitudes);
+ * on the host into on-chip tile passes (tiles of up to 2^12 amplitudes);
  * the fusion width inside a pass (1..4 qubits) is opts->fuse_k, or chosen
  * per circuit by a cost model when fuse_k is 0 (juqcs_batch_autotune
  * replaces it with timed trials).  No device memory is touched: bind a
